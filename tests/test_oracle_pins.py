@@ -1,0 +1,473 @@
+"""Pins for the FP64 oracle against what the paper and mathematics fix.
+
+None of these re-derive the oracle's own code: each checks a closed form, an
+invariant, a library routine or a brute-force evaluation written differently
+(citations are to the TC-GS paper, arXiv 2505.24796).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen
+
+LN255 = math.log(255.0)
+
+
+def one_tile_lists(n):
+    """Ranges/ids for a single 16x16 tile holding Gaussians 0..n-1 in order."""
+    return np.array([[0, n]], np.uint32), np.arange(n, dtype=np.uint32)
+
+
+def conic_of(cov):
+    a, b, c = cov
+    return np.linalg.inv(np.array([[a, b], [b, c]]))
+
+
+# ---------------------------------------------------------------- P1 -------
+def test_single_gaussian_closed_form(orc):
+    """Algorithm 1 with one Gaussian: C = c*alpha when alpha >= 1/255, with
+    alpha = min(0.99, o exp(-q/2)); T_final = 1 - alpha (Sec. 3.1, Alg. 1)."""
+    g = np.random.default_rng(7)
+    for trial in range(200):
+        o = g.uniform(0.004, 1.0)
+        L = np.array([[g.uniform(0.3, 4), 0], [g.normal(0, 1), g.uniform(0.3, 4)]])
+        Sinv = np.linalg.inv(L @ L.T)
+        S = np.array([Sinv[0, 0], Sinv[0, 1], Sinv[1, 1]])
+        mu = g.uniform(-4, 20, 2)
+        col = g.uniform(0, 1, 3)
+        ranges, ids = one_tile_lists(1)
+        out = orc.render(16, 16, ranges, ids, mu[None], S[None], [o], col[None])
+        for y in range(0, 16, 5):
+            for x in range(0, 16, 3):
+                d = mu - np.array([x, y], float)
+                q = d @ Sinv @ d
+                a = min(0.99, o * math.exp(-0.5 * q))
+                if a < 1 / 255:
+                    exp_c, exp_t = np.zeros(3), 1.0
+                else:
+                    exp_c, exp_t = col * a, 1 - a
+                np.testing.assert_allclose(out["rgb"][:, y, x], exp_c, rtol=0, atol=1e-14)
+                assert abs(out["T"][y, x] - exp_t) < 1e-14
+
+
+def test_isotropic_and_axis_aligned(orc):
+    """Special cases: isotropic q = |d|^2/s^2 and axis-aligned q = dx^2/a + dy^2/c."""
+    ranges, ids = one_tile_lists(1)
+    s2 = 9.0
+    out = orc.render(16, 16, ranges, ids, [[7.0, 9.0]], [[1 / s2, 0, 1 / s2]], [0.8], [[1, 1, 1]])
+    for (x, y) in [(7, 9), (0, 0), (15, 3)]:
+        q = ((x - 7) ** 2 + (y - 9) ** 2) / s2
+        a = 0.8 * math.exp(-q / 2)
+        a = a if a >= 1 / 255 else 0.0
+        assert abs(out["rgb"][0, y, x] - a) < 1e-15
+    out = orc.render(16, 16, ranges, ids, [[3.5, 12.25]], [[1 / 4.0, 0, 1 / 25.0]], [0.5], [[1, 0, 0]])
+    q = (10 - 3.5) ** 2 / 4 + (2 - 12.25) ** 2 / 25
+    a = 0.5 * math.exp(-q / 2)
+    assert abs(out["rgb"][0, 2, 10] - (a if a >= 1 / 255 else 0)) < 1e-15
+
+
+def test_clamp_and_cull_boundaries(orc):
+    """alpha is clamped at 0.99; alpha < 1/255 is culled (strict test)."""
+    ranges, ids = one_tile_lists(1)
+    out = orc.render(16, 16, ranges, ids, [[5.0, 5.0]], [[1.0, 0, 1.0]], [1.0], [[1, 1, 1]])
+    assert abs(out["T"][5, 5] - 0.01) < 1e-15 and abs(out["rgb"][0, 5, 5] - 0.99) < 1e-15
+    # opacity below 1/255 is culled everywhere
+    out = orc.render(16, 16, ranges, ids, [[5.0, 5.0]], [[1.0, 0, 1.0]], [1 / 256], [[1, 1, 1]])
+    assert np.all(out["T"] == 1.0) and np.all(out["rgb"] == 0.0)
+    assert np.all(out["f_cull"] == 1) and np.all(out["f_blend"] == 0)
+
+
+# ---------------------------------------------------------------- P2 -------
+def test_two_gaussians_order(orc):
+    """C = c1 a1 + c2 a2 (1 - a1); swapping depth order swaps the roles."""
+    mu = np.array([[6.0, 6.0], [9.0, 7.0]])
+    S = np.array([[0.2, 0.03, 0.1], [0.15, -0.02, 0.3]])
+    o = np.array([0.7, 0.6])
+    col = np.array([[1.0, 0.2, 0.1], [0.0, 0.5, 0.9]])
+    for order in ([0, 1], [1, 0]):
+        ranges = np.array([[0, 2]], np.uint32)
+        ids = np.array(order, np.uint32)
+        out = orc.render(16, 16, ranges, ids, mu, S, o, col)
+        x, y = 7, 6
+        al = []
+        for g in order:
+            d = mu[g] - [x, y]
+            M = np.array([[S[g, 0], S[g, 1]], [S[g, 1], S[g, 2]]])
+            al.append(min(0.99, o[g] * math.exp(-0.5 * d @ M @ d)))
+        exp_c = col[order[0]] * al[0] + col[order[1]] * al[1] * (1 - al[0])
+        np.testing.assert_allclose(out["rgb"][:, y, x], exp_c, atol=1e-14)
+        assert abs(out["T"][y, x] - (1 - al[0]) * (1 - al[1])) < 1e-14
+
+
+# ---------------------------------------------------------------- P3 -------
+def test_termination_closed_form(orc):
+    """Identical alpha = 0.8 fragments: T = 0.2^k; the sixth test gives
+    0.2^6 = 6.4e-5 < 1e-4, so five are composited and the sixth stops
+    the pixel without being composited (Alg. 1)."""
+    n = 10
+    ranges, ids = one_tile_lists(n)
+    mu = np.tile([[4.0, 4.0]], (n, 1))
+    S = np.tile([[1e-9, 0, 1e-9]], (n, 1))
+    o = np.full(n, 0.8)
+    col = np.tile([[1.0, 0.5, 0.25]], (n, 1))
+    out = orc.render(16, 16, ranges, ids, mu, S, o, col)
+    a = 0.8 * math.exp(-0.5 * 1e-9 * 0)  # centre pixel q = 0
+    expC = sum(a * (1 - a) ** k for k in range(5))
+    assert abs(out["rgb"][0, 4, 4] - expC) < 1e-12
+    assert out["n_contrib"][4, 4] == 5 and out["term"][4, 4] == 1
+    assert out["n_proc"][4, 4] == 6 and out["f_blend"][4, 4] == 5
+
+
+def test_invariants_random_scene(orc):
+    """With every colour 1, C = sum_i alpha_i T_i and C + T_final = 1 by the
+    telescoping of T <- T - alpha T; T_final >= 1e-4; C <= max colour."""
+    sc = scenegen.scene_2d(1500, 96, 80, seed=11, o_min=0.5)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, 96, 80)
+    ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, 96, 80)
+    ones = np.ones((sc.P, 3))
+    out = orc.render(96, 80, ranges, ids, sc.means2d, pre["conics"], sc.opacities, ones)
+    np.testing.assert_allclose(out["rgb"][0] + out["T"], 1.0, atol=1e-12)
+    assert out["T"].min() >= 1e-4
+    assert (out["term"] == 1).any()  # the scene is dense enough to terminate somewhere
+    out2 = orc.render(96, 80, ranges, ids, sc.means2d, pre["conics"], sc.opacities, sc.rgb)
+    assert out2["rgb"].max() <= sc.rgb.max() + 1e-12 and out2["rgb"].min() >= 0
+    # fragment accounting: processed = blended + culled + terminating
+    assert np.all(out2["n_proc"] == out2["f_blend"] + out2["f_cull"] + out2["term"])
+
+
+# ---------------------------------------------------------------- P4 / P7 --
+def _exact_beta_log2(mu, S, o, p):
+    d = np.asarray(mu, float) - np.asarray(p, float)
+    M = np.array([[S[0], S[1]], [S[1], S[2]]])
+    return (math.log(o) - 0.5 * d @ M @ d) / math.log(2)
+
+
+def _uv(mu, S, o, p, org):
+    """|u_i v_i| terms of the Frag2Mat dot product (log2-scaled), for the
+    bound of the rounding-error proposition (Appendix A.3)."""
+    dx, dy = mu[0] - org[0], mu[1] - org[1]
+    px, py = p[0] - org[0], p[1] - org[1]
+    v = np.array([math.log(o) - 0.5 * (S[0] * dx * dx + 2 * S[1] * dx * dy + S[2] * dy * dy),
+                  S[0] * dx + S[1] * dy, S[1] * dx + S[2] * dy, -0.5 * S[0], -S[1], -0.5 * S[2]])
+    u = np.array([1, px, py, px * px, px * py, py * py])
+    return np.abs(u * v) / math.log(2)
+
+
+def _u(p, org):
+    px, py = p[0] - org[0], p[1] - org[1]
+    return np.array([1, px, py, px * px, px * py, py * py])
+
+
+@pytest.mark.parametrize("mode,unit", [(2, 2.0 ** -11), (3, 2.0 ** -22), (4, 2.0 ** -24)])
+def test_emulated_beta_identity_and_bound(orc, mode, unit):
+    """Frag2Mat (Sec. 4.2): u^T v equals ln o - 1/2 d^T S d; in local
+    coordinates (Sec. 4.3) the only error is rounding v, bounded by
+    unit * sum |u_i v_i| (Appendix A, with the exact-u and RNE refinements)."""
+    g = np.random.default_rng(3)
+    worst = 0.0
+    for _ in range(3000):
+        tc = np.array([16 * g.integers(0, 100) + 7.5, 16 * g.integers(0, 60) + 7.5])
+        p = tc + g.integers(-7, 9, 2) - 0.5
+        mu = tc + g.normal(0, 12, 2)
+        L = np.array([[g.uniform(0.5, 30), 0], [g.normal(0, 3), g.uniform(0.5, 30)]])
+        Si = np.linalg.inv(L @ L.T)
+        S = np.array([Si[0, 0], Si[0, 1], Si[1, 1]])
+        o = g.uniform(0.01, 1)
+        b = orc.beta_emulated(mode, mu, S, o, p, tc)
+        ex = _exact_beta_log2(mu, S, o, p)
+        # relative part, plus half the FP16 subnormal spacing (2^-25) per
+        # term for coefficients that fall below the FP16 normal range
+        sub = 2.0 ** -25 * (np.abs(_u(p, tc)).sum() + 2) if mode in (2, 3) else 0.0
+        bound = unit * _uv(mu, S, o, p, tc).sum() * (3 if mode == 2 else 1) + sub + 1e-12
+        assert abs(b - ex) <= bound, (b, ex, bound)
+        worst = max(worst, abs(b - ex) / bound)
+    assert worst > 0.05  # the bound is reached to within a small factor: rounding is real
+
+
+def test_global_fp16_collapses_local_recovers(orc):
+    """Sec. 4.3 / Table 5: FP16 in global coordinates loses beta (quadratic
+    terms of size w^2), local coordinates keep it at O(w + h) eps."""
+    g = np.random.default_rng(5)
+    err_g, err_l = [], []
+    for _ in range(300):
+        tc = np.array([16 * g.integers(5, 15) + 7.5, 16 * g.integers(5, 15) + 7.5])
+        p = tc + g.integers(-7, 9, 2) - 0.5
+        mu = p + g.normal(0, 3, 2)
+        S = np.array([0.25, 0.02, 0.3])
+        o = 0.9
+        ex = _exact_beta_log2(mu, S, o, p)
+        err_g.append(abs(orc.beta_emulated(1, mu, S, o, p, tc) - ex))
+        err_l.append(abs(orc.beta_emulated(2, mu, S, o, p, tc) - ex))
+    assert np.median(err_g) > 1.0       # whole units of beta lost
+    assert np.max(err_l) < 0.05
+
+
+def test_g2l_translation_invariance(orc):
+    """G2L (Sec. 4.3): v depends on mu' - p(T) only, so shifting mu' and p by
+    whole tiles leaves the emulated beta bit-identical; the global frame does not."""
+    g = np.random.default_rng(9)
+    diff_global = 0
+    for _ in range(200):
+        tc = np.array([16 * 3 + 7.5, 16 * 2 + 7.5])
+        p = tc + g.integers(-7, 9, 2) - 0.5
+        mu = np.round((tc + g.normal(0, 6, 2)) * 256) / 256
+        S = np.array([0.3, -0.05, 0.2])
+        sh = np.array([16.0 * 41, 16.0 * 17])
+        for mode in (2, 3, 4):
+            assert orc.beta_emulated(mode, mu, S, 0.7, p, tc) == \
+                orc.beta_emulated(mode, mu + sh, S, 0.7, p + sh, tc + sh)
+        diff_global += orc.beta_emulated(1, mu, S, 0.7, p, tc) != \
+            orc.beta_emulated(1, mu + sh, S, 0.7, p + sh, tc + sh)
+    assert diff_global > 100
+
+
+# ---------------------------------------------------------------- rounding -
+def test_round_fp16_matches_numpy(orc):
+    g = np.random.default_rng(1)
+    xs = np.concatenate([g.normal(0, 1, 2000), g.normal(0, 1e4, 500), g.uniform(-1e-6, 1e-6, 500),
+                         [65504.0, 65519.0, 65520.0, -65520.0, 1e6, 2.0 ** -24, 2.0 ** -25,
+                          3 * 2.0 ** -26, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11]])
+    for x in xs:
+        with np.errstate(over="ignore"):
+            ref = float(np.float16(x))
+        got = orc.round_fp16(float(x))
+        assert (ref == got) or (math.isinf(ref) and math.isinf(got) and ref == got), (x, ref, got)
+
+
+def test_round_bf16_matches_torch(orc):
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(2)
+    xs = np.concatenate([g.normal(0, 1, 2000), g.normal(0, 1e20, 200), [1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8]])
+    xs = xs.astype(np.float32).astype(np.float64)  # torch converts from float32
+    ref = torch.tensor(xs, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    for x, r in zip(xs, ref):
+        assert orc.round_bf16(float(x)) == r
+
+
+# ---------------------------------------------------------------- SH -------
+def test_sh_orthonormal(orc):
+    """The degree-3 real SH basis is orthonormal on the sphere (quadrature)."""
+    nt, npf = 24, 48
+    xg, wg = np.polynomial.legendre.leggauss(nt)  # in cos(theta)
+    phi = (np.arange(npf) + 0.5) * 2 * np.pi / npf
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (np.repeat(wg, npf) * (2 * np.pi / npf))
+    Y = orc.sh_basis(dirs, 3)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-10)
+    assert abs(Y[0, 0] - 0.5 / math.sqrt(math.pi)) < 1e-15
+    # degree 1 is proportional to (y, z, x) with the Condon-Shortley sign on m = +-1
+    d = np.array([[0.3, -0.5, 0.8]])
+    d = d / np.linalg.norm(d)
+    Y1 = orc.sh_basis(d, 1)[0]
+    c1 = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose(Y1[1:4], [-c1 * d[0, 1], c1 * d[0, 2], -c1 * d[0, 0]], atol=1e-15)
+
+
+# ---------------------------------------------------------------- preprocess
+def test_preprocess_2d_against_linalg(orc):
+    """Conic = inverse covariance; r = ceil(3 sqrt(lambda_max)) when the
+    eigenvalues are well separated; tiles_touched = brute-force count of
+    tiles met by the pixel box [floor(mu) - r, floor(mu) + r]."""
+    sc = scenegen.scene_2d(300, 100, 70, seed=4)
+    out = orc.preprocess_2d(sc.means2d, sc.cov2d, 100, 70)
+    for i in range(sc.P):
+        C = np.array(sc.cov2d[i], float)
+        M = np.array([[C[0], C[1]], [C[1], C[2]]])
+        inv = np.linalg.inv(M)
+        np.testing.assert_allclose(out["conics"][i], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=1e-12)
+        ev = np.linalg.eigvalsh(M)
+        mid = 0.5 * (C[0] + C[2])
+        if mid * mid - np.linalg.det(M) > 0.1:
+            assert out["radii"][i] == math.ceil(3 * math.sqrt(ev[-1]))
+        r = out["radii"][i]
+        fx, fy = math.floor(sc.means2d[i, 0]), math.floor(sc.means2d[i, 1])
+        cnt = 0
+        for ty in range(5):
+            for tx in range(7):
+                if (fx + r >= 16 * tx and fx - r <= 16 * tx + 15 and fx - r <= 99 and
+                        fy + r >= 16 * ty and fy - r <= 16 * ty + 15 and fy - r <= 69):
+                    cnt += 1
+        assert out["tiles_touched"][i] == cnt
+
+
+def test_preprocess_3d_textbook(orc):
+    """Projection checks: a Gaussian on the optical axis projects to the
+    principal point with Sigma' = (f s / z)^2 I + 0.3 I; off axis, Sigma'
+    equals the finite-difference Jacobian of the pinhole map pushed through
+    the 3D covariance (Sec. 3.1: Sigma' = J W Sigma W^T J^T)."""
+    cam = scenegen.orbit_camera(0, 1, 640, 480)
+    P = 3
+    means = np.array([[0, 0, 0], [1.5, -1.0, 2.0], [-2.0, 0.5, -3.0]], np.float32)
+    scales = np.array([[0.1, 0.1, 0.1], [0.2, 0.05, 0.1], [0.02, 0.3, 0.08]], np.float32)
+    q = np.array([[1, 0, 0, 0], [0.9, 0.1, -0.3, 0.2], [0.2, 0.7, 0.1, -0.4]], np.float32)
+    sh = np.zeros((P, 16, 3), np.float32)
+    sc = scenegen.Scene3D(means=means, scales=scales, quats=q, opacities=np.full(P, 0.5, np.float32), sh=sh)
+    out = orc.preprocess_3d(sc, cam)
+    f = cam.fx
+    np.testing.assert_allclose(out["means2d"][0], [320, 240], atol=1e-9)
+    np.testing.assert_allclose(out["cov2d"][0], [(f * 0.1 / 15) ** 2 + 0.3, 0, (f * 0.1 / 15) ** 2 + 0.3],
+                               rtol=1e-6, atol=1e-9)
+    assert abs(out["depths"][0] - 15.0) < 1e-6
+    V = cam.viewmat.astype(np.float64)
+
+    def proj(x):
+        t = V[:3, :3] @ x + V[:3, 3]
+        return np.array([f * t[0] / t[2] + cam.cx, f * t[1] / t[2] + cam.cy])
+
+    for i in (1, 2):
+        m = means[i].astype(np.float64)
+        h = 1e-5
+        Jfd = np.stack([(proj(m + h * e) - proj(m - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        w, x, y, z = (q[i] / np.linalg.norm(q[i])).astype(np.float64)
+        R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                      [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+        Sig = R @ np.diag(scales[i].astype(np.float64) ** 2) @ R.T
+        C2 = Jfd @ Sig @ Jfd.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(out["cov2d"][i], [C2[0, 0], C2[0, 1], C2[1, 1]], rtol=1e-6)
+        np.testing.assert_allclose(out["means2d"][i], proj(m), rtol=1e-12)
+    # SH colour: with only the DC coefficient set, rgb = k00 Y00 + 0.5
+    sh2 = sh.copy()
+    sh2[:, 0, :] = [0.4, -0.2, -3.0]
+    sc2 = scenegen.Scene3D(means=means, scales=scales, quats=q, opacities=sc.opacities, sh=sh2)
+    out2 = orc.preprocess_3d(sc2, cam)
+    y00 = 0.5 / math.sqrt(math.pi)
+    np.testing.assert_allclose(out2["rgb"][0], [0.4 * y00 + 0.5, -0.2 * y00 + 0.5, 0.0], atol=1e-7)
+
+
+def test_preprocess_3d_near_plane_and_rotation_invariance(orc):
+    """Gaussians behind the near plane are dropped; a rotation about the
+    Gaussian's own isotropic shape does not change its projection."""
+    cam = scenegen.orbit_camera(0, 1, 320, 240)
+    means = np.array([[0, 0, 14.9], [0, 0, 20.0], [0.3, 0.2, 1.0], [0.3, 0.2, 1.0]], np.float32)
+    scales = np.array([[0.1] * 3, [0.1] * 3, [0.05] * 3, [0.05] * 3], np.float32)
+    q = np.array([[1, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0], [0.5, 0.5, -0.5, 0.5]], np.float32)
+    sc = scenegen.Scene3D(means=means, scales=scales, quats=q, opacities=np.full(4, .5, np.float32),
+                          sh=np.zeros((4, 16, 3), np.float32))
+    out = orc.preprocess_3d(sc, cam)
+    assert out["radii"][0] == 0 and out["radii"][1] == 0   # depth 0.1 and -5
+    np.testing.assert_allclose(out["cov2d"][2], out["cov2d"][3], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- P5 / P6 --
+def _brute_force(sc, conics, radii, W, H):
+    """Per pixel: every Gaussian whose coverage box meets the pixel's tile, in
+    (depth, index) order, then Algorithm 1.  Plain Python loops."""
+    img = np.zeros((3, H, W))
+    Tf = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            tx, ty = x // 16, y // 16
+            cand = []
+            for i in range(sc.P):
+                r = int(radii[i])
+                if r <= 0:
+                    continue
+                fx, fy = math.floor(sc.means2d[i, 0]), math.floor(sc.means2d[i, 1])
+                x0, x1 = max(fx - r, 0), min(fx + r, W - 1)
+                y0, y1 = max(fy - r, 0), min(fy + r, H - 1)
+                if x0 > x1 or y0 > y1:
+                    continue
+                if x0 // 16 <= tx <= x1 // 16 and y0 // 16 <= ty <= y1 // 16:
+                    cand.append((float(sc.depths[i]), i))
+            cand.sort()
+            T, C = 1.0, np.zeros(3)
+            for _, i in cand:
+                d = sc.means2d[i].astype(float) - [x, y]
+                S = conics[i]
+                q = S[0] * d[0] ** 2 + 2 * S[1] * d[0] * d[1] + S[2] * d[1] ** 2
+                a = min(0.99, float(sc.opacities[i]) * math.exp(-0.5 * q))
+                if a < 1 / 255:
+                    continue
+                if T - a * T < 1e-4:
+                    break
+                C += sc.rgb[i].astype(float) * a * T
+                T = T - a * T
+            img[:, y, x] = C
+            Tf[y, x] = T
+    return img, Tf
+
+
+def test_tiled_matches_brute_force(orc):
+    W, H = 32, 24
+    for seed in (21, 22):
+        sc = scenegen.scene_2d(20, W, H, seed=seed, s_min=0.8, s_max=5.0)
+        pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+        ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+        out = orc.render(W, H, ranges, ids, sc.means2d, pre["conics"], sc.opacities, sc.rgb)
+        img, Tf = _brute_force(sc, pre["conics"], pre["radii"], W, H)
+        np.testing.assert_allclose(out["rgb"], img, atol=1e-12)
+        np.testing.assert_allclose(out["T"], Tf, atol=1e-12)
+
+
+def test_permutation_invariance(orc):
+    """Shuffling the input order (distinct depths) leaves the image identical."""
+    W, H = 64, 48
+    sc = scenegen.scene_2d(150, W, H, seed=31)
+    perm = np.random.default_rng(0).permutation(sc.P)
+    outs = []
+    for pr in (np.arange(sc.P), perm):
+        m, cv, o, c, d = sc.means2d[pr], sc.cov2d[pr], sc.opacities[pr], sc.rgb[pr], sc.depths[pr]
+        pre = orc.preprocess_2d(m, cv, W, H)
+        ranges, ids = orc.bin_splats(m, pre["radii"], d, W, H)
+        outs.append(orc.render(W, H, ranges, ids, m, pre["conics"], o, c)["rgb"])
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_binning_order_and_ties(orc):
+    """Ties in depth are broken by Gaussian index; lists are sorted by depth."""
+    W, H = 48, 32
+    sc = scenegen.scene_2d(200, W, H, seed=41)
+    d = sc.depths.copy()
+    d[::3] = 5.0
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+    ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], d, W, H)
+    assert ranges[-1, 1] == len(ids) or ranges[:, 1].max() == len(ids)
+    for t in range(ranges.shape[0]):
+        s, e = ranges[t]
+        seg = ids[s:e]
+        keys = list(zip(d[seg], seg))
+        assert keys == sorted(keys)
+    assert int(pre["tiles_touched"].sum()) == len(ids)
+
+
+def test_alternatives_cover_nominal(orc):
+    """The admissible set always contains the nominal result (mask 0)."""
+    W, H = 64, 64
+    sc = scenegen.scene_2d(300, W, H, seed=51)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+    ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+    out = orc.render(W, H, ranges, ids, sc.means2d, pre["conics"], sc.opacities, sc.rgb,
+                     delta_c=1e-2, delta_t=1e-1)
+    ys, xs = np.nonzero(out["n_amb"] > 0)
+    assert len(ys) > 0
+    pix = np.stack([xs, ys], 1)[:50]
+    alt, altT = orc.render_alternatives(W, H, ranges, ids, sc.means2d, pre["conics"], sc.opacities,
+                                        sc.rgb, pix, delta_c=1e-2, delta_t=1e-1)
+    for j, (x, y) in enumerate(pix):
+        np.testing.assert_array_equal(alt[j, 0], out["rgb"][:, y, x])
+        assert np.any(np.abs(alt[j] - alt[j, :1]).max(axis=1) > 0)  # a flip changes something
+
+
+def test_emulated_render_quality(orc):
+    """E6 analogue at 256x256: FP16 in global coordinates is far from the
+    definition, local FP16 (K = 8 layout) is close, split variants closer."""
+    W = H = 256
+    sc = scenegen.scene_2d(2000, W, H, seed=1001)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+    ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+    ref = orc.render(W, H, ranges, ids, sc.means2d, pre["conics"], sc.opacities, sc.rgb)["rgb"]
+
+    def psnr(x):
+        mse = np.mean((x - ref) ** 2)
+        return 10 * np.log10(1.0 / mse) if mse > 0 else np.inf
+
+    p = {m: psnr(orc.render(W, H, ranges, ids, sc.means2d, pre["conics"], sc.opacities, sc.rgb,
+                            mode=m)["rgb"]) for m in (1, 2, 3, 4)}
+    assert p[1] < 30
+    assert p[2] > 50
+    assert p[3] > p[2] and p[4] > p[2]
