@@ -140,6 +140,7 @@ static int64_t tile_rect(double mx, double my, int r, int W, int H, int *tx0, in
 {
     if (r <= 0 || !isfinite(mx) || !isfinite(my)) return 0;
     if (fabs(mx) >= ORC_COORD_LIMIT || fabs(my) >= ORC_COORD_LIMIT) return 0;
+    if (r > (int)ORC_COORD_LIMIT) r = (int)ORC_COORD_LIMIT;
     double fx = floor(mx), fy = floor(my);
     double x0 = fx - r, x1 = fx + r, y0 = fy - r, y1 = fy + r;
     if (x1 < 0 || y1 < 0 || x0 > W - 1 || y0 > H - 1) return 0;

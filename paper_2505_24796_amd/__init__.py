@@ -1,0 +1,264 @@
+"""Python binding of libgsmfma, an MI355X (gfx950) tile-based Gaussian
+splatting rasteriser.
+
+Argument marshalling only: every step of the rendering path runs in the HIP
+kernels of ``libgsmfma.so``.  PyTorch provides device memory and the current
+stream.  There is no CPU fallback: when the library is missing or no GPU is
+present the calls raise.
+
+Entry points mirror the C ABI in ``include/gs.h``:
+
+* :func:`preprocess` / :func:`preprocess_2d` -- projection (TC-GS Sec. 3.1)
+* :func:`bin_sort` -- per-tile depth-ordered splat lists (Sec. 3.1)
+* :func:`rasterize_fwd` -- Algorithm 1 with the exponent computed per
+  ``precision`` (plain FP32, EarlyCull, Frag2Mat on FP16/BF16 matrix cores
+  with G2L local coordinates, Sec. 4)
+* :func:`rasterize_beta` -- diagnostic dump of the exponent matrix B
+* :func:`render` -- the three stages chained
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_size_t, c_uint32, c_void_p
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgsmfma.so")
+
+TILE = 16
+
+PRECISIONS = {
+    "fp32": 0,
+    "fp32_earlycull": 1,
+    "fp16_global": 2,
+    "fp16_g2l": 3,
+    "fp16_g2l_split": 4,
+    "bf16_g2l_split": 5,
+}
+
+STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARG", 2: "GS_ERR_UNSUPPORTED", 3: "GS_ERR_HIP",
+          4: "GS_ERR_CAPACITY", 5: "GS_ERR_NOT_IMPLEMENTED"}
+
+
+class GSError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class gs_camera(ctypes.Structure):
+    _fields_ = [("viewmat", c_float * 16), ("fx", c_float), ("fy", c_float), ("cx", c_float),
+                ("cy", c_float), ("width", c_int32), ("height", c_int32), ("near_z", c_float),
+                ("frustum_guard", c_float), ("lowpass", c_float), ("campos", c_float * 3)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgsmfma.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2505_24796_amd.build` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = c_void_p
+        L.gs_status_string.restype = ctypes.c_char_p
+        L.gs_status_string.argtypes = [ctypes.c_int]
+        L.gs_version.restype = ctypes.c_int
+        L.gs_preprocess.restype = ctypes.c_int
+        L.gs_preprocess.argtypes = [c_int32, vp, vp, vp, vp, c_int32, POINTER(gs_camera),
+                                    vp, vp, vp, vp, vp, vp, vp]
+        L.gs_preprocess_2d.restype = ctypes.c_int
+        L.gs_preprocess_2d.argtypes = [c_int32, vp, vp, c_int32, c_int32, vp, vp, vp, vp]
+        L.gs_bin_sort_workspace_bytes.restype = c_size_t
+        L.gs_bin_sort_workspace_bytes.argtypes = [c_int32, c_uint32, c_int32, c_int32]
+        L.gs_bin_sort.restype = ctypes.c_int
+        L.gs_bin_sort.argtypes = [c_int32, vp, vp, vp, c_int32, c_int32, c_uint32, vp, c_size_t,
+                                  vp, vp, vp, vp]
+        L.gs_rasterize_fwd.restype = ctypes.c_int
+        L.gs_rasterize_fwd.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp,
+                                       POINTER(c_float), c_int32, vp, vp, vp, vp, vp]
+        L.gs_rasterize_beta.restype = ctypes.c_int
+        L.gs_rasterize_beta.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, c_int32,
+                                        c_int32, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        raise GSError(fn, status)
+
+
+def _ptr(t):
+    return c_void_p(0) if t is None else c_void_p(t.data_ptr())
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def grid(width: int, height: int):
+    return (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+
+
+def make_camera(viewmat, fx, fy, cx, cy, width, height, near_z=0.2, frustum_guard=1.3,
+                lowpass=0.3, campos=(0.0, 0.0, 0.0)) -> gs_camera:
+    c = gs_camera()
+    vm = [float(v) for v in (viewmat.reshape(-1).tolist() if hasattr(viewmat, "reshape") else viewmat)]
+    c.viewmat[:] = vm
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    c.width, c.height = int(width), int(height)
+    c.near_z, c.frustum_guard, c.lowpass = float(near_z), float(frustum_guard), float(lowpass)
+    c.campos[:] = [float(v) for v in campos]
+    return c
+
+
+def preprocess(means3d, scales, quats, sh, cam: gs_camera, sh_degree: int = 3) -> dict:
+    P = means3d.shape[0]
+    f32 = torch.float32
+    for n, t in (("means3d", means3d), ("scales", scales), ("quats", quats), ("sh", sh)):
+        _dev(t, f32, n)
+    dev = means3d.device
+    out = dict(means2d=torch.empty(P, 2, dtype=f32, device=dev),
+               conics=torch.empty(P, 3, dtype=f32, device=dev),
+               depths=torch.empty(P, dtype=f32, device=dev),
+               radii=torch.empty(P, dtype=torch.int32, device=dev),
+               rgb=torch.empty(P, 3, dtype=f32, device=dev),
+               tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
+    st = lib().gs_preprocess(P, _ptr(means3d), _ptr(scales), _ptr(quats), _ptr(sh), sh_degree,
+                             ctypes.byref(cam), _ptr(out["means2d"]), _ptr(out["conics"]),
+                             _ptr(out["depths"]), _ptr(out["radii"]), _ptr(out["rgb"]),
+                             _ptr(out["tiles_touched"]), _stream())
+    _check("gs_preprocess", st)
+    return out
+
+
+def preprocess_2d(means2d, cov2d, width: int, height: int) -> dict:
+    P = means2d.shape[0]
+    _dev(means2d, torch.float32, "means2d")
+    _dev(cov2d, torch.float32, "cov2d")
+    dev = means2d.device
+    out = dict(conics=torch.empty(P, 3, dtype=torch.float32, device=dev),
+               radii=torch.empty(P, dtype=torch.int32, device=dev),
+               tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
+    st = lib().gs_preprocess_2d(P, _ptr(means2d), _ptr(cov2d), width, height, _ptr(out["conics"]),
+                                _ptr(out["radii"]), _ptr(out["tiles_touched"]), _stream())
+    _check("gs_preprocess_2d", st)
+    return out
+
+
+class BinSorter:
+    """Owns a workspace and output buffers for gs_bin_sort at a fixed
+    (P, capacity, width, height); reusable across frames (no allocation per
+    call)."""
+
+    def __init__(self, P: int, capacity: int, width: int, height: int, device="cuda"):
+        self.P, self.capacity, self.width, self.height = P, int(capacity), width, height
+        nbytes = lib().gs_bin_sort_workspace_bytes(P, self.capacity, width, height)
+        if nbytes == 0:
+            raise ValueError("invalid bin_sort sizes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        gx, gy = grid(width, height)
+        self.sorted_ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.ranges = torch.empty(gx * gy, 2, dtype=torch.int32, device=device)
+        self.num_splats = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def __call__(self, means2d, radii, depths):
+        _dev(means2d, torch.float32, "means2d")
+        _dev(radii, torch.int32, "radii")
+        _dev(depths, torch.float32, "depths")
+        st = lib().gs_bin_sort(self.P, _ptr(means2d), _ptr(radii), _ptr(depths), self.width,
+                               self.height, self.capacity, _ptr(self.workspace),
+                               self.workspace.numel(), _ptr(self.sorted_ids), _ptr(self.ranges),
+                               _ptr(self.num_splats), _stream())
+        _check("gs_bin_sort", st)
+        return self.sorted_ids, self.ranges, self.num_splats
+
+    def n_splats(self) -> int:
+        """Host read of the device splat count (synchronises)."""
+        return int(self.num_splats.item()) & 0xFFFFFFFF
+
+
+def bin_sort(means2d, radii, depths, width: int, height: int, capacity: int | None = None):
+    """One-shot binning.  Without ``capacity`` the splat count is computed by
+    a first call with capacity 0 (one host synchronisation)."""
+    P = means2d.shape[0]
+    if capacity is None:
+        probe = BinSorter(P, 0, width, height, device=means2d.device)
+        probe(means2d, radii, depths)
+        capacity = max(probe.n_splats(), 1)
+    bs = BinSorter(P, capacity, width, height, device=means2d.device)
+    bs(means2d, radii, depths)
+    return bs
+
+
+class Rasterizer:
+    """Owns the output buffers of gs_rasterize_fwd for one image size."""
+
+    def __init__(self, width: int, height: int, device="cuda"):
+        self.width, self.height = width, height
+        self.rgb = torch.empty(3, height, width, dtype=torch.float32, device=device)
+        self.T = torch.empty(height, width, dtype=torch.float32, device=device)
+        self.n_contrib = torch.empty(height, width, dtype=torch.int32, device=device)
+        self.counters = torch.zeros(4, dtype=torch.int64, device=device)
+
+    def __call__(self, ranges, sorted_ids, means2d, conics, opacities, rgb, precision="fp32",
+                 background=(0.0, 0.0, 0.0), count: bool = False):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        for n, t, dt in (("ranges", ranges, torch.int32), ("sorted_ids", sorted_ids, torch.int32),
+                         ("means2d", means2d, torch.float32), ("conics", conics, torch.float32),
+                         ("opacities", opacities, torch.float32), ("rgb", rgb, torch.float32)):
+            _dev(t, dt, n)
+        bg = (c_float * 3)(*[float(b) for b in background])
+        if count:
+            self.counters.zero_()
+        st = lib().gs_rasterize_fwd(self.width, self.height, _ptr(ranges), _ptr(sorted_ids),
+                                    _ptr(means2d), _ptr(conics), _ptr(opacities), _ptr(rgb), bg,
+                                    prec, _ptr(self.rgb), _ptr(self.T), _ptr(self.n_contrib),
+                                    _ptr(self.counters) if count else c_void_p(0), _stream())
+        _check("gs_rasterize_fwd", st)
+        return self.rgb, self.T, self.n_contrib
+
+
+def rasterize_fwd(width, height, ranges, sorted_ids, means2d, conics, opacities, rgb,
+                  precision="fp32", background=(0.0, 0.0, 0.0), count=False):
+    r = Rasterizer(width, height, device=means2d.device)
+    r(ranges, sorted_ids, means2d, conics, opacities, rgb, precision, background, count)
+    return r
+
+
+def rasterize_beta(width, height, tile, ranges, sorted_ids, means2d, conics, opacities,
+                   precision="fp16_g2l_split", count=32):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    out = torch.empty(count, 256, dtype=torch.float32, device=means2d.device)
+    st = lib().gs_rasterize_beta(width, height, int(tile), _ptr(ranges), _ptr(sorted_ids),
+                                 _ptr(means2d), _ptr(conics), _ptr(opacities), prec, int(count),
+                                 _ptr(out), _stream())
+    _check("gs_rasterize_beta", st)
+    return out
+
+
+def render(means3d, scales, quats, sh, opacities, cam: gs_camera, precision="fp16_g2l_split",
+           capacity=None, background=(0.0, 0.0, 0.0)):
+    """Preprocess -> bin/sort -> rasterise, all on the current stream."""
+    pre = preprocess(means3d, scales, quats, sh, cam)
+    bs = bin_sort(pre["means2d"], pre["radii"], pre["depths"], cam.width, cam.height, capacity)
+    r = Rasterizer(cam.width, cam.height, device=means3d.device)
+    r(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opacities, pre["rgb"], precision,
+      background)
+    return r, bs, pre

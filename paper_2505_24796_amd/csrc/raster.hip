@@ -1,0 +1,617 @@
+// Conditional alpha-blending per 16x16 tile (TC-GS paper, Sec. 3.1,
+// Algorithm 1) in two forms:
+//
+//  * k_raster_fp32: Algorithm 1 literally on the vector ALUs, one pixel per
+//    lane, the tile's splats staged through LDS 256 at a time.  With EARLY the
+//    1/255 test is made on the exponent before exp (EarlyCull, Sec. 4.1).
+//
+//  * k_raster_mfma: the exponent matrix B = U^T V (Frag2Mat, Sec. 4.2) of
+//    256 pixels x 32 splats on the matrix cores, in tile-local coordinates
+//    (G2L, Sec. 4.3), then EarlyCull and blending on the vector ALUs.
+//
+// MFMA layout (v_mfma_f32_32x32x{8,16}): rows = 32 splats (operand A = V),
+// columns = 32 pixels (operand B = U), FP32 accumulators.  A wave owns one
+// 8x8 pixel quadrant of the tile = two 32-pixel column groups, so each
+// 32-splat sub-batch costs two MFMAs.  Output lane l of group G holds column
+// l%32 and 16 of the 32 rows; rows are assigned to splats so that after one
+// v_permlane32_swap per accumulator pair every lane holds the exponents of
+// ITS OWN pixel for all 32 splats in depth order: register r of the first
+// accumulator = splat r, of the second = splat 16 + r.  Blending then runs
+// per lane with no LDS round trip for B.
+//
+// EarlyCull on SIMD: a splat is visited only if ballot(beta >= -log2 255) is
+// non-zero over the wave's 64 pixels; the exp and the blend run only then.
+// The coefficients are pre-scaled by log2(e) so alpha = 2^beta (v_exp_f32).
+#include "common.h"
+
+namespace {
+
+constexpr float ALPHA_MAX = 0.99f;
+constexpr float T_MIN = 1e-4f;
+constexpr float CULL_ALPHA = 1.0f / 255.0f;
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float CULL_LN = -5.541263545158426f;   // -ln 255
+constexpr float CULL_LOG2 = -7.994353436858858f; // -log2 255
+constexpr int BATCH = 256;                       // splats staged per LDS round
+constexpr int SUB = 32;                          // splats per MFMA
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+struct RasterArgs {
+    int W, H, gx, gy;
+    const uint32_t *ranges;
+    const uint32_t *ids;
+    const float2 *means2d;
+    const float *conics;
+    const float *opac;
+    const float *rgb;
+    float bg0, bg1, bg2;
+    float *out_rgb;
+    float *out_T;
+    uint32_t *out_nc;
+    unsigned long long *counters;
+};
+
+__device__ __forceinline__ void add_counters(unsigned long long *c, uint32_t nb, uint32_t nc,
+                                             uint32_t nt) {
+    // wave-reduce then one atomic per wave
+    unsigned long long b = nb, cl = nc, t = nt;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        b += __shfl_xor(b, d, 64);
+        cl += __shfl_xor(cl, d, 64);
+        t += __shfl_xor(t, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(c + 0, b);
+        atomicAdd(c + 1, cl);
+        atomicAdd(c + 2, t);
+        atomicAdd(c + 3, b + cl + t);
+    }
+}
+
+__device__ __forceinline__ void write_pixel(const RasterArgs &a, int px, int py, float C0, float C1,
+                                            float C2, float T, uint32_t last) {
+    if (px < a.W && py < a.H) {
+        size_t pi = (size_t)py * a.W + px, hw = (size_t)a.W * a.H;
+        a.out_rgb[pi] = fmaf(T, a.bg0, C0);
+        a.out_rgb[hw + pi] = fmaf(T, a.bg1, C1);
+        a.out_rgb[2 * hw + pi] = fmaf(T, a.bg2, C2);
+        a.out_T[pi] = T;
+        a.out_nc[pi] = last;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain FP32 kernel
+// ---------------------------------------------------------------------------
+template <bool EARLY, bool COUNT>
+__global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
+    __shared__ float2 s_mu[BATCH];
+    __shared__ float4 s_co[BATCH];  // s11, s12, s22, o (or ln o with EARLY)
+    __shared__ float4 s_rgb[BATCH];
+    int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
+    if (tile < 0) return;
+    int tx = tile % a.gx, ty = tile / a.gx;
+    int px = tx * GS_TILE + (threadIdx.x & 15), py = ty * GS_TILE + (threadIdx.x >> 4);
+    bool done = !(px < a.W && py < a.H);
+    uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    float fx = (float)px, fy = (float)py;
+    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    uint32_t last = 0, nb = 0, nc = 0, nt = 0;
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+        if (__syncthreads_count(done) == BATCH) break;
+        uint32_t k = b0 + threadIdx.x;
+        if (k < end) {
+            uint32_t id = a.ids[k];
+            s_mu[threadIdx.x] = a.means2d[id];
+            float o = a.opac[id];
+            s_co[threadIdx.x] = make_float4(a.conics[3 * id], a.conics[3 * id + 1],
+                                            a.conics[3 * id + 2], EARLY ? __logf(o) : o);
+            s_rgb[threadIdx.x] = make_float4(a.rgb[3 * id], a.rgb[3 * id + 1], a.rgb[3 * id + 2], 0.f);
+        }
+        __syncthreads();
+        int cnt = (int)min((uint32_t)BATCH, end - b0);
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                float2 m = s_mu[j];
+                float4 c = s_co[j];
+                float dx = m.x - fx, dy = m.y - fy;
+                float power = -0.5f * (c.x * dx * dx + c.z * dy * dy) - c.y * dx * dy;
+                float alpha;
+                if (EARLY) {
+                    float beta = c.w + power;
+                    if (beta < CULL_LN) {
+                        if (COUNT) ++nc;
+                        continue;
+                    }
+                    alpha = fminf(ALPHA_MAX, __expf(beta));
+                } else {
+                    alpha = fminf(ALPHA_MAX, c.w * __expf(power));
+                    if (alpha < CULL_ALPHA) {
+                        if (COUNT) ++nc;
+                        continue;
+                    }
+                }
+                float test = fmaf(-alpha, T, T);
+                if (test < T_MIN) {
+                    done = true;
+                    if (COUNT) nt = 1;
+                    break;
+                }
+                float w = alpha * T;
+                float4 col = s_rgb[j];
+                C0 = fmaf(col.x, w, C0);
+                C1 = fmaf(col.y, w, C1);
+                C2 = fmaf(col.z, w, C2);
+                T = test;
+                last = b0 - start + (uint32_t)j + 1u;
+                if (COUNT) ++nb;
+            }
+        }
+    }
+    write_pixel(a, px, py, C0, C1, C2, T, last);
+    if (COUNT) add_counters(a.counters, nb, nc, nt);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core kernel
+// ---------------------------------------------------------------------------
+enum Variant { VAR_F16_GLOBAL = 0, VAR_F16_G2L = 1, VAR_F16_SPLIT = 2, VAR_BF16_SPLIT = 3 };
+
+template <int VAR> struct VarTraits;
+// K = 8: [v0/3 x3, v1..v5] against [1 x3, dx, dy, dx^2, dxdy, dy^2]
+template <> struct VarTraits<VAR_F16_GLOBAL> { static constexpr int ROW1 = 16, ROW2 = 0; static constexpr bool LOCAL = false; };
+template <> struct VarTraits<VAR_F16_G2L> { static constexpr int ROW1 = 16, ROW2 = 0; static constexpr bool LOCAL = true; };
+// K = 16: [hi(6), 0, 0 | lo(6), 0, 0] against [u(6), 0, 0 | u(6), 0, 0]
+template <> struct VarTraits<VAR_F16_SPLIT> { static constexpr int ROW1 = 32, ROW2 = 0; static constexpr bool LOCAL = true; };
+// K = 16 + 8: [hi(6),0,0 | mid(6),0,0] then [lo0..3 | lo4, lo5, 0, 0]
+template <> struct VarTraits<VAR_BF16_SPLIT> { static constexpr int ROW1 = 32, ROW2 = 16; static constexpr bool LOCAL = true; };
+
+// Row of the 32x32 MFMA that holds splat j of a sub-batch: output register
+// r of lanes 0-31 holds row 8(r/4) + r%4, of lanes 32-63 row 8(r/4)+4+r%4.
+__device__ __forceinline__ int row_of_splat(int j) {
+    int h = j >> 4, r = j & 15;
+    return 8 * (r >> 2) + 4 * h + (r & 3);
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    __bf16 b = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, b);
+}
+__device__ __forceinline__ float bf16_val(float x) { return (float)(__bf16)x; }
+
+// Write the operand-A row of one splat.  Coefficients (Sec. 4.2) in the frame
+// with origin (ox, oy), scaled by log2(e):
+//   v0 = log2 o - 1/2 log2e dmu^T S dmu, v1 = log2e (s11 dx + s12 dy),
+//   v2 = log2e (s12 dx + s22 dy), v3 = -1/2 log2e s11, v4 = -log2e s12,
+//   v5 = -1/2 log2e s22,  dmu = mu' - origin.
+template <int VAR>
+__device__ __forceinline__ void build_row(bool valid, float2 mu, float s11, float s12, float s22,
+                                          float o, float ox, float oy, uint8_t *row1, uint8_t *row2) {
+    float v[6];
+    if (valid) {
+        float dx = mu.x - ox, dy = mu.y - oy;
+        float q = fmaf(s11 * dx, dx, fmaf(2.0f * s12 * dx, dy, s22 * dy * dy));
+        v[0] = __log2f(o) - 0.5f * LOG2E * q;
+        v[1] = LOG2E * fmaf(s11, dx, s12 * dy);
+        v[2] = LOG2E * fmaf(s12, dx, s22 * dy);
+        v[3] = -0.5f * LOG2E * s11;
+        v[4] = -LOG2E * s12;
+        v[5] = -0.5f * LOG2E * s22;
+    } else {
+        v[0] = -__builtin_inff();
+        v[1] = v[2] = v[3] = v[4] = v[5] = 0.0f;
+    }
+    if (VAR == VAR_F16_GLOBAL || VAR == VAR_F16_G2L) {
+        _Float16 w0 = (_Float16)(v[0] * (1.0f / 3.0f));
+        half8_t r = {w0, w0, w0, (_Float16)v[1], (_Float16)v[2], (_Float16)v[3], (_Float16)v[4],
+                     (_Float16)v[5]};
+        *(half8_t *)row1 = r;
+    } else if (VAR == VAR_F16_SPLIT) {
+        half8_t hi, lo;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            _Float16 h = (_Float16)v[i];
+            hi[i] = h;
+            lo[i] = valid ? (_Float16)(v[i] - (float)h) : (_Float16)0.0f;
+        }
+        hi[6] = hi[7] = lo[6] = lo[7] = (_Float16)0.0f;
+        *(half8_t *)row1 = hi;
+        *(half8_t *)(row1 + 16) = lo;
+    } else {
+        uint16_t hb[8], mb[8], lb[4 + 4];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            float h = bf16_val(v[i]);
+            float rem = valid ? v[i] - h : 0.0f;
+            float m = bf16_val(rem);
+            float rem2 = valid ? rem - m : 0.0f;
+            hb[i] = bf16_bits(v[i]);
+            mb[i] = bf16_bits(rem);
+            lb[i] = bf16_bits(rem2);
+        }
+        hb[6] = hb[7] = mb[6] = mb[7] = lb[6] = lb[7] = 0;
+        uint4 w1 = make_uint4(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16), 0u);
+        uint4 w2 = make_uint4(mb[0] | (mb[1] << 16), mb[2] | (mb[3] << 16), mb[4] | (mb[5] << 16), 0u);
+        uint4 w3 = make_uint4(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16), lb[4] | (lb[5] << 16), 0u);
+        *(uint4 *)row1 = w1;
+        *(uint4 *)(row1 + 16) = w2;
+        *(uint4 *)row2 = w3;
+    }
+}
+
+// Operand B (pixel features) of one lane for column group G.
+struct UOperand {
+    half4_t k8;
+    half8_t k16;
+    bf16x8_t b16;
+    short4_t b8;
+};
+
+template <int VAR>
+__device__ __forceinline__ UOperand make_u(float ux, float uy, int slice) {
+    UOperand u;
+    float f[6] = {1.0f, ux, uy, ux * ux, ux * uy, uy * uy};
+    if (VAR == VAR_F16_GLOBAL || VAR == VAR_F16_G2L) {
+        float e[8] = {1.0f, 1.0f, 1.0f, f[1], f[2], f[3], f[4], f[5]};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u.k8[i] = (_Float16)e[4 * slice + i];
+    } else if (VAR == VAR_F16_SPLIT) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) u.k16[i] = (_Float16)f[i];
+        u.k16[6] = u.k16[7] = (_Float16)0.0f;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) u.b16[i] = (__bf16)f[i];
+        u.b16[6] = u.b16[7] = (__bf16)0.0f;
+        float e[8] = {f[0], f[1], f[2], f[3], f[4], f[5], 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u.b8[i] = (short)bf16_bits(e[4 * slice + i]);
+    }
+    return u;
+}
+
+// B for the two column groups of this lane's wave quadrant -> exponents of
+// this lane's own pixel for 32 splats (log2 units): lo[r] = splat r,
+// hi[r] = splat 16 + r.
+template <int VAR>
+__device__ __forceinline__ void exponents(const uint8_t *a1, const uint8_t *a2, const UOperand &u0,
+                                          const UOperand &u1, int lane, float lo[16], float hi[16]) {
+    f32x16_t acc0 = {}, acc1 = {};
+    int row = lane & 31, slice = lane >> 5;
+    if (VAR == VAR_F16_GLOBAL || VAR == VAR_F16_G2L) {
+        half4_t av = *(const half4_t *)(a1 + row * 16 + slice * 8);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x8f16(av, u0.k8, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(av, u1.k8, acc1, 0, 0, 0);
+    } else if (VAR == VAR_F16_SPLIT) {
+        half8_t av = *(const half8_t *)(a1 + row * 32 + slice * 16);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, u0.k16, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, u1.k16, acc1, 0, 0, 0);
+    } else {
+        bf16x8_t av = *(const bf16x8_t *)(a1 + row * 32 + slice * 16);
+        short4_t aw = *(const short4_t *)(a2 + row * 16 + slice * 8);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, u0.b16, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, u1.b16, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, u0.b8, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw, u1.b8, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc0[r]), __float_as_uint(acc1[r]),
+                                                   false, false);
+        lo[r] = __uint_as_float(sw[0]);
+        hi[r] = __uint_as_float(sw[1]);
+    }
+}
+
+// LDS footprint of one staged batch.
+template <int VAR> struct Stage {
+    static constexpr int A1 = BATCH * VarTraits<VAR>::ROW1;
+    static constexpr int A2 = BATCH * VarTraits<VAR>::ROW2;
+    static constexpr int RGB = BATCH * 16;
+    static constexpr int BYTES = A1 + A2 + RGB;
+};
+
+struct SplatRegs {
+    float2 mu;
+    float s11, s12, s22, o, r, g, b;
+    bool valid;
+};
+
+__device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bool valid) {
+    SplatRegs s;
+    s.valid = valid;
+    if (valid) {
+        s.mu = a.means2d[id];
+        s.s11 = a.conics[3 * id];
+        s.s12 = a.conics[3 * id + 1];
+        s.s22 = a.conics[3 * id + 2];
+        s.o = a.opac[id];
+        s.r = a.rgb[3 * id];
+        s.g = a.rgb[3 * id + 1];
+        s.b = a.rgb[3 * id + 2];
+    } else {
+        s.mu = make_float2(0.f, 0.f);
+        s.s11 = s.s12 = s.s22 = 0.f;
+        s.o = 1.f;
+        s.r = s.g = s.b = 0.f;
+    }
+    return s;
+}
+
+template <int VAR>
+__device__ __forceinline__ void stage_splat(uint8_t *stage, int j, const SplatRegs &s, float ox,
+                                            float oy) {
+    int sub = j / SUB, row = row_of_splat(j % SUB);
+    uint8_t *row1 = stage + sub * SUB * VarTraits<VAR>::ROW1 + row * VarTraits<VAR>::ROW1;
+    uint8_t *row2 = stage + Stage<VAR>::A1 + sub * SUB * VarTraits<VAR>::ROW2 + row * VarTraits<VAR>::ROW2;
+    build_row<VAR>(s.valid, s.mu, s.s11, s.s12, s.s22, s.o, ox, oy, row1, row2);
+    float4 *rgb = (float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
+    rgb[j] = make_float4(s.r, s.g, s.b, 0.f);
+}
+
+template <int VAR, bool COUNT>
+__global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][Stage<VAR>::BYTES];
+    __shared__ int s_flags[2][4];
+    int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
+    if (tile < 0) return;
+    const int tx = tile % a.gx, ty = tile / a.gx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int qx = (wave & 1) * 8, qy = (wave >> 1) * 8;
+    const int px = tx * GS_TILE + qx + (lane & 7), py = ty * GS_TILE + qy + (lane >> 3);
+    // frame origin: the tile centre (G2L) or the image origin
+    const float ox = VarTraits<VAR>::LOCAL ? tx * GS_TILE + 7.5f : 0.0f;
+    const float oy = VarTraits<VAR>::LOCAL ? ty * GS_TILE + 7.5f : 0.0f;
+    // operand B: column j = lane%32 of group G is pixel (qx + j%8, qy + 4G + j/8)
+    UOperand u0, u1;
+    {
+        int j = lane & 31, slice = lane >> 5;
+        float bx = (float)(tx * GS_TILE + qx + (j & 7)) - ox;
+        float by0 = (float)(ty * GS_TILE + qy + (j >> 3)) - oy;
+        u0 = make_u<VAR>(bx, by0, slice);
+        u1 = make_u<VAR>(bx, by0 + 4.0f, slice);
+    }
+    bool done = !(px < a.W && py < a.H);
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t n = end - start;
+    const uint32_t nbatch = (n + BATCH - 1) / BATCH;
+    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    uint32_t last = 0, nb = 0, ncl = 0, nt = 0;
+
+    // software pipeline: data of batch b+1 and the id of batch b+2 are in
+    // flight while batch b is blended
+    uint32_t k0 = start + threadIdx.x;
+    uint32_t id_cur = k0 < end ? a.ids[k0] : 0u;
+    SplatRegs cur = gather(a, id_cur, k0 < end);
+    uint32_t k1 = k0 + BATCH;
+    uint32_t id_next = k1 < end ? a.ids[k1] : 0u;
+
+    for (uint32_t b = 0; b < nbatch; ++b) {
+        const int buf = b & 1;
+        uint8_t *stage = lds[buf];
+        stage_splat<VAR>(stage, threadIdx.x, cur, ox, oy);
+        {
+            uint32_t kn = start + (b + 1) * BATCH + threadIdx.x;
+            cur = gather(a, id_next, kn < end);
+            uint32_t kn2 = kn + BATCH;
+            id_next = kn2 < end ? a.ids[kn2] : 0u;
+        }
+        bool wave_done = __ballot(!done) == 0ull;
+        if (lane == 0) s_flags[buf][wave] = wave_done;
+        __syncthreads();
+        if (s_flags[buf][0] & s_flags[buf][1] & s_flags[buf][2] & s_flags[buf][3]) break;
+        if (wave_done) continue;
+        const uint32_t bcount = min((uint32_t)BATCH, n - b * BATCH);
+        const uint32_t nsub = (bcount + SUB - 1) / SUB;
+        const float4 *rgbs = (const float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
+        for (uint32_t sidx = 0; sidx < nsub; ++sidx) {
+            float lo[16], hi[16];
+            exponents<VAR>(stage + sidx * SUB * VarTraits<VAR>::ROW1,
+                           stage + Stage<VAR>::A1 + sidx * SUB * VarTraits<VAR>::ROW2, u0, u1, lane,
+                           lo, hi);
+            const uint32_t scount = min((uint32_t)SUB, bcount - sidx * SUB);
+            uint32_t valid = scount >= 32 ? 0xFFFFFFFFu : ((1u << scount) - 1u);
+            float thr = done ? __builtin_inff() : CULL_LOG2;
+            uint32_t alive = 0;
+            if (COUNT) {
+                alive = valid;
+            } else {
+#pragma unroll
+                for (int g = 0; g < 16; ++g) {
+                    alive |= (__ballot(lo[g] >= thr) != 0ull) ? (1u << g) : 0u;
+                    alive |= (__ballot(hi[g] >= thr) != 0ull) ? (1u << (16 + g)) : 0u;
+                }
+                alive &= valid;
+            }
+            const uint32_t base = b * BATCH + sidx * SUB;
+#pragma unroll
+            for (int g = 0; g < 32; ++g) {
+                if (alive & (1u << g)) {
+                    float beta = g < 16 ? lo[g] : hi[g - 16];
+                    if (COUNT && !done && !(beta >= thr)) ++ncl;
+                    if (beta >= thr) {
+                        float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(beta));
+                        float test = fmaf(-alpha, T, T);
+                        if (test < T_MIN) {
+                            done = true;
+                            thr = __builtin_inff();
+                            if (COUNT) nt = 1;
+                        } else {
+                            float4 col = rgbs[sidx * SUB + g];
+                            float w = alpha * T;
+                            C0 = fmaf(col.x, w, C0);
+                            C1 = fmaf(col.y, w, C1);
+                            C2 = fmaf(col.z, w, C2);
+                            T = test;
+                            last = base + (uint32_t)g + 1u;
+                            if (COUNT) ++nb;
+                        }
+                    }
+                }
+            }
+            if (__ballot(!done) == 0ull) break;
+        }
+    }
+    write_pixel(a, px, py, C0, C1, C2, T, last);
+    if (COUNT) add_counters(a.counters, nb, ncl, nt);
+}
+
+// Diagnostic: exponents of the first `count` splats of one tile.
+template <int VAR>
+__global__ __launch_bounds__(256) void k_beta_dump(RasterArgs a, int tile, int count, float *out) {
+    __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR>::BYTES];
+    const int tx = tile % a.gx, ty = tile / a.gx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int qx = (wave & 1) * 8, qy = (wave >> 1) * 8;
+    const float ox = VarTraits<VAR>::LOCAL ? tx * GS_TILE + 7.5f : 0.0f;
+    const float oy = VarTraits<VAR>::LOCAL ? ty * GS_TILE + 7.5f : 0.0f;
+    UOperand u0, u1;
+    {
+        int j = lane & 31, slice = lane >> 5;
+        float bx = (float)(tx * GS_TILE + qx + (j & 7)) - ox;
+        float by0 = (float)(ty * GS_TILE + qy + (j >> 3)) - oy;
+        u0 = make_u<VAR>(bx, by0, slice);
+        u1 = make_u<VAR>(bx, by0 + 4.0f, slice);
+    }
+    const int pix = (qy + (lane >> 3)) * GS_TILE + qx + (lane & 7);
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t n = end - start;
+    for (int b0 = 0; b0 < count; b0 += BATCH) {
+        uint32_t k = start + b0 + threadIdx.x;
+        bool valid = (uint32_t)(b0 + threadIdx.x) < n;
+        uint32_t id = valid ? a.ids[k] : 0u;
+        __syncthreads();
+        stage_splat<VAR>(stage, threadIdx.x, gather(a, id, valid), ox, oy);
+        __syncthreads();
+        for (int sidx = 0; sidx < BATCH / SUB && b0 + sidx * SUB < count; ++sidx) {
+            float lo[16], hi[16];
+            exponents<VAR>(stage + sidx * SUB * VarTraits<VAR>::ROW1,
+                           stage + Stage<VAR>::A1 + sidx * SUB * VarTraits<VAR>::ROW2, u0, u1, lane,
+                           lo, hi);
+#pragma unroll
+            for (int g = 0; g < 32; ++g) {
+                int row = b0 + sidx * SUB + g;
+                if (row < count) {
+                    float v = g < 16 ? lo[g] : hi[g - 16];
+                    out[(size_t)row * GS_TILE_PIX + pix] = (uint32_t)row < n ? v : __builtin_nanf("");
+                }
+            }
+        }
+    }
+}
+
+template <int VAR>
+void launch_mfma(const RasterArgs &a, int blocks, bool count, hipStream_t s) {
+    if (count)
+        hipLaunchKernelGGL((k_raster_mfma<VAR, true>), dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_raster_mfma<VAR, false>), dim3(blocks), dim3(256), 0, s, a);
+}
+
+bool valid_inputs(int32_t width, int32_t height, const void *const *p, int n) {
+    if (width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return false;
+    for (int i = 0; i < n; ++i)
+        if (!p[i] || !gs::aligned(p[i], 4)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
+                                      const uint32_t *sorted_ids, const float *means2d,
+                                      const float *conics, const float *opacities,
+                                      const float *rgb, const float *background, int32_t precision,
+                                      float *out_rgb, float *out_T, uint32_t *out_ncontrib,
+                                      uint64_t *d_counters, void *stream) {
+    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, opacities, rgb, out_rgb, out_T, out_ncontrib};
+    if (!valid_inputs(width, height, ptrs, 9) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
+    if (d_counters && !gs::aligned(d_counters, 8)) return GS_ERR_INVALID_ARG;
+    if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
+    RasterArgs a;
+    a.W = width;
+    a.H = height;
+    a.gx = gs::grid_x(width);
+    a.gy = gs::grid_y(height);
+    a.ranges = tile_ranges;
+    a.ids = sorted_ids;
+    a.means2d = (const float2 *)means2d;
+    a.conics = conics;
+    a.opac = opacities;
+    a.rgb = rgb;
+    a.bg0 = background ? background[0] : 0.f;
+    a.bg1 = background ? background[1] : 0.f;
+    a.bg2 = background ? background[2] : 0.f;
+    a.out_rgb = out_rgb;
+    a.out_T = out_T;
+    a.out_nc = out_ncontrib;
+    a.counters = (unsigned long long *)d_counters;
+    hipStream_t s = (hipStream_t)stream;
+    int blocks = gs::xcd_grid_blocks(a.gx, a.gy);
+    bool cnt = d_counters != nullptr;
+    switch (precision) {
+    case GS_PREC_FP32:
+        if (cnt) hipLaunchKernelGGL((k_raster_fp32<false, true>), dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_raster_fp32<false, false>), dim3(blocks), dim3(256), 0, s, a);
+        break;
+    case GS_PREC_FP32_EARLYCULL:
+        if (cnt) hipLaunchKernelGGL((k_raster_fp32<true, true>), dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_raster_fp32<true, false>), dim3(blocks), dim3(256), 0, s, a);
+        break;
+    case GS_PREC_FP16_GLOBAL: launch_mfma<VAR_F16_GLOBAL>(a, blocks, cnt, s); break;
+    case GS_PREC_FP16_G2L: launch_mfma<VAR_F16_G2L>(a, blocks, cnt, s); break;
+    case GS_PREC_FP16_G2L_SPLIT: launch_mfma<VAR_F16_SPLIT>(a, blocks, cnt, s); break;
+    case GS_PREC_BF16_G2L_SPLIT: launch_mfma<VAR_BF16_SPLIT>(a, blocks, cnt, s); break;
+    }
+    return gs::launch_status();
+}
+
+extern "C" gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t tile,
+                                       const uint32_t *tile_ranges, const uint32_t *sorted_ids,
+                                       const float *means2d, const float *conics,
+                                       const float *opacities, int32_t precision, int32_t count,
+                                       float *out_beta, void *stream) {
+    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, opacities, out_beta};
+    if (!valid_inputs(width, height, ptrs, 6) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
+    int ntiles = gs::grid_x(width) * gs::grid_y(height);
+    if (tile < 0 || tile >= ntiles || count <= 0) return GS_ERR_INVALID_ARG;
+    if (precision < GS_PREC_FP16_GLOBAL || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
+    RasterArgs a{};
+    a.W = width;
+    a.H = height;
+    a.gx = gs::grid_x(width);
+    a.gy = gs::grid_y(height);
+    a.ranges = tile_ranges;
+    a.ids = sorted_ids;
+    a.means2d = (const float2 *)means2d;
+    a.conics = conics;
+    a.opac = opacities;
+    a.rgb = opacities;  // colours are not needed; any valid pointer
+    hipStream_t s = (hipStream_t)stream;
+    switch (precision) {
+    case GS_PREC_FP16_GLOBAL: hipLaunchKernelGGL(k_beta_dump<VAR_F16_GLOBAL>, dim3(1), dim3(256), 0, s, a, tile, count, out_beta); break;
+    case GS_PREC_FP16_G2L: hipLaunchKernelGGL(k_beta_dump<VAR_F16_G2L>, dim3(1), dim3(256), 0, s, a, tile, count, out_beta); break;
+    case GS_PREC_FP16_G2L_SPLIT: hipLaunchKernelGGL(k_beta_dump<VAR_F16_SPLIT>, dim3(1), dim3(256), 0, s, a, tile, count, out_beta); break;
+    case GS_PREC_BF16_G2L_SPLIT: hipLaunchKernelGGL(k_beta_dump<VAR_BF16_SPLIT>, dim3(1), dim3(256), 0, s, a, tile, count, out_beta); break;
+    }
+    return gs::launch_status();
+}
+
+extern "C" const char *gs_status_string(int status) {
+    switch (status) {
+    case GS_OK: return "GS_OK";
+    case GS_ERR_INVALID_ARG: return "GS_ERR_INVALID_ARG";
+    case GS_ERR_UNSUPPORTED: return "GS_ERR_UNSUPPORTED";
+    case GS_ERR_HIP: return "GS_ERR_HIP";
+    case GS_ERR_CAPACITY: return "GS_ERR_CAPACITY";
+    case GS_ERR_NOT_IMPLEMENTED: return "GS_ERR_NOT_IMPLEMENTED";
+    default: return "GS_ERR_UNKNOWN";
+    }
+}
+
+extern "C" int gs_version(void) { return 100; }

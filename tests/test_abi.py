@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI: the library builds, loads, exports every
+symbol the header declares, and rejects invalid arguments before touching
+the GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs.h")
+
+
+@pytest.fixture(scope="module")
+def gslib():
+    import paper_2505_24796_amd as gs
+    if not os.path.exists(gs.LIB_PATH):
+        from paper_2505_24796_amd import build
+        build.build()
+    return gs.lib()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("gs_preprocess", "gs_preprocess_2d", "gs_bin_sort", "gs_bin_sort_workspace_bytes",
+              "gs_rasterize_fwd", "gs_rasterize_beta", "gs_status_string", "gs_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(gslib):
+    import paper_2505_24796_amd as gs
+    out = subprocess.run(["nm", "-D", "--defined-only", gs.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_header_compiles_as_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "gs.h"\nint main(void){gs_camera c; (void)c; return GS_OK;}\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    "-c", str(src), "-o", str(tmp_path / "t.o")], check=True)
+
+
+def test_status_strings(gslib):
+    assert gslib.gs_status_string(0) == b"GS_OK"
+    assert gslib.gs_status_string(4) == b"GS_ERR_CAPACITY"
+    assert gslib.gs_status_string(99) == b"GS_ERR_UNKNOWN"
+    assert gslib.gs_version() >= 100
+
+
+def test_invalid_arguments_rejected_on_host(gslib):
+    import paper_2505_24796_amd as gs
+    v = ctypes.c_void_p
+    cam = gs.make_camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1], 100, 100, 50, 50, 100, 100)
+    # negative P
+    assert gslib.gs_preprocess(-1, v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(16), v(16),
+                               v(16), v(16), v(16), v(16), v(0)) == 1
+    # bad SH degree
+    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), 4, ctypes.byref(cam), v(16), v(16),
+                               v(16), v(16), v(16), v(16), v(0)) == 1
+    # null output
+    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(0), v(16),
+                               v(16), v(16), v(16), v(16), v(0)) == 1
+    # misaligned quaternions (16 B required)
+    assert gslib.gs_preprocess(1, v(16), v(16), v(20), v(16), 3, ctypes.byref(cam), v(16), v(16),
+                               v(16), v(16), v(16), v(16), v(0)) == 1
+    # oversized image
+    assert gslib.gs_preprocess_2d(1, v(16), v(16), 20000, 10, v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_bin_sort_workspace_bytes(10, 100, 0, 10) == 0
+    assert gslib.gs_bin_sort_workspace_bytes(10, 100, 64, 64) > 0
+    # workspace too small -> capacity error
+    assert gslib.gs_bin_sort(10, v(16), v(16), v(16), 64, 64, 100, v(256), 8, v(16), v(16), v(16),
+                             v(0)) == 4
+    # unknown precision
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    args = [64, 64, v(16), v(16), v(16), v(16), v(16), v(16), bg]
+    assert gslib.gs_rasterize_fwd(*args, 9, v(16), v(16), v(16), v(0), v(0)) == 1
+    # null output image
+    assert gslib.gs_rasterize_fwd(*args, 0, v(0), v(16), v(16), v(0), v(0)) == 1
+    # beta dump: tile out of range, FP32 precision not allowed
+    assert gslib.gs_rasterize_beta(64, 64, 16, v(16), v(16), v(16), v(16), v(16), 4, 32, v(16),
+                                   v(0)) == 1
+    assert gslib.gs_rasterize_beta(64, 64, 0, v(16), v(16), v(16), v(16), v(16), 0, 32, v(16),
+                                   v(0)) == 1
+
+
+def test_zero_gaussians_is_noop(gslib):
+    v = ctypes.c_void_p
+    assert gslib.gs_preprocess_2d(0, v(0), v(0), 64, 64, v(0), v(0), v(0), v(0)) == 0
+
+
+def test_oracle_independent_of_product():
+    """The oracle and the product library share no code: no include, import
+    or symbol crosses between them."""
+    orc = open(os.path.join(ROOT, "oracle", "gs_oracle.c")).read()
+    assert "gs.h" not in orc and "csrc" not in orc
+    orc_py = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+    assert "paper_2505_24796_amd" not in orc_py
+    for f in os.listdir(os.path.join(ROOT, "paper_2505_24796_amd", "csrc")):
+        assert "oracle" not in open(os.path.join(ROOT, "paper_2505_24796_amd", "csrc", f)).read()
+    pkg = open(os.path.join(ROOT, "paper_2505_24796_amd", "__init__.py")).read()
+    assert "import oracle" not in pkg and "from oracle" not in pkg
