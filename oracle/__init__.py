@@ -156,9 +156,13 @@ def bin_splats(means2d, radii, depths, W: int, H: int):
 
 
 def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0, 0.0),
-           mode: int = MODE_DEF, delta_c: float = 0.0, delta_t: float = 0.0, tiles=None) -> dict:
+           mode: int = MODE_DEF, delta_c: float = 0.0, delta_t: float = 0.0, tiles=None,
+           delta_r: float = 0.0) -> dict:
     """Algorithm 1 per pixel in FP64.  With ``tiles`` only those tiles are
-    rendered (other pixels are NaN / -1).  Colour is planar (3, H, W)."""
+    rendered (other pixels are NaN / -1).  Colour is planar (3, H, W).
+    A cull decision is flagged as near-threshold when |ln alpha + ln 255| <
+    delta_c + delta_r * (sum of |terms| of q/2); a termination decision when
+    |T(1 - alpha) - 1e-4| < delta_t * 1e-4."""
     rg, idv = np.ascontiguousarray(ranges, np.uint32), np.ascontiguousarray(ids, np.uint32)
     if idv.size == 0:
         idv = np.zeros(1, np.uint32)
@@ -172,7 +176,7 @@ def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0
     if tiles is not None and ntl == 0:
         return out
     lib().orc_render(c_int(W), c_int(H), _p(rg), _p(idv), _p(m), _p(c), _p(o), _p(col), _p(b),
-                     c_int(mode), c_double(delta_c), c_double(delta_t), c_int(ntl),
+                     c_int(mode), c_double(delta_c), c_double(delta_r), c_double(delta_t), c_int(ntl),
                      _p(tl) if ntl else c_void_p(0),
                      _p(out["rgb"]), _p(out["T"]), _p(out["n_contrib"]), _p(out["n_proc"]),
                      _p(out["f_blend"]), _p(out["f_cull"]), _p(out["term"]), _p(out["n_amb"]))
@@ -181,7 +185,7 @@ def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0
 
 def render_alternatives(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, pix_xy,
                         bg=(0.0, 0.0, 0.0), mode: int = MODE_DEF, delta_c: float = 1e-5,
-                        delta_t: float = 1e-3):
+                        delta_t: float = 1e-3, delta_r: float = 0.0):
     """All results reachable by inverting up to the first four near-threshold
     decisions at each listed pixel: returns (rgb (n, 16, 3), T (n, 16))."""
     rg, idv = np.ascontiguousarray(ranges, np.uint32), np.ascontiguousarray(ids, np.uint32)
@@ -195,7 +199,8 @@ def render_alternatives(W: int, H: int, ranges, ids, means2d, conics, opac, rgb,
     if n:
         lib().orc_render_alternatives(c_int(W), c_int(H), _p(rg), _p(idv), _p(m), _p(c), _p(o),
                                       _p(col), _p(b), c_int(mode), c_double(delta_c),
-                                      c_double(delta_t), c_int(n), _p(px), _p(alt_rgb), _p(alt_T))
+                                      c_double(delta_r), c_double(delta_t), c_int(n), _p(px),
+                                      _p(alt_rgb), _p(alt_T))
     return alt_rgb[:n], alt_T[:n]
 
 

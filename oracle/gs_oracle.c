@@ -447,7 +447,7 @@ typedef struct {
     const uint32_t *ranges, *ids;
     const double *means2d, *conics, *opac, *rgb;
     int W, H, mode;
-    double dc, dt;
+    double dc, dr, dt;
 } scene_ref_t;
 
 /* Algorithm 1 for one pixel.  flip_mask: the j-th (j < 4) near-threshold
@@ -466,7 +466,7 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
         uint32_t g = s->ids[k];
         const double *mu = s->means2d + 2 * g, *S = s->conics + 3 * g;
         double o = s->opac[g];
-        double alpha, margin;
+        double alpha, margin, band = s->dc;
         int cull;
         if (s->mode == MODE_DEF) {
             double dx = mu[0] - p[0], dy = mu[1] - p[1];
@@ -474,6 +474,9 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
             alpha = o * exp(-0.5 * q);
             cull = alpha < 1.0 / 255.0;
             margin = (log(o) - 0.5 * q) - cull_ln;        /* distance in ln(alpha) */
+            /* a reduced-precision evaluation errs relative to the size of the
+             * quadratic form's terms, not of q itself */
+            band += s->dr * 0.5 * (fabs(S[0]) * dx * dx + 2.0 * fabs(S[1] * dx * dy) + fabs(S[2]) * dy * dy);
         } else {
             /* EarlyCull (Sec. 4.1): the test on the exponent, here in log2 units */
             double b2 = orc_beta_emulated(s->mode, mu, S, o, p, tc);
@@ -482,7 +485,7 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
             margin = (b2 - cull_ln * LOG2E) / LOG2E;
         }
         if (alpha > 0.99) alpha = 0.99;
-        if (fabs(margin) < s->dc) {
+        if (fabs(margin) < band) {
             ++namb;
             if (nflag < 4 && ((flip_mask >> nflag) & 1u)) cull = !cull;
             ++nflag;
@@ -516,12 +519,12 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
  * out_rgb[3][H][W] with the background composited as C + T*bg. */
 void orc_render(int W, int H, const uint32_t *ranges, const uint32_t *ids,
                 const double *means2d, const double *conics, const double *opac,
-                const double *rgb, const double *bg, int mode, double delta_c, double delta_t,
-                int ntl, const int32_t *tile_list,
+                const double *rgb, const double *bg, int mode, double delta_c, double delta_r,
+                double delta_t, int ntl, const int32_t *tile_list,
                 double *out_rgb, double *out_T, int32_t *n_contrib, int32_t *n_proc,
                 int32_t *f_blend, int32_t *f_cull, int32_t *term, int32_t *n_amb)
 {
-    scene_ref_t s = {ranges, ids, means2d, conics, opac, rgb, W, H, mode, delta_c, delta_t};
+    scene_ref_t s = {ranges, ids, means2d, conics, opac, rgb, W, H, mode, delta_c, delta_r, delta_t};
     int gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
     int nt = ntl > 0 ? ntl : gx * gy;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -554,10 +557,10 @@ void orc_render(int W, int H, const uint32_t *ranges, const uint32_t *ids,
 void orc_render_alternatives(int W, int H, const uint32_t *ranges, const uint32_t *ids,
                              const double *means2d, const double *conics, const double *opac,
                              const double *rgb, const double *bg, int mode, double delta_c,
-                             double delta_t, int npix, const int32_t *pix_xy,
+                             double delta_r, double delta_t, int npix, const int32_t *pix_xy,
                              double *alt_rgb, double *alt_T)
 {
-    scene_ref_t s = {ranges, ids, means2d, conics, opac, rgb, W, H, mode, delta_c, delta_t};
+    scene_ref_t s = {ranges, ids, means2d, conics, opac, rgb, W, H, mode, delta_c, delta_r, delta_t};
 #pragma omp parallel for schedule(dynamic, 4)
     for (int j = 0; j < npix; ++j) {
         for (unsigned m = 0; m < 16; ++m) {

@@ -8,6 +8,7 @@ import oracle
 
 DELTA_C = 1e-5   # |ln alpha + ln 255| below this counts as a near-threshold cull decision
 DELTA_T = 1e-3   # |T(1-a)/1e-4 - 1| below this counts as a near-threshold termination
+DELTA_R = 1e-6   # plus this fraction of the quadratic form's term magnitudes (FP32: ~16 ulp)
 
 
 def dev(a, dtype=None):
@@ -33,7 +34,7 @@ def fp32_check(W, H, ranges, ids, means2d, conics, opac, rgb, gpu_rgb, gpu_T, to
     admissible result (decisions within delta of a threshold may go either
     way).  Returns a stats dict."""
     ref = oracle.render(W, H, ranges, ids, means2d, conics, opac, rgb, bg=bg,
-                        delta_c=DELTA_C, delta_t=DELTA_T, tiles=tiles)
+                        delta_c=DELTA_C, delta_t=DELTA_T, delta_r=DELTA_R, tiles=tiles)
     mask = ~np.isnan(ref["T"])
     err = np.abs(gpu_rgb - ref["rgb"]).max(axis=0)
     errT = np.abs(gpu_T - ref["T"])
@@ -45,7 +46,7 @@ def fp32_check(W, H, ranges, ids, means2d, conics, opac, rgb, gpu_rgb, gpu_T, to
     if len(ys):
         alt, altT = oracle.render_alternatives(W, H, ranges, ids, means2d, conics, opac, rgb,
                                                np.stack([xs, ys], 1), bg=bg, delta_c=DELTA_C,
-                                               delta_t=DELTA_T)
+                                               delta_t=DELTA_T, delta_r=DELTA_R)
         for j, (x, y) in enumerate(zip(xs, ys)):
             e = np.abs(alt[j] - gpu_rgb[:, y, x]).max(axis=1)
             eT = np.abs(altT[j] - gpu_T[y, x])
