@@ -4,14 +4,14 @@
 // Instead of one radix sort of N 64-bit (tile | depth) keys, the stage
 //   1. sorts the P Gaussians by depth (stable LSD radix, 4 x 8-bit passes on
 //      an order-preserving image of the float bits; ties keep id order),
-//   2. scans the per-Gaussian tile counts in that order and emits the splats
-//      (tile, id) in depth order,
-//   3. sorts the N splats by tile only (stable LSD radix, ceil(bits/8)
-//      passes over ceil(log2 ntiles) bits), which keeps depth order within a
-//      tile, and
+//   2. scans the per-Gaussian tile counts in that order and expands the
+//      splats (tile, id) in depth order, load-balanced over fixed windows of
+//      output slots,
+//   3. sorts the N splats by tile only (stable LSD radix over
+//      ceil(log2 ntiles) bits), which keeps depth order within a tile, and
 //   4. finds each tile's [start, end).
-// This touches every splat 2 x (8 + 8) bytes per tile pass instead of
-// 6 passes x 24 bytes, and every stage is bound by HBM bandwidth.
+// Every splat moves 2 x (4 + 4) bytes per tile pass instead of 6 passes of
+// 24 bytes; all stages are HBM-bandwidth kernels.
 #include "common.h"
 
 namespace {
@@ -24,6 +24,8 @@ constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int WAVES = SORT_THREADS / 64;
 constexpr int WAVE_ITEMS = SORT_TILE / WAVES;          // 1024 per wave
 constexpr int WAVE_CHUNKS = WAVE_ITEMS / 64;           // 16 chunks of 64
+constexpr int EMIT_ITEMS = 8;
+constexpr int EMIT_TILE = SORT_THREADS * EMIT_ITEMS;   // output slots per block
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -41,29 +43,28 @@ struct Count {
 };
 
 // ---------------------------------------------------------------------------
-// Device-wide exclusive scan of u32 values (u64 running totals so that an
-// overflowing splat count is detected instead of wrapping).
+// Block-level scans
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+template <typename T> __device__ __forceinline__ T wave_incl_scan(T v) {
     int lane = threadIdx.x & 63;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        uint64_t o = __shfl_up(v, d, 64);
+        T o = __shfl_up(v, d, 64);
         if (lane >= d) v += o;
     }
     return v;
 }
 
 // Block-wide exclusive scan of one value per thread; returns the block total.
-__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t &excl, uint64_t *lds4) {
+// `lds` needs blockDim.x / 64 entries.
+template <typename T> __device__ __forceinline__ T block_excl_scan(T v, T &excl, T *lds) {
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = wave_incl_scan_u64(v);
-    if (lane == 63) lds4[w] = inc;
+    T inc = wave_incl_scan(v);
+    if (lane == 63) lds[w] = inc;
     __syncthreads();
-    uint64_t off = 0, tot = 0;
-#pragma unroll
+    T off = 0, tot = 0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-        uint64_t s = lds4[i];
+        T s = lds[i];
         if (i < w) off += s;
         tot += s;
     }
@@ -72,76 +73,78 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t &excl, 
     return tot;
 }
 
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of the per-Gaussian splat counts (u64 running
+// totals so that an overflowing count is detected instead of wrapping).  The
+// down-sweep also records, for every window of EMIT_TILE output slots, the
+// Gaussian that owns the window's first slot.
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SORT_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
                                                               uint32_t n,
                                                               uint64_t *__restrict__ part) {
-    __shared__ uint64_t lds4[WAVES];
+    __shared__ uint64_t lds[WAVES];
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k)
         if (base + k < n) s += in[base + k];
     uint64_t ex;
-    uint64_t tot = block_excl_scan(s, ex, lds4);
+    uint64_t tot = block_excl_scan<uint64_t>(s, ex, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // Single block: exclusive scan of the block partials in place; writes the
-// grand total (saturated to u32) to *total when total is non-null.
+// grand total (saturated to u32) to *total.
 __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ part, uint32_t nparts,
                                                         uint32_t *__restrict__ total) {
-    __shared__ uint64_t lds16[16];
+    __shared__ uint64_t lds[16];
     uint64_t carry = 0;
     for (uint32_t base = 0; base < nparts; base += 1024) {
         uint32_t i = base + threadIdx.x;
         uint64_t v = i < nparts ? part[i] : 0;
         uint64_t ex;
-        uint64_t tot = block_excl_scan(v, ex, lds16);
+        uint64_t tot = block_excl_scan<uint64_t>(v, ex, lds);
         if (i < nparts) part[i] = carry + ex;
         carry += tot;
     }
-    if (total && threadIdx.x == 0) *total = carry > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)carry;
+    if (threadIdx.x == 0) *total = carry > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)carry;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *in, uint32_t *out,
-                                                            uint32_t n,
-                                                            const uint64_t *__restrict__ part) {
-    __shared__ uint64_t lds4[WAVES];
+__global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__restrict__ cnt,
+                                                            uint32_t *__restrict__ offs, uint32_t n,
+                                                            const uint64_t *__restrict__ part,
+                                                            uint32_t *__restrict__ win_start,
+                                                            uint32_t nwin) {
+    __shared__ uint64_t lds[WAVES];
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
     uint32_t v[SORT_ITEMS];
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        v[k] = base + k < n ? in[base + k] : 0u;
+        v[k] = base + k < n ? cnt[base + k] : 0u;
         s += v[k];
     }
     uint64_t ex;
-    block_excl_scan(s, ex, lds4);
+    block_excl_scan<uint64_t>(s, ex, lds);
     uint64_t run = part[blockIdx.x] + ex;
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        if (base + k < n) out[base + k] = (uint32_t)run;
+        if (base + k < n) {
+            offs[base + k] = (uint32_t)run;
+            // windows whose first slot falls inside [run, run + v)
+            if (v[k] > 0) {
+                uint64_t w0 = (run + EMIT_TILE - 1) / EMIT_TILE;
+                uint64_t w1 = (run + v[k] - 1) / EMIT_TILE;
+                for (uint64_t w = w0; w <= w1 && w < nwin; ++w) win_start[w] = (uint32_t)(base + k);
+            }
+        }
         run += v[k];
     }
 }
 
-struct ScanPlan {
-    uint32_t n, blocks;
-};
-
-gs_status device_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint64_t *part,
-                      uint32_t *total, hipStream_t s) {
-    uint32_t blocks = (n + SORT_TILE - 1) / SORT_TILE;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(blocks), dim3(SORT_THREADS), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, blocks, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(blocks), dim3(SORT_THREADS), 0, s, in, out, n,
-                       (const uint64_t *)part);
-    return gs::launch_status();
-}
-
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (8-bit digit) of u32 keys with u32 values.
+// Stable LSD radix sort pass (8-bit digit) of u32 keys with u32 values:
+// per-block digit histograms -> per-digit scan over blocks -> scatter.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              Count cnt, int shift,
@@ -163,19 +166,47 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// One block per digit: exclusive scan of that digit's counts over blocks, in
+// place; the digit total goes to totals[d].
+__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict__ hist,
+                                                            uint32_t nblocks,
+                                                            uint32_t *__restrict__ totals) {
+    __shared__ uint32_t lds[WAVES];
+    uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += SORT_THREADS) {
+        uint32_t i = b0 + threadIdx.x;
+        uint32_t v = i < nblocks ? row[i] : 0u;
+        uint32_t ex;
+        uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
+        if (i < nblocks) row[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
-    uint32_t nblocks) {
+    const uint32_t *__restrict__ totals, uint32_t nblocks) {
     __shared__ uint32_t wcnt[WAVES][RADIX];
-    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t gbase[RADIX];   // global position of this block's first key of digit d
+    __shared__ uint32_t lstart[RADIX];  // local position of this block's first key of digit d
+    __shared__ uint32_t skey[SORT_TILE];
+    __shared__ uint32_t sval[SORT_TILE];
+    __shared__ uint32_t lds_scan[WAVES];
     uint32_t n = cnt.get();
     size_t base = (size_t)blockIdx.x * SORT_TILE;
     if (base >= n) return;  // whole block idle: uniform exit
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
-    gbase[threadIdx.x] = hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
+    {
+        // exclusive scan of the global digit totals -> digit base
+        uint32_t t = totals[threadIdx.x], ex;
+        block_excl_scan<uint32_t>(t, ex, lds_scan);
+        gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
+    }
     __syncthreads();
 
     uint32_t key[WAVE_CHUNKS], val[WAVE_CHUNKS], pos[WAVE_CHUNKS];
@@ -186,6 +217,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         bool ok = i < n;
         key[c] = ok ? kin[i] : 0u;
         val[c] = ok ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < WAVE_CHUNKS; ++c) {
+        size_t i = wbase + (size_t)c * 64 + lane;
+        bool ok = i < n;
         uint32_t d = (key[c] >> shift) & (RADIX - 1);
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -201,6 +237,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     {
+        // per digit: prefix over waves, and the block's digit-major local start
         uint32_t d = threadIdx.x, off = 0;
 #pragma unroll
         for (int i = 0; i < WAVES; ++i) {
@@ -208,17 +245,31 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
             wcnt[i][d] = off;
             off += t;
         }
+        uint32_t ex;
+        block_excl_scan<uint32_t>(off, ex, lds_scan);
+        lstart[d] = ex;
     }
     __syncthreads();
+    // stage in LDS in (digit, original order) order ...
 #pragma unroll
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n) {
             uint32_t d = (key[c] >> shift) & (RADIX - 1);
-            uint32_t dst = gbase[d] + wcnt[w][d] + pos[c];
-            kout[dst] = key[c];
-            vout[dst] = val[c];
+            uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
+            skey[lp] = key[c];
+            sval[lp] = val[c];
         }
+    }
+    __syncthreads();
+    // ... and write runs of equal digits to consecutive global addresses
+    uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
+    for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
+        uint32_t k = skey[lp];
+        uint32_t d = (k >> shift) & (RADIX - 1);
+        uint32_t dst = gbase[d] + (lp - lstart[d]);
+        kout[dst] = k;
+        vout[dst] = sval[lp];
     }
 }
 
@@ -228,7 +279,7 @@ struct SortBufs {
 
 // Sorts on bits [0, bits) with ceil(bits/8) passes; returns the index of the
 // buffer pair holding the result.
-int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint64_t *part,
+int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
                hipStream_t s) {
     uint32_t nblocks = (max_n + SORT_TILE - 1) / SORT_TILE;
     if (nblocks == 0) nblocks = 1;
@@ -236,9 +287,9 @@ int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, 
     for (int shift = 0; shift < bits; shift += RADIX_BITS) {
         hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], cnt,
                            shift, hist, nblocks);
-        device_scan(hist, hist, RADIX * nblocks, part, nullptr, s);
+        hipLaunchKernelGGL(k_hist_rows, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
-                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, nblocks);
+                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals, nblocks);
         cur ^= 1;
     }
     return cur;
@@ -253,81 +304,123 @@ __device__ __forceinline__ uint32_t depth_key(float d) {
     return (f & 0x80000000u) ? ~f : (f | 0x80000000u);
 }
 
-__device__ __forceinline__ int splat_count(const float2 *means2d, const int *radii,
-                                           const float *depths, int i, int W, int H, int gx,
-                                           int &tx0, int &tx1, int &ty0, int &ty1) {
-    float d = depths[i];
-    if (!isfinite(d)) return 0;
-    float2 m = means2d[i];
-    return gs::tile_rect(m.x, m.y, radii[i], W, H, gx, tx0, tx1, ty0, ty1);
-}
-
+// Depth keys and the packed tile rectangle of every Gaussian (coalesced);
+// also clears the tile ranges.
 __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restrict__ means2d,
                                                     const int *__restrict__ radii,
                                                     const float *__restrict__ depths, int W, int H,
                                                     int gx, uint32_t *__restrict__ keys,
-                                                    uint32_t *__restrict__ ids) {
+                                                    uint32_t *__restrict__ ids,
+                                                    uint2 *__restrict__ rects,
+                                                    uint32_t *__restrict__ ranges, int n2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n2) ranges[i] = 0u;
     if (i >= P) return;
-    int a, b, c, d;
-    int n = splat_count(means2d, radii, depths, i, W, H, gx, a, b, c, d);
-    keys[i] = n > 0 ? depth_key(depths[i]) : 0xFFFFFFFFu;
+    float d = depths[i];
+    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+    int n = 0;
+    if (isfinite(d)) {
+        float2 m = means2d[i];
+        n = gs::tile_rect(m.x, m.y, radii[i], W, H, gx, tx0, tx1, ty0, ty1);
+    }
+    keys[i] = n > 0 ? depth_key(d) : 0xFFFFFFFFu;
     ids[i] = (uint32_t)i;
+    rects[i] = n > 0 ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
+                                  (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16))
+                     : make_uint2(0u, 0u);
 }
 
 __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restrict__ order,
-                                                const float2 *__restrict__ means2d,
-                                                const int *__restrict__ radii,
-                                                const float *__restrict__ depths, int W, int H,
-                                                int gx, uint32_t *__restrict__ cnt) {
+                                                const uint2 *__restrict__ rects,
+                                                uint2 *__restrict__ rects_sorted,
+                                                uint32_t *__restrict__ cnt) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= P) return;
-    int a, b, c, d;
-    cnt[j] = (uint32_t)splat_count(means2d, radii, depths, (int)order[j], W, H, gx, a, b, c, d);
+    uint2 r = rects[order[j]];
+    rects_sorted[j] = r;
+    cnt[j] = (r.y & 0xFFFFu) * (r.y >> 16);
 }
 
-__global__ __launch_bounds__(256) void k_emit(int P, const uint32_t *__restrict__ order,
-                                              const uint32_t *__restrict__ offs,
-                                              const float2 *__restrict__ means2d,
-                                              const int *__restrict__ radii,
-                                              const float *__restrict__ depths, int W, int H,
-                                              int gx, const uint32_t *__restrict__ n_splats,
-                                              uint32_t cap, uint32_t *__restrict__ tkey,
-                                              uint32_t *__restrict__ tid) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P) return;
-    if (*n_splats > cap) return;  // overflow: nothing is written
-    uint32_t g = order[j];
-    int tx0, tx1, ty0, ty1;
-    int n = splat_count(means2d, radii, depths, (int)g, W, H, gx, tx0, tx1, ty0, ty1);
-    if (n == 0) return;
-    uint32_t o = offs[j];
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            tkey[o] = (uint32_t)(ty * gx + tx);
-            tid[o] = g;
-            ++o;
+// Expands the splats of output window blockIdx.x: slot o belongs to the
+// Gaussian j with offs[j] <= o < offs[j] + cnt[j] (searched in LDS among the
+// window's Gaussians); its local index picks the tile in row-major order of
+// the Gaussian's rectangle.
+__global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
+                                                       const uint32_t *__restrict__ offs,
+                                                       const uint2 *__restrict__ rects_sorted,
+                                                       const uint32_t *__restrict__ win_start,
+                                                       uint32_t nwin, int gx,
+                                                       const uint32_t *__restrict__ n_splats,
+                                                       uint32_t cap, uint32_t *__restrict__ tkey,
+                                                       uint32_t *__restrict__ tid) {
+    __shared__ uint32_t s_off[EMIT_TILE + 1];
+    __shared__ uint2 s_rect[EMIT_TILE + 1];
+    __shared__ uint32_t s_id[EMIT_TILE + 1];
+    uint32_t N = *n_splats;
+    if (N > cap) return;  // overflow: nothing is written
+    uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
+    if (o0 >= N) return;
+    uint32_t j0 = win_start[blockIdx.x];
+    uint32_t o_last = min(o0 + (uint32_t)EMIT_TILE, N) - 1u;
+    // the Gaussian owning o_last is at most EMIT_TILE entries after j0 (every
+    // Gaussian in between owns at least one slot of this window)
+    uint32_t m = min((uint32_t)EMIT_TILE + 1u, (uint32_t)P - j0);
+    for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS) {
+        s_off[k] = offs[j0 + k];
+        s_rect[k] = rects_sorted[j0 + k];
+        s_id[k] = order[j0 + k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < EMIT_ITEMS; ++it) {
+        uint32_t o = o0 + (uint32_t)it * SORT_THREADS + threadIdx.x;
+        if (o > o_last) break;
+        // last k with s_off[k] <= o and a non-empty rectangle
+        uint32_t lo = 0, hi = m;  // invariant: s_off[lo] <= o, answer in [lo, hi)
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= o) lo = mid;
+            else hi = mid;
         }
+        // zero-count Gaussians share their successor's offset; step back to
+        // the one that owns slot o
+        while (lo > 0 && (s_rect[lo].y == 0u || s_off[lo] > o)) --lo;
+        uint2 r = s_rect[lo];
+        uint32_t w = max(r.y & 0xFFFFu, 1u);
+        uint32_t l = o - s_off[lo];
+        uint32_t row = l / w, col = l - row * w;
+        uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
+        tkey[o] = ty * (uint32_t)gx + tx;
+        tid[o] = s_id[lo];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_ranges_zero(uint32_t *__restrict__ ranges, int n2) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n2) ranges[i] = 0u;
-}
-
+// Tile ranges from the tile-sorted keys: 4 keys per thread.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tkey, Count cnt,
-                                                uint32_t *__restrict__ ranges) {
+                                                uint32_t ntiles, uint32_t *__restrict__ ranges) {
     uint32_t n = cnt.get();
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t t = tkey[i];
-    if (i == 0 || tkey[i - 1] != t) ranges[2 * t] = i;
-    if (i == n - 1 || tkey[i + 1] != t) ranges[2 * t + 1] = i + 1;
+    uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= n) return;
+    uint32_t k[6];
+    k[0] = i0 > 0 ? tkey[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) k[j + 1] = (i0 + j < n) ? tkey[i0 + j] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t i = i0 + j;
+        if (i >= n) break;
+        uint32_t t = k[j + 1];
+        if (t >= ntiles) continue;  // cannot happen for keys built here; keeps writes in bounds
+        if (k[j] != t) ranges[2 * t] = i;
+        if (k[j + 2] != t) ranges[2 * t + 1] = i + 1;
+    }
 }
 
 // Workspace carve-up (every region 256-byte aligned).
 struct Layout {
-    size_t dkey0, dkey1, did0, did1, cnt, tkey0, tkey1, tid, hist, part, total;
+    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, tkey0, tkey1, tid, hist,
+        totals, part, win, total;
+    uint32_t nwin;
 };
 
 Layout layout(uint32_t P, uint32_t cap) {
@@ -340,18 +433,22 @@ Layout layout(uint32_t P, uint32_t cap) {
     };
     uint32_t maxn = P > cap ? P : cap;
     uint32_t nblocks = (maxn + SORT_TILE - 1) / SORT_TILE + 1;
-    size_t hist_n = (size_t)RADIX * nblocks;
-    size_t parts = (hist_n + SORT_TILE - 1) / SORT_TILE + (P + SORT_TILE - 1) / SORT_TILE + 2;
+    L.nwin = (cap + EMIT_TILE - 1) / EMIT_TILE + 1;
     L.dkey0 = take(4ull * P);
     L.dkey1 = take(4ull * P);
     L.did0 = take(4ull * P);
     L.did1 = take(4ull * P);
+    L.rects = take(8ull * P);
+    L.rects_sorted = take(8ull * P);
     L.cnt = take(4ull * P);
+    L.offs = take(4ull * P);
     L.tkey0 = take(4ull * cap);
     L.tkey1 = take(4ull * cap);
     L.tid = take(4ull * cap);
-    L.hist = take(4ull * hist_n);
-    L.part = take(8ull * parts);
+    L.hist = take(4ull * RADIX * nblocks);
+    L.totals = take(4ull * RADIX);
+    L.part = take(8ull * ((P + SORT_TILE - 1) / SORT_TILE + 2));
+    L.win = take(4ull * L.nwin);
     L.total = off;
     return L;
 }
@@ -367,6 +464,7 @@ int ceil_log2(uint32_t x) {
 extern "C" size_t gs_bin_sort_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
                                               int32_t height) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
+    if (capacity >= 0x80000000u) return 0;
     return layout((uint32_t)P, capacity).total;
 }
 
@@ -394,25 +492,34 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     int gx = gs::grid_x(width), gy = gs::grid_y(height);
     int ntiles = gx * gy;
 
-    hipLaunchKernelGGL(k_ranges_zero, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, tile_ranges,
-                       2 * ntiles);
     if (P == 0) {
-        // N = 0
-        hipLaunchKernelGGL(k_ranges_zero, dim3(1), dim3(256), 0, s, d_num_splats, 1);
+        hipLaunchKernelGGL(k_depth_keys, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, 0,
+                           (const float2 *)nullptr, (const int *)nullptr, (const float *)nullptr,
+                           width, height, gx, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                           (uint2 *)nullptr, tile_ranges, 2 * ntiles);
+        hipMemsetAsync(d_num_splats, 0, 4, s);
         return gs::launch_status();
     }
     const float2 *m2 = (const float2 *)means2d;
-    int pblocks = (P + 255) / 256;
-    // 1. depth order of the Gaussians
-    hipLaunchKernelGGL(k_depth_keys, dim3(pblocks), dim3(256), 0, s, P, m2, radii, depths, width,
-                       height, gx, U(L.dkey0), U(L.did0));
+    int nthr = P > 2 * ntiles ? P : 2 * ntiles;
+    // 1. depth keys, rectangles, cleared ranges; depth order of the Gaussians
+    hipLaunchKernelGGL(k_depth_keys, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2, radii,
+                       depths, width, height, gx, U(L.dkey0), U(L.did0), (uint2 *)(ws + L.rects),
+                       tile_ranges, 2 * ntiles);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
-    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32, U(L.hist), part, s);
+    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32, U(L.hist),
+                          U(L.totals), s);
     const uint32_t *order = db.v[dcur];
-    // 2. counts in depth order, scan, emit
-    hipLaunchKernelGGL(k_counts, dim3(pblocks), dim3(256), 0, s, P, order, m2, radii, depths, width,
-                       height, gx, U(L.cnt));
-    device_scan(U(L.cnt), U(L.cnt), (uint32_t)P, part, d_num_splats, s);
+    // 2. counts in depth order, scan (+ window owners), expansion
+    int pblocks = (P + 255) / 256;
+    hipLaunchKernelGGL(k_counts, dim3(pblocks), dim3(256), 0, s, P, order,
+                       (const uint2 *)(ws + L.rects), (uint2 *)(ws + L.rects_sorted), U(L.cnt));
+    uint32_t sblocks = (P + SORT_TILE - 1) / SORT_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt),
+                       (uint32_t)P, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, sblocks, d_num_splats);
+    hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
+                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin);
     int tbits = ceil_log2((uint32_t)ntiles);
     if (tbits == 0) tbits = 1;
     int npass = (tbits + RADIX_BITS - 1) / RADIX_BITS;
@@ -420,18 +527,19 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     // so the sorted ids land in sorted_ids.
     uint32_t *emit_ids = (npass % 2 == 0) ? sorted_ids : U(L.tid);
     uint32_t *other_ids = (npass % 2 == 0) ? U(L.tid) : sorted_ids;
-    if (capacity == 0) {
-        emit_ids = other_ids = U(L.tid);  // nothing fits; kernels see N > 0 = overflow
-    }
-    hipLaunchKernelGGL(k_emit, dim3(pblocks), dim3(256), 0, s, P, order, U(L.cnt), m2, radii,
-                       depths, width, height, gx, d_num_splats, capacity, U(L.tkey0), emit_ids);
+    if (capacity == 0) emit_ids = other_ids = U(L.tid);  // nothing fits
+    uint32_t eblocks = (capacity + EMIT_TILE - 1) / EMIT_TILE;
+    if (eblocks > 0)
+        hipLaunchKernelGGL(k_emit, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order, U(L.offs),
+                           (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, gx,
+                           d_num_splats, capacity, U(L.tkey0), emit_ids);
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     Count nc{0u, d_num_splats, capacity};
-    int tcur = radix_sort(tb, nc, capacity, tbits, U(L.hist), part, s);
+    int tcur = radix_sort(tb, nc, capacity, tbits, U(L.hist), U(L.totals), s);
     // 4. ranges
-    uint32_t rblocks = (capacity + 255) / 256;
-    if (rblocks == 0) rblocks = 1;
-    hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, tile_ranges);
+    uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
+    hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
+                       tile_ranges);
     return gs::launch_status();
 }

@@ -346,19 +346,57 @@ __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bo
 
 template <int VAR>
 __device__ __forceinline__ void stage_splat(uint8_t *stage, int j, const SplatRegs &s, float ox,
-                                            float oy) {
+                                            float oy, uint32_t list_pos) {
     int sub = j / SUB, row = row_of_splat(j % SUB);
     uint8_t *row1 = stage + sub * SUB * VarTraits<VAR>::ROW1 + row * VarTraits<VAR>::ROW1;
     uint8_t *row2 = stage + Stage<VAR>::A1 + sub * SUB * VarTraits<VAR>::ROW2 + row * VarTraits<VAR>::ROW2;
     build_row<VAR>(s.valid, s.mu, s.s11, s.s12, s.s22, s.o, ox, oy, row1, row2);
     float4 *rgb = (float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
-    rgb[j] = make_float4(s.r, s.g, s.b, 0.f);
+    rgb[j] = make_float4(s.r, s.g, s.b, __uint_as_float(list_pos));
+}
+
+// Can the splat reach the 1/255 threshold anywhere in the pixel box
+// [x0, x0 + 15] x [y0, y0 + 15]?  Exact minimum of the convex form
+// q/2 = 1/2 d^T S d over the box (zero if the centre is inside, otherwise the
+// smallest of the four edge minima, each a clamped 1D minimisation), compared
+// with ln o + ln 255 with a margin that covers FP32 rounding of the bound.
+// A splat that fails the test is culled at every pixel of the tile, so
+// dropping it changes no output of the exact computation.
+__device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y0) {
+    if (!s.valid) return false;
+    const float x1 = x0 + (GS_TILE - 1), y1 = y0 + (GS_TILE - 1);
+    const float a = s.s11, b = s.s12, c = s.s22;
+    const float mx = s.mu.x, my = s.mu.y;
+    float fmin = 0.0f, fabs_terms = 0.0f;
+    if (!(mx >= x0 && mx <= x1 && my >= y0 && my <= y1)) {
+        fmin = __builtin_inff();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float dx, dy;
+            if (e < 2) {
+                dx = (e == 0 ? x0 : x1) - mx;
+                dy = fminf(fmaxf(-b * dx / c, y0 - my), y1 - my);
+            } else {
+                dy = (e == 2 ? y0 : y1) - my;
+                dx = fminf(fmaxf(-b * dy / a, x0 - mx), x1 - mx);
+            }
+            float t0 = a * dx * dx, t1 = 2.0f * b * dx * dy, t2 = c * dy * dy;
+            float f = 0.5f * (t0 + t1 + t2);
+            if (f < fmin) {
+                fmin = f;
+                fabs_terms = 0.5f * (fabsf(t0) + fabsf(t1) + fabsf(t2));
+            }
+        }
+    }
+    float margin = 1e-3f * (1.0f + fmin) + 1e-5f * fabs_terms;
+    return __logf(s.o) - fmin >= CULL_LN - margin;
 }
 
 template <int VAR, bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][Stage<VAR>::BYTES];
-    __shared__ int s_flags[2][4];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR>::BYTES];
+    __shared__ int s_wcnt[4];
+    __shared__ int s_wdone[4];
     int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
     if (tile < 0) return;
     const int tx = tile % a.gx, ty = tile / a.gx;
@@ -368,14 +406,15 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
     // frame origin: the tile centre (G2L) or the image origin
     const float ox = VarTraits<VAR>::LOCAL ? tx * GS_TILE + 7.5f : 0.0f;
     const float oy = VarTraits<VAR>::LOCAL ? ty * GS_TILE + 7.5f : 0.0f;
+    const float bx0 = (float)(tx * GS_TILE), by0 = (float)(ty * GS_TILE);
     // operand B: column j = lane%32 of group G is pixel (qx + j%8, qy + 4G + j/8)
     UOperand u0, u1;
     {
         int j = lane & 31, slice = lane >> 5;
         float bx = (float)(tx * GS_TILE + qx + (j & 7)) - ox;
-        float by0 = (float)(ty * GS_TILE + qy + (j >> 3)) - oy;
-        u0 = make_u<VAR>(bx, by0, slice);
-        u1 = make_u<VAR>(bx, by0 + 4.0f, slice);
+        float by = (float)(ty * GS_TILE + qy + (j >> 3)) - oy;
+        u0 = make_u<VAR>(bx, by, slice);
+        u1 = make_u<VAR>(bx, by + 4.0f, slice);
     }
     bool done = !(px < a.W && py < a.H);
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
@@ -393,29 +432,45 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
     uint32_t id_next = k1 < end ? a.ids[k1] : 0u;
 
     for (uint32_t b = 0; b < nbatch; ++b) {
-        const int buf = b & 1;
-        uint8_t *stage = lds[buf];
-        stage_splat<VAR>(stage, threadIdx.x, cur, ox, oy);
+        // 1. which splats of the batch can contribute to this tile at all
+        // (counting mode keeps every splat so culled fragments are counted
+        // per pixel in list order)
+        const bool keep = COUNT ? cur.valid : tile_alive(cur, bx0, by0);
+        const uint64_t kmask = __ballot(keep);
+        const bool wave_done = __ballot(!done) == 0ull;
+        if (lane == 0) {
+            s_wcnt[wave] = __popcll(kmask);
+            s_wdone[wave] = wave_done;
+        }
+        __syncthreads();  // (A) also: every wave has finished the previous batch
+        if (s_wdone[0] & s_wdone[1] & s_wdone[2] & s_wdone[3]) break;
+        int wofs = 0, total = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int c = s_wcnt[i];
+            wofs += i < wave ? c : 0;
+            total += c;
+        }
+        // 2. compacted staging of the kept splats (depth order preserved)
+        if (keep)
+            stage_splat<VAR>(stage, wofs + (int)gs::lanes_below(kmask), cur, ox, oy,
+                             b * BATCH + threadIdx.x);
         {
             uint32_t kn = start + (b + 1) * BATCH + threadIdx.x;
             cur = gather(a, id_next, kn < end);
             uint32_t kn2 = kn + BATCH;
             id_next = kn2 < end ? a.ids[kn2] : 0u;
         }
-        bool wave_done = __ballot(!done) == 0ull;
-        if (lane == 0) s_flags[buf][wave] = wave_done;
-        __syncthreads();
-        if (s_flags[buf][0] & s_flags[buf][1] & s_flags[buf][2] & s_flags[buf][3]) break;
-        if (wave_done) continue;
-        const uint32_t bcount = min((uint32_t)BATCH, n - b * BATCH);
-        const uint32_t nsub = (bcount + SUB - 1) / SUB;
+        __syncthreads();  // (B) staging visible
+        if (wave_done || total == 0) continue;
+        const uint32_t nsub = ((uint32_t)total + SUB - 1) / SUB;
         const float4 *rgbs = (const float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
         for (uint32_t sidx = 0; sidx < nsub; ++sidx) {
             float lo[16], hi[16];
             exponents<VAR>(stage + sidx * SUB * VarTraits<VAR>::ROW1,
                            stage + Stage<VAR>::A1 + sidx * SUB * VarTraits<VAR>::ROW2, u0, u1, lane,
                            lo, hi);
-            const uint32_t scount = min((uint32_t)SUB, bcount - sidx * SUB);
+            const uint32_t scount = min((uint32_t)SUB, (uint32_t)total - sidx * SUB);
             uint32_t valid = scount >= 32 ? 0xFFFFFFFFu : ((1u << scount) - 1u);
             float thr = done ? __builtin_inff() : CULL_LOG2;
             uint32_t alive = 0;
@@ -429,7 +484,6 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
                 }
                 alive &= valid;
             }
-            const uint32_t base = b * BATCH + sidx * SUB;
 #pragma unroll
             for (int g = 0; g < 32; ++g) {
                 if (alive & (1u << g)) {
@@ -449,7 +503,7 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
                             C1 = fmaf(col.y, w, C1);
                             C2 = fmaf(col.z, w, C2);
                             T = test;
-                            last = base + (uint32_t)g + 1u;
+                            last = __float_as_uint(col.w) + 1u;
                             if (COUNT) ++nb;
                         }
                     }
@@ -487,7 +541,7 @@ __global__ __launch_bounds__(256) void k_beta_dump(RasterArgs a, int tile, int c
         bool valid = (uint32_t)(b0 + threadIdx.x) < n;
         uint32_t id = valid ? a.ids[k] : 0u;
         __syncthreads();
-        stage_splat<VAR>(stage, threadIdx.x, gather(a, id, valid), ox, oy);
+        stage_splat<VAR>(stage, threadIdx.x, gather(a, id, valid), ox, oy, b0 + threadIdx.x);
         __syncthreads();
         for (int sidx = 0; sidx < BATCH / SUB && b0 + sidx * SUB < count; ++sidx) {
             float lo[16], hi[16];
