@@ -114,8 +114,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
                                                             uint32_t *__restrict__ offs, uint32_t n,
                                                             const uint64_t *__restrict__ part,
                                                             uint32_t *__restrict__ win_start,
-                                                            uint32_t nwin) {
+                                                            uint32_t nwin,
+                                                            const uint32_t *__restrict__ total) {
     __shared__ uint64_t lds[WAVES];
+    const uint64_t N = *total;
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
     uint32_t v[SORT_ITEMS];
     uint64_t s = 0;
@@ -136,6 +138,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
                 uint64_t w0 = (run + EMIT_TILE - 1) / EMIT_TILE;
                 uint64_t w1 = (run + v[k] - 1) / EMIT_TILE;
                 for (uint64_t w = w0; w <= w1 && w < nwin; ++w) win_start[w] = (uint32_t)(base + k);
+                // the owner of the last slot closes the last window
+                uint64_t wl = (N + EMIT_TILE - 1) / EMIT_TILE;
+                if (run + v[k] == N && wl < nwin) win_start[wl] = (uint32_t)(base + k);
             }
         }
         run += v[k];
@@ -341,10 +346,13 @@ __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restric
     cnt[j] = (r.y & 0xFFFFu) * (r.y >> 16);
 }
 
-// Expands the splats of output window blockIdx.x: slot o belongs to the
-// Gaussian j with offs[j] <= o < offs[j] + cnt[j] (searched in LDS among the
-// window's Gaussians); its local index picks the tile in row-major order of
-// the Gaussian's rectangle.
+// Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
+// slots).  The window's Gaussians are j0 = owner of its first slot up to
+// j1 = owner of the next window's first slot (or of the last slot); their
+// offsets and rectangles are staged in LDS.  Each thread locates the owner
+// of its first of EMIT_ITEMS consecutive slots by binary search and walks
+// the rectangle(s) from there in row-major order; results are staged in LDS
+// and written out coalesced.
 __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ offs,
                                                        const uint2 *__restrict__ rects_sorted,
@@ -356,42 +364,61 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
     __shared__ uint32_t s_off[EMIT_TILE + 1];
     __shared__ uint2 s_rect[EMIT_TILE + 1];
     __shared__ uint32_t s_id[EMIT_TILE + 1];
+    __shared__ uint32_t s_tk[EMIT_TILE];
+    __shared__ uint32_t s_tg[EMIT_TILE];
     uint32_t N = *n_splats;
     if (N > cap) return;  // overflow: nothing is written
     uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
-    if (o0 >= N) return;
+    if (o0 >= N || blockIdx.x + 1 >= nwin) return;
+    uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
     uint32_t j0 = win_start[blockIdx.x];
-    uint32_t o_last = min(o0 + (uint32_t)EMIT_TILE, N) - 1u;
-    // the Gaussian owning o_last is at most EMIT_TILE entries after j0 (every
-    // Gaussian in between owns at least one slot of this window)
-    uint32_t m = min((uint32_t)EMIT_TILE + 1u, (uint32_t)P - j0);
+    uint32_t j1 = win_start[blockIdx.x + 1];
+    if (j0 >= (uint32_t)P) return;  // cannot happen when the scan ran; keeps reads in bounds
+    // every Gaussian between j0 and j1 owns at least one slot of the window
+    uint32_t m = (j1 >= j0 ? j1 - j0 : 0u) + 1u;
+    m = min(m, (uint32_t)EMIT_TILE + 1u);
+    m = min(m, (uint32_t)P - min(j0, (uint32_t)P - 1u));
     for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS) {
         s_off[k] = offs[j0 + k];
         s_rect[k] = rects_sorted[j0 + k];
         s_id[k] = order[j0 + k];
     }
     __syncthreads();
-#pragma unroll
-    for (int it = 0; it < EMIT_ITEMS; ++it) {
-        uint32_t o = o0 + (uint32_t)it * SORT_THREADS + threadIdx.x;
-        if (o > o_last) break;
-        // last k with s_off[k] <= o and a non-empty rectangle
-        uint32_t lo = 0, hi = m;  // invariant: s_off[lo] <= o, answer in [lo, hi)
+    uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
+    if (s0 < oend) {
+        uint32_t lo = 0, hi = m;  // invariant: s_off[lo] <= s0
         while (hi - lo > 1) {
             uint32_t mid = (lo + hi) >> 1;
-            if (s_off[mid] <= o) lo = mid;
+            if (s_off[mid] <= s0) lo = mid;
             else hi = mid;
         }
-        // zero-count Gaussians share their successor's offset; step back to
-        // the one that owns slot o
-        while (lo > 0 && (s_rect[lo].y == 0u || s_off[lo] > o)) --lo;
-        uint2 r = s_rect[lo];
-        uint32_t w = max(r.y & 0xFFFFu, 1u);
-        uint32_t l = o - s_off[lo];
+        uint32_t k = lo;
+        uint2 r = s_rect[k];
+        uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
+        uint32_t l = s0 - s_off[k];
         uint32_t row = l / w, col = l - row * w;
-        uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
-        tkey[o] = ty * (uint32_t)gx + tx;
-        tid[o] = s_id[lo];
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            uint32_t o = s0 + (uint32_t)i;
+            if (o >= oend) break;
+            uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
+            s_tk[o - o0] = ty * (uint32_t)gx + tx;
+            s_tg[o - o0] = s_id[k];
+            if (++col == w) {
+                col = 0;
+                if (++row == h && k + 1 < m) {
+                    row = 0;
+                    ++k;
+                    r = s_rect[k];
+                    w = max(r.y & 0xFFFFu, 1u);
+                    h = max(r.y >> 16, 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < oend - o0; i += SORT_THREADS) {
+        tkey[o0 + i] = s_tk[i];
+        tid[o0 + i] = s_tg[i];
     }
 }
 
@@ -433,7 +460,7 @@ Layout layout(uint32_t P, uint32_t cap) {
     };
     uint32_t maxn = P > cap ? P : cap;
     uint32_t nblocks = (maxn + SORT_TILE - 1) / SORT_TILE + 1;
-    L.nwin = (cap + EMIT_TILE - 1) / EMIT_TILE + 1;
+    L.nwin = (cap + EMIT_TILE - 1) / EMIT_TILE + 2;
     L.dkey0 = take(4ull * P);
     L.dkey1 = take(4ull * P);
     L.did0 = take(4ull * P);
@@ -519,7 +546,7 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
                        (uint32_t)P, part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, sblocks, d_num_splats);
     hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
-                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin);
+                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin, d_num_splats);
     int tbits = ceil_log2((uint32_t)ntiles);
     if (tbits == 0) tbits = 1;
     int npass = (tbits + RADIX_BITS - 1) / RADIX_BITS;
