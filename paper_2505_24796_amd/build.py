@@ -39,11 +39,48 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _kernel_resources(src: str) -> list:
+    """Device-only assembly of one source; returns the code-object metadata of
+    every kernel (name, VGPRs, spills, private segment)."""
+    import yaml
+    asm = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
+    cmd = [hipcc(), *CFLAGS, "-S", "--cuda-device-only", os.path.join(CSRC, src), "-o", asm]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed for {src}:\n{r.stderr}")
+    txt = open(asm).read()
+    meta = txt.split(".amdgpu_metadata", 1)[1].split(".end_amdgpu_metadata", 1)[0]
+    return yaml.safe_load(meta.replace("\t", " ")).get("amdhsa.kernels", [])
+
+
+def check_resources() -> list:
+    """Every kernel must run from registers: no scratch (private segment) and
+    no register spills.  A regression here (e.g. a loop over the exponent
+    registers that is no longer fully unrolled) costs several times the run
+    time, so the build refuses it."""
+    bad, rows = [], []
+    for src in SOURCES:
+        for k in _kernel_resources(src):
+            row = (k[".name"], k.get(".vgpr_count"), k.get(".private_segment_fixed_size", 0),
+                   k.get(".vgpr_spill_count", 0), k.get(".sgpr_spill_count", 0))
+            rows.append(row)
+            if row[2] or row[3] or row[4]:
+                bad.append(row)
+    if bad:
+        raise RuntimeError("kernels using scratch or spilling registers: " +
+                           "; ".join(f"{b[0]} (private {b[2]} B, vgpr spills {b[3]}, sgpr spills {b[4]})"
+                                     for b in bad))
+    return rows
+
+
 def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libgsmfma.so in-tree."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with ThreadPoolExecutor(max_workers=2 * len(SOURCES)) as ex:
+        objs_f = [ex.submit(_compile, s) for s in SOURCES]
+        res_f = ex.submit(check_resources)
+        objs = [f.result() for f in objs_f]
+        res_f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -352,7 +352,8 @@ __device__ __forceinline__ void stage_splat(uint8_t *stage, int j, const SplatRe
     uint8_t *row2 = stage + Stage<VAR>::A1 + sub * SUB * VarTraits<VAR>::ROW2 + row * VarTraits<VAR>::ROW2;
     build_row<VAR>(s.valid, s.mu, s.s11, s.s12, s.s22, s.o, ox, oy, row1, row2);
     float4 *rgb = (float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
-    rgb[j] = make_float4(s.r, s.g, s.b, __uint_as_float(list_pos));
+    // w: 1-based position of the splat in the tile list (for n_contrib)
+    rgb[j] = make_float4(s.r, s.g, s.b, __uint_as_float(list_pos + 1u));
 }
 
 // Can the splat reach the 1/255 threshold anywhere in the pixel box
@@ -416,7 +417,8 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
         u0 = make_u<VAR>(bx, by, slice);
         u1 = make_u<VAR>(bx, by + 4.0f, slice);
     }
-    bool done = !(px < a.W && py < a.H);
+    // per-lane cull threshold; +inf marks a finished (or out-of-image) pixel
+    float thr = (px < a.W && py < a.H) ? CULL_LOG2 : __builtin_inff();
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const uint32_t n = end - start;
     const uint32_t nbatch = (n + BATCH - 1) / BATCH;
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
         // per pixel in list order)
         const bool keep = COUNT ? cur.valid : tile_alive(cur, bx0, by0);
         const uint64_t kmask = __ballot(keep);
-        const bool wave_done = __ballot(!done) == 0ull;
+        const bool wave_done = __ballot(thr != __builtin_inff()) == 0ull;
         if (lane == 0) {
             s_wcnt[wave] = __popcll(kmask);
             s_wdone[wave] = wave_done;
@@ -471,45 +473,40 @@ __global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
                            stage + Stage<VAR>::A1 + sidx * SUB * VarTraits<VAR>::ROW2, u0, u1, lane,
                            lo, hi);
             const uint32_t scount = min((uint32_t)SUB, (uint32_t)total - sidx * SUB);
-            uint32_t valid = scount >= 32 ? 0xFFFFFFFFu : ((1u << scount) - 1u);
-            float thr = done ? __builtin_inff() : CULL_LOG2;
-            uint32_t alive = 0;
-            if (COUNT) {
-                alive = valid;
-            } else {
+            const float4 *cols = rgbs + sidx * SUB;
+            // Front-to-back over the 32 splats.  `thr` is the lane's cull
+            // threshold, +inf once the pixel has terminated, so one compare
+            // both culls and masks finished pixels; a splat is visited only
+            // if some lane of the wave survives it (EarlyCull at wave level).
+            // The body is branch-free per lane: non-surviving lanes compute
+            // but commit nothing.
+            const uint32_t valid = scount >= 32u ? 0xFFFFFFFFu : ((1u << scount) - 1u);
 #pragma unroll
-                for (int g = 0; g < 16; ++g) {
-                    alive |= (__ballot(lo[g] >= thr) != 0ull) ? (1u << g) : 0u;
-                    alive |= (__ballot(hi[g] >= thr) != 0ull) ? (1u << (16 + g)) : 0u;
-                }
-                alive &= valid;
-            }
-#pragma unroll
-            for (int g = 0; g < 32; ++g) {
-                if (alive & (1u << g)) {
-                    float beta = g < 16 ? lo[g] : hi[g - 16];
-                    if (COUNT && !done && !(beta >= thr)) ++ncl;
-                    if (beta >= thr) {
-                        float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(beta));
-                        float test = fmaf(-alpha, T, T);
-                        if (test < T_MIN) {
-                            done = true;
-                            thr = __builtin_inff();
-                            if (COUNT) nt = 1;
-                        } else {
-                            float4 col = rgbs[sidx * SUB + g];
-                            float w = alpha * T;
-                            C0 = fmaf(col.x, w, C0);
-                            C1 = fmaf(col.y, w, C1);
-                            C2 = fmaf(col.z, w, C2);
-                            T = test;
-                            last = __float_as_uint(col.w) + 1u;
-                            if (COUNT) ++nb;
-                        }
+            for (int g = 0; g < SUB; ++g) {
+                if (!((valid >> g) & 1u)) break;
+                const float beta = g < 16 ? lo[g] : hi[g - 16];
+                const bool sv = beta >= thr;
+                if (COUNT) ncl += (thr != __builtin_inff() && !sv) ? 1u : 0u;
+                if (COUNT || __ballot(sv) != 0ull) {
+                    const float4 col = cols[g];
+                    const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(beta));
+                    const float test = fmaf(-alpha, T, T);
+                    const bool term = test < T_MIN;
+                    const bool blend = sv && !term;
+                    const float w = blend ? alpha * T : 0.0f;
+                    C0 = fmaf(col.x, w, C0);
+                    C1 = fmaf(col.y, w, C1);
+                    C2 = fmaf(col.z, w, C2);
+                    T = blend ? test : T;
+                    last = blend ? __float_as_uint(col.w) : last;
+                    thr = (sv && term) ? __builtin_inff() : thr;
+                    if (COUNT) {
+                        nb += blend ? 1u : 0u;
+                        nt += (sv && term) ? 1u : 0u;
                     }
                 }
             }
-            if (__ballot(!done) == 0ull) break;
+            if (__ballot(thr != __builtin_inff()) == 0ull) break;
         }
     }
     write_pixel(a, px, py, C0, C1, C2, T, last);
