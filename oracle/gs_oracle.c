@@ -39,6 +39,12 @@
  *     <= near are dropped), tx/tz and ty/tz clamped to 1.3 tan(fov/2) inside
  *     J, low-pass dilation Sigma' += 0.3 I, eigenvalue term floored at 0.1.
  *
+ * Pins: Algorithm 1, binning and the emulated exponent are pinned by closed
+ * forms, invariants, brute force and library routines in the tests.  The 3D
+ * projection conventions above are readings (the paper prints no projection
+ * example): parity unpinned against the paper, checked only by textbook
+ * properties (optical axis, isotropic size, finite-difference Jacobian).
+ *
  * Everything here is double precision except where a function emulates the
  * rounding of a reduced-precision format on purpose (the *_emu modes), which
  * is spelled out at the rounding function.
