@@ -393,8 +393,11 @@ __device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y
     return __logf(s.o) - fmin >= CULL_LN - margin;
 }
 
+// At least 5 resident waves per SIMD (the compiler then fits the kernel in
+// <= 80 VGPRs, i.e. 6 waves): the blend's exp / LDS / gather latencies are
+// hidden by other waves rather than by instruction-level parallelism.
 template <int VAR, bool COUNT>
-__global__ __launch_bounds__(256) void k_raster_mfma(RasterArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_mfma(RasterArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR>::BYTES];
     __shared__ int s_wcnt[4];
     __shared__ int s_wdone[4];
