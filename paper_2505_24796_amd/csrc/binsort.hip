@@ -148,74 +148,90 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (8-bit digit) of u32 keys with u32 values:
-// per-block digit histograms -> per-digit scan over blocks -> scatter.
+// Stable LSD radix sort of u32 keys with u32 values, one kernel per 8-bit
+// pass.  The global digit totals of every pass come from one histogram
+// kernel up front.  Within a pass, blocks take tickets in launch order (so a
+// block only ever waits for blocks that are already running), rank their
+// 4096 keys stably in LDS, publish their per-digit counts, and obtain the
+// exclusive prefix over earlier blocks by decoupled look-back on the
+// published words; then they write runs of equal digits to consecutive
+// global addresses.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
-                                                             Count cnt, int shift,
-                                                             uint32_t *__restrict__ hist,
-                                                             uint32_t nblocks) {
-    __shared__ uint32_t h[RADIX];
-    uint32_t n = cnt.get();
-    h[threadIdx.x] = 0;
+constexpr int MAX_PASSES = 4;
+constexpr uint32_t ST_AGG = 1u << 30;       // word holds this block's count
+constexpr uint32_t ST_PREFIX = 1u << 31;    // word holds the inclusive prefix
+constexpr uint32_t ST_VALUE = (1u << 30) - 1u;
+constexpr uint32_t SPIN_LIMIT = 1u << 22;   // bounded wait; sets the error word
+
+__device__ __forceinline__ void st_store(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t st_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-sort device state.  `gtot` is cleared by the stage's first kernel;
+// `status` and `tickets` by k_sort_hist, which runs before the passes.
+struct SortState {
+    uint32_t *gtot;     // [MAX_PASSES][RADIX] global digit totals
+    uint32_t *tickets;  // [MAX_PASSES]
+    uint32_t *status;   // [MAX_PASSES][nblocks][RADIX] look-back words
+    uint32_t *error;    // [1] non-zero if a look-back wait hit its limit
+    uint32_t nblocks;
+};
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *__restrict__ keys,
+                                                            Count cnt, int npass, SortState st) {
+    __shared__ uint32_t h[MAX_PASSES][RADIX];
+#pragma unroll
+    for (int p = 0; p < MAX_PASSES; ++p) h[p][threadIdx.x] = 0;
+    // clear this block's look-back words of every pass, and the tickets
+    for (int p = 0; p < npass; ++p)
+        st.status[((size_t)p * st.nblocks + blockIdx.x) * RADIX + threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < MAX_PASSES) st.tickets[threadIdx.x] = 0u;
     __syncthreads();
+    uint32_t n = cnt.get();
     size_t base = (size_t)blockIdx.x * SORT_TILE;
     if (base < n) {
 #pragma unroll
         for (int k = 0; k < SORT_ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+            if (i < n) {
+                uint32_t key = keys[i];
+                for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(key >> (RADIX_BITS * p)) & (RADIX - 1)], 1u);
+            }
         }
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-// One block per digit: exclusive scan of that digit's counts over blocks, in
-// place; the digit total goes to totals[d].
-__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict__ hist,
-                                                            uint32_t nblocks,
-                                                            uint32_t *__restrict__ totals) {
-    __shared__ uint32_t lds[WAVES];
-    uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nblocks; b0 += SORT_THREADS) {
-        uint32_t i = b0 + threadIdx.x;
-        uint32_t v = i < nblocks ? row[i] : 0u;
-        uint32_t ex;
-        uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
-        if (i < nblocks) row[i] = carry + ex;
-        carry += tot;
+    for (int p = 0; p < npass; ++p) {
+        uint32_t c = h[p][threadIdx.x];
+        if (c) atomicAdd(&st.gtot[p * RADIX + threadIdx.x], c);
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+__global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
-    const uint32_t *__restrict__ totals, uint32_t nblocks) {
+    uint32_t *__restrict__ vout, Count cnt, int pass, SortState st) {
     __shared__ uint32_t wcnt[WAVES][RADIX];
     __shared__ uint32_t gbase[RADIX];   // global position of this block's first key of digit d
     __shared__ uint32_t lstart[RADIX];  // local position of this block's first key of digit d
     __shared__ uint32_t skey[SORT_TILE];
     __shared__ uint32_t sval[SORT_TILE];
     __shared__ uint32_t lds_scan[WAVES];
-    uint32_t n = cnt.get();
-    size_t base = (size_t)blockIdx.x * SORT_TILE;
-    if (base >= n) return;  // whole block idle: uniform exit
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ uint32_t s_ticket;
+    const int shift = RADIX_BITS * pass;
+    if (threadIdx.x == 0) s_ticket = atomicAdd(&st.tickets[pass], 1u);
 #pragma unroll
     for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
-    {
-        // exclusive scan of the global digit totals -> digit base
-        uint32_t t = totals[threadIdx.x], ex;
-        block_excl_scan<uint32_t>(t, ex, lds_scan);
-        gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
-    }
     __syncthreads();
+    const uint32_t blk = s_ticket;
+    const uint32_t n = cnt.get();
+    const size_t base = (size_t)blk * SORT_TILE;
+    if (base >= n) return;  // this and every later ticket is empty: uniform exit
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 
     uint32_t key[WAVE_CHUNKS], val[WAVE_CHUNKS], pos[WAVE_CHUNKS];
-    size_t wbase = base + (size_t)w * WAVE_ITEMS;
+    const size_t wbase = base + (size_t)w * WAVE_ITEMS;
 #pragma unroll
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
@@ -223,6 +239,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         key[c] = ok ? kin[i] : 0u;
         val[c] = ok ? vin[i] : 0u;
     }
+    // stable rank inside the block: per wave, chunk by chunk, lanes with
+    // equal digits found by 8 ballots
 #pragma unroll
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
@@ -242,17 +260,45 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     {
-        // per digit: prefix over waves, and the block's digit-major local start
-        uint32_t d = threadIdx.x, off = 0;
+        const uint32_t d = threadIdx.x;
+        uint32_t cntd = 0;
 #pragma unroll
         for (int i = 0; i < WAVES; ++i) {
             uint32_t t = wcnt[i][d];
-            wcnt[i][d] = off;
-            off += t;
+            wcnt[i][d] = cntd;
+            cntd += t;
         }
+        // publish this block's count, then look back for the prefix
+        uint32_t *my = st.status + ((size_t)pass * st.nblocks + blk) * RADIX + d;
+        uint32_t excl = 0;
+        if (blk == 0) {
+            st_store(my, ST_PREFIX | cntd);
+        } else {
+            st_store(my, ST_AGG | cntd);
+            uint32_t j = blk - 1, spins = 0;
+            for (;;) {
+                uint32_t wv = st_load(st.status + ((size_t)pass * st.nblocks + j) * RADIX + d);
+                if ((wv & (ST_AGG | ST_PREFIX)) == 0u) {
+                    if (++spins > SPIN_LIMIT) {
+                        atomicOr(st.error, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += wv & ST_VALUE;
+                if ((wv & ST_PREFIX) || j == 0) break;
+                --j;
+            }
+            st_store(my, ST_PREFIX | (excl + cntd));
+        }
+        // digit base = exclusive scan of the global totals of this pass
         uint32_t ex;
-        block_excl_scan<uint32_t>(off, ex, lds_scan);
-        lstart[d] = ex;
+        block_excl_scan<uint32_t>(st.gtot[pass * RADIX + d], ex, lds_scan);
+        gbase[d] = ex + excl;
+        uint32_t lex;
+        block_excl_scan<uint32_t>(cntd, lex, lds_scan);
+        lstart[d] = lex;
     }
     __syncthreads();
     // stage in LDS in (digit, original order) order ...
@@ -268,7 +314,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     // ... and write runs of equal digits to consecutive global addresses
-    uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
+    const uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
         uint32_t d = (k >> shift) & (RADIX - 1);
@@ -282,19 +328,15 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
-// Sorts on bits [0, bits) with ceil(bits/8) passes; returns the index of the
-// buffer pair holding the result.
-int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
-               hipStream_t s) {
-    uint32_t nblocks = (max_n + SORT_TILE - 1) / SORT_TILE;
-    if (nblocks == 0) nblocks = 1;
+// Sorts on bits [0, bits) with ceil(bits/8) passes (at most 4); returns the
+// index of the buffer pair holding the result.  st.gtot must be zero.
+int radix_sort(SortBufs b, Count cnt, int bits, SortState st, hipStream_t s) {
+    int npass = (bits + RADIX_BITS - 1) / RADIX_BITS;
+    hipLaunchKernelGGL(k_sort_hist, dim3(st.nblocks), dim3(SORT_THREADS), 0, s, b.k[0], cnt, npass, st);
     int cur = 0;
-    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], cnt,
-                           shift, hist, nblocks);
-        hipLaunchKernelGGL(k_hist_rows, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
-                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals, nblocks);
+    for (int p = 0; p < npass; ++p) {
+        hipLaunchKernelGGL(k_onesweep, dim3(st.nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], b.v[cur],
+                           b.k[cur ^ 1], b.v[cur ^ 1], cnt, p, st);
         cur ^= 1;
     }
     return cur;
@@ -317,9 +359,11 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     int gx, uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
                                                     uint2 *__restrict__ rects,
-                                                    uint32_t *__restrict__ ranges, int n2) {
+                                                    uint32_t *__restrict__ ranges, int n2,
+                                                    uint32_t *__restrict__ clear, int nclear) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n2) ranges[i] = 0u;
+    if (i < nclear) clear[i] = 0u;
     if (i >= P) return;
     float d = depths[i];
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
@@ -422,16 +466,32 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
     }
 }
 
-// Tile ranges from the tile-sorted keys: 4 keys per thread.
+// Tile ranges from the tile-sorted keys: 4 keys per thread (one 16-byte
+// load; the neighbours come from the adjacent lanes).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tkey, Count cnt,
                                                 uint32_t ntiles, uint32_t *__restrict__ ranges) {
-    uint32_t n = cnt.get();
-    uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
-    if (i0 >= n) return;
+    const uint32_t n = cnt.get();
+    const uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int lane = threadIdx.x & 63;
     uint32_t k[6];
-    k[0] = i0 > 0 ? tkey[i0 - 1] : 0xFFFFFFFFu;
+    if (i0 + 3 < n) {
+        uint4 q = *(const uint4 *)(tkey + i0);
+        k[1] = q.x;
+        k[2] = q.y;
+        k[3] = q.z;
+        k[4] = q.w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) k[j + 1] = (i0 + j < n) ? tkey[i0 + j] : 0xFFFFFFFFu;
+        for (int j = 0; j < 4; ++j) k[j + 1] = (i0 + j < n) ? tkey[i0 + j] : 0xFFFFFFFFu;
+    }
+    // previous key: last key of the lane below; next key: first key of the lane above
+    uint32_t prev = __shfl_up(k[4], 1, 64), next = __shfl_down(k[1], 1, 64);
+    if (lane == 0) prev = (i0 > 0 && i0 - 1 < n) ? tkey[i0 - 1] : 0xFFFFFFFFu;
+    if (lane == 63) next = (i0 + 4 < n) ? tkey[i0 + 4] : 0xFFFFFFFFu;
+    if (i0 + 4 >= n) next = 0xFFFFFFFFu;
+    k[0] = i0 > 0 ? prev : 0xFFFFFFFFu;
+    k[5] = next;
+    if (i0 >= n) return;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         uint32_t i = i0 + j;
@@ -445,10 +505,13 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
 
 // Workspace carve-up (every region 256-byte aligned).
 struct Layout {
-    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, tkey0, tkey1, tid, hist,
-        totals, part, win, total;
-    uint32_t nwin;
+    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, tkey0, tkey1, tid, clear,
+        dstatus, tstatus, part, win, total;
+    uint32_t nwin, dblocks, tblocks;
 };
+
+// Cleared region: [depth gtot | tile gtot | depth tickets | tile tickets | error]
+constexpr int CLEAR_WORDS = 2 * MAX_PASSES * RADIX + 2 * MAX_PASSES + 1;
 
 Layout layout(uint32_t P, uint32_t cap) {
     Layout L{};
@@ -458,8 +521,10 @@ Layout layout(uint32_t P, uint32_t cap) {
         off = align_up(off + (bytes ? bytes : 4), 256);
         return o;
     };
-    uint32_t maxn = P > cap ? P : cap;
-    uint32_t nblocks = (maxn + SORT_TILE - 1) / SORT_TILE + 1;
+    L.dblocks = (P + SORT_TILE - 1) / SORT_TILE;
+    L.tblocks = (cap + SORT_TILE - 1) / SORT_TILE;
+    if (L.dblocks == 0) L.dblocks = 1;
+    if (L.tblocks == 0) L.tblocks = 1;
     L.nwin = (cap + EMIT_TILE - 1) / EMIT_TILE + 2;
     L.dkey0 = take(4ull * P);
     L.dkey1 = take(4ull * P);
@@ -472,8 +537,9 @@ Layout layout(uint32_t P, uint32_t cap) {
     L.tkey0 = take(4ull * cap);
     L.tkey1 = take(4ull * cap);
     L.tid = take(4ull * cap);
-    L.hist = take(4ull * RADIX * nblocks);
-    L.totals = take(4ull * RADIX);
+    L.clear = take(4ull * CLEAR_WORDS);
+    L.dstatus = take(4ull * MAX_PASSES * L.dblocks * RADIX);
+    L.tstatus = take(4ull * MAX_PASSES * L.tblocks * RADIX);
     L.part = take(8ull * ((P + SORT_TILE - 1) / SORT_TILE + 2));
     L.win = take(4ull * L.nwin);
     L.total = off;
@@ -491,7 +557,7 @@ int ceil_log2(uint32_t x) {
 extern "C" size_t gs_bin_sort_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
                                               int32_t height) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
-    if (capacity >= 0x80000000u) return 0;
+    if (capacity >= 0x40000000u || P >= 0x40000000) return 0;
     return layout((uint32_t)P, capacity).total;
 }
 
@@ -508,7 +574,7 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     if (P > 0 && (!means2d || !radii || !depths || !gs::aligned(means2d, 8) ||
                   !gs::aligned(radii, 4) || !gs::aligned(depths, 4)))
         return GS_ERR_INVALID_ARG;
-    if (capacity >= 0x80000000u) return GS_ERR_INVALID_ARG;
+    if (capacity >= 0x40000000u || P >= 0x40000000) return GS_ERR_INVALID_ARG;
     if (capacity > 0 && (!sorted_ids || !gs::aligned(sorted_ids, 4))) return GS_ERR_INVALID_ARG;
     Layout L = layout((uint32_t)P, capacity);
     if (workspace_bytes < L.total) return GS_ERR_CAPACITY;
@@ -519,23 +585,28 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     int gx = gs::grid_x(width), gy = gs::grid_y(height);
     int ntiles = gx * gy;
 
+    uint32_t *clear = U(L.clear);
+    SortState dst{clear, clear + 2 * MAX_PASSES * RADIX, U(L.dstatus),
+                  clear + 2 * MAX_PASSES * RADIX + 2 * MAX_PASSES, L.dblocks};
+    SortState tst{clear + MAX_PASSES * RADIX, clear + 2 * MAX_PASSES * RADIX + MAX_PASSES,
+                  U(L.tstatus), clear + 2 * MAX_PASSES * RADIX + 2 * MAX_PASSES, L.tblocks};
     if (P == 0) {
         hipLaunchKernelGGL(k_depth_keys, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, 0,
                            (const float2 *)nullptr, (const int *)nullptr, (const float *)nullptr,
                            width, height, gx, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                           (uint2 *)nullptr, tile_ranges, 2 * ntiles);
+                           (uint2 *)nullptr, tile_ranges, 2 * ntiles, clear, 0);
         hipMemsetAsync(d_num_splats, 0, 4, s);
         return gs::launch_status();
     }
     const float2 *m2 = (const float2 *)means2d;
     int nthr = P > 2 * ntiles ? P : 2 * ntiles;
-    // 1. depth keys, rectangles, cleared ranges; depth order of the Gaussians
+    if (nthr < CLEAR_WORDS) nthr = CLEAR_WORDS;
+    // 1. depth keys, rectangles, cleared ranges and sort state; depth order
     hipLaunchKernelGGL(k_depth_keys, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2, radii,
                        depths, width, height, gx, U(L.dkey0), U(L.did0), (uint2 *)(ws + L.rects),
-                       tile_ranges, 2 * ntiles);
+                       tile_ranges, 2 * ntiles, clear, CLEAR_WORDS);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
-    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32, U(L.hist),
-                          U(L.totals), s);
+    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, 32, dst, s);
     const uint32_t *order = db.v[dcur];
     // 2. counts in depth order, scan (+ window owners), expansion
     int pblocks = (P + 255) / 256;
@@ -563,7 +634,7 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     Count nc{0u, d_num_splats, capacity};
-    int tcur = radix_sort(tb, nc, capacity, tbits, U(L.hist), U(L.totals), s);
+    int tcur = radix_sort(tb, nc, tbits, tst, s);
     // 4. ranges
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
     hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
