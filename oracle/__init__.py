@@ -155,6 +155,25 @@ def bin_splats(means2d, radii, depths, W: int, H: int):
     return ranges, ids[:N]
 
 
+def bin_tiles(means2d, radii, depths, W: int, H: int, tiles):
+    """Per-tile splat lists for the listed tiles only (same rule and order as
+    bin_splats): returns (ranges (len(tiles), 2) uint32, ids uint32)."""
+    m, r, d = _f32(means2d), _i32(radii), _f32(depths)
+    tl = _i32(tiles)
+    P = m.shape[0]
+    ranges = np.zeros((len(tl), 2), np.uint32)
+    L = lib()
+    L.orc_bin_tiles.restype = c_int64
+    N = int(L.orc_bin_tiles(c_int(P), _p(m), _p(r), _p(d), c_int(W), c_int(H), c_int(len(tl)),
+                            _p(tl), _p(ranges), c_void_p(0), c_int64(0)))
+    if N < 0:
+        raise MemoryError("oracle binning: allocation failed")
+    ids = np.zeros(max(N, 1), np.uint32)
+    L.orc_bin_tiles(c_int(P), _p(m), _p(r), _p(d), c_int(W), c_int(H), c_int(len(tl)), _p(tl),
+                    _p(ranges), _p(ids), c_int64(N))
+    return ranges, ids[:N]
+
+
 def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0, 0.0),
            mode: int = MODE_DEF, delta_c: float = 0.0, delta_t: float = 0.0, tiles=None,
            delta_r: float = 0.0) -> dict:

@@ -375,6 +375,57 @@ int64_t orc_bin(int P, const float *means2d, const int32_t *radii, const float *
     return N;
 }
 
+/* Binning restricted to a list of tiles (for sampled checks of very large
+ * frames): the same rule and order as orc_bin, but only splats on the listed
+ * tiles are kept.  ranges[2*j], ranges[2*j+1] delimit the list of tile_list[j]
+ * in ids.  Returns the number of kept splats (writes at most capacity ids). */
+int64_t orc_bin_tiles(int P, const float *means2d, const int32_t *radii, const float *depths,
+                      int W, int H, int ntl, const int32_t *tile_list, uint32_t *ranges,
+                      uint32_t *ids, int64_t capacity)
+{
+    int gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
+    int ntiles = gx * gy;
+    int32_t *slot = (int32_t *)malloc((size_t)ntiles * sizeof(int32_t));
+    if (!slot) return -1;
+    for (int t = 0; t < ntiles; ++t) slot[t] = -1;
+    for (int j = 0; j < ntl; ++j) slot[tile_list[j]] = j;
+    int64_t cap = 1024, k = 0;
+    splat_t *sp = (splat_t *)malloc((size_t)cap * sizeof(splat_t));
+    if (!sp) { free(slot); return -1; }
+    for (int i = 0; i < P; ++i) {
+        int tx0, tx1, ty0, ty1;
+        if (!isfinite(depths[i])) continue;
+        if (!tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], W, H, &tx0, &tx1, &ty0, &ty1)) continue;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) {
+                int j = slot[ty * gx + tx];
+                if (j < 0) continue;
+                if (k == cap) {
+                    cap *= 2;
+                    splat_t *n2 = (splat_t *)realloc(sp, (size_t)cap * sizeof(splat_t));
+                    if (!n2) { free(sp); free(slot); return -1; }
+                    sp = n2;
+                }
+                sp[k].tile = j;  /* position in tile_list, so the lists come out in list order */
+                sp[k].depth = depths[i] == 0.0f ? 0.0f : depths[i];
+                sp[k].id = i;
+                ++k;
+            }
+    }
+    qsort(sp, (size_t)k, sizeof(splat_t), splat_cmp);
+    for (int j = 0; j < 2 * ntl; ++j) ranges[j] = 0;
+    int64_t lim = k < capacity ? k : capacity;
+    for (int64_t m = 0; m < lim; ++m) ids[m] = (uint32_t)sp[m].id;
+    for (int64_t m = 0; m < k; ++m) {
+        int j = sp[m].tile;
+        if (m == 0 || sp[m - 1].tile != j) ranges[2 * j] = (uint32_t)m;
+        if (m == k - 1 || sp[m + 1].tile != j) ranges[2 * j + 1] = (uint32_t)(m + 1);
+    }
+    free(sp);
+    free(slot);
+    return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exponent modes.                                                          */
 /*  0 DEFINITION: alpha = o exp(-q/2), q = d^T S d, d = mu' - p (Alg. 1).   */

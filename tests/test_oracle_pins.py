@@ -471,3 +471,16 @@ def test_emulated_render_quality(orc):
     assert p[1] < 30
     assert p[2] > 50
     assert p[3] > p[2] and p[4] > p[2]
+
+
+def test_bin_tiles_matches_full_binning(orc):
+    """The tile-subset binning used for sampled checks of large frames gives
+    exactly the full binning's lists for the listed tiles."""
+    W, H = 250, 190
+    sc = scenegen.scene_2d(3000, W, H, seed=7)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+    r_all, i_all = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+    tl = np.array([5, 100, 17, 3, 191, 0])
+    r_t, i_t = orc.bin_tiles(sc.means2d, pre["radii"], sc.depths, W, H, tl)
+    for j, t in enumerate(tl):
+        assert np.array_equal(i_all[r_all[t, 0]:r_all[t, 1]], i_t[r_t[j, 0]:r_t[j, 1]])
