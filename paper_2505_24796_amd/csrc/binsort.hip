@@ -162,6 +162,10 @@ constexpr uint32_t ST_AGG = 1u << 30;       // word holds this block's count
 constexpr uint32_t ST_PREFIX = 1u << 31;    // word holds the inclusive prefix
 constexpr uint32_t ST_VALUE = (1u << 30) - 1u;
 constexpr uint32_t SPIN_LIMIT = 1u << 22;   // bounded wait; sets the error word
+constexpr int LOOKBACK = 16;                // predecessors read per look-back step
+constexpr int GTOT_COPIES = 8;              // histogram totals spread over 8 copies
+constexpr int HIST_ITEMS = 128;             // keys per thread in the histogram kernel
+constexpr int HIST_TILE = SORT_THREADS * HIST_ITEMS;
 
 __device__ __forceinline__ void st_store(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -172,40 +176,45 @@ __device__ __forceinline__ uint32_t st_load(const uint32_t *p) {
 
 // Per-sort device state.  `gtot` is cleared by the stage's first kernel;
 // `status` and `tickets` by k_sort_hist, which runs before the passes.
+// The digit totals are accumulated into GTOT_COPIES copies (block b adds to
+// copy b mod 8) so that no counter takes more than a few dozen contended
+// device-scope atomics; readers sum the copies.
 struct SortState {
-    uint32_t *gtot;     // [MAX_PASSES][RADIX] global digit totals
+    uint32_t *gtot;     // [GTOT_COPIES][MAX_PASSES][RADIX] global digit totals
     uint32_t *tickets;  // [MAX_PASSES]
     uint32_t *status;   // [MAX_PASSES][nblocks][RADIX] look-back words
     uint32_t *error;    // [1] non-zero if a look-back wait hit its limit
     uint32_t nblocks;
 };
 
+// Digit totals of every pass (HIST_TILE keys per block), and clearing of
+// the passes' look-back words and tickets (grid-stride).
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *__restrict__ keys,
                                                             Count cnt, int npass, SortState st) {
     __shared__ uint32_t h[MAX_PASSES][RADIX];
 #pragma unroll
     for (int p = 0; p < MAX_PASSES; ++p) h[p][threadIdx.x] = 0;
-    // clear this block's look-back words of every pass, and the tickets
-    for (int p = 0; p < npass; ++p)
-        st.status[((size_t)p * st.nblocks + blockIdx.x) * RADIX + threadIdx.x] = 0u;
+    const size_t nstatus = (size_t)npass * st.nblocks * RADIX;
+    for (size_t i = (size_t)blockIdx.x * SORT_THREADS + threadIdx.x; i < nstatus;
+         i += (size_t)gridDim.x * SORT_THREADS)
+        st.status[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x < MAX_PASSES) st.tickets[threadIdx.x] = 0u;
     __syncthreads();
-    uint32_t n = cnt.get();
-    size_t base = (size_t)blockIdx.x * SORT_TILE;
+    const uint32_t n = cnt.get();
+    const size_t base = (size_t)blockIdx.x * HIST_TILE;
     if (base < n) {
-#pragma unroll
-        for (int k = 0; k < SORT_ITEMS; ++k) {
+        for (int k = 0; k < HIST_ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i < n) {
-                uint32_t key = keys[i];
-                for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(key >> (RADIX_BITS * p)) & (RADIX - 1)], 1u);
-            }
+            if (i >= n) break;
+            uint32_t key = keys[i];
+            for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(key >> (RADIX_BITS * p)) & (RADIX - 1)], 1u);
         }
     }
     __syncthreads();
+    uint32_t *g = st.gtot + (size_t)(blockIdx.x % GTOT_COPIES) * MAX_PASSES * RADIX;
     for (int p = 0; p < npass; ++p) {
         uint32_t c = h[p][threadIdx.x];
-        if (c) atomicAdd(&st.gtot[p * RADIX + threadIdx.x], c);
+        if (c) atomicAdd(&g[p * RADIX + threadIdx.x], c);
     }
 }
 
@@ -268,33 +277,53 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
             wcnt[i][d] = cntd;
             cntd += t;
         }
-        // publish this block's count, then look back for the prefix
+        // publish this block's count, then look back for the prefix:
+        // LOOKBACK predecessors are read at once and consumed in order until
+        // an inclusive prefix is found (done) or a word is still empty (wait
+        // and re-read from there)
+        const uint32_t *col = st.status + (size_t)pass * st.nblocks * RADIX + d;
         uint32_t *my = st.status + ((size_t)pass * st.nblocks + blk) * RADIX + d;
         uint32_t excl = 0;
         if (blk == 0) {
             st_store(my, ST_PREFIX | cntd);
         } else {
             st_store(my, ST_AGG | cntd);
-            uint32_t j = blk - 1, spins = 0;
+            int64_t j = (int64_t)blk - 1;
+            uint32_t spins = 0;
             for (;;) {
-                uint32_t wv = st_load(st.status + ((size_t)pass * st.nblocks + j) * RADIX + d);
-                if ((wv & (ST_AGG | ST_PREFIX)) == 0u) {
+                uint32_t wv[LOOKBACK];
+#pragma unroll
+                for (int k = 0; k < LOOKBACK; ++k)
+                    wv[k] = (j - k >= 0) ? st_load(col + (size_t)(j - k) * RADIX) : ST_PREFIX;
+                int consumed = 0;
+                bool found = false;
+#pragma unroll
+                for (int k = 0; k < LOOKBACK; ++k) {
+                    if (found || consumed < k) continue;
+                    uint32_t w = wv[k];
+                    if ((w & (ST_AGG | ST_PREFIX)) == 0u) continue;  // empty: stop consuming here
+                    excl += w & ST_VALUE;
+                    consumed = k + 1;
+                    if (w & ST_PREFIX) found = true;
+                }
+                if (found) break;
+                j -= consumed;
+                if (consumed == 0) {
                     if (++spins > SPIN_LIMIT) {
                         atomicOr(st.error, 1u);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += wv & ST_VALUE;
-                if ((wv & ST_PREFIX) || j == 0) break;
-                --j;
             }
             st_store(my, ST_PREFIX | (excl + cntd));
         }
         // digit base = exclusive scan of the global totals of this pass
+        uint32_t tot = 0;
+#pragma unroll
+        for (int c = 0; c < GTOT_COPIES; ++c) tot += st.gtot[((size_t)c * MAX_PASSES + pass) * RADIX + d];
         uint32_t ex;
-        block_excl_scan<uint32_t>(st.gtot[pass * RADIX + d], ex, lds_scan);
+        block_excl_scan<uint32_t>(tot, ex, lds_scan);
         gbase[d] = ex + excl;
         uint32_t lex;
         block_excl_scan<uint32_t>(cntd, lex, lds_scan);
@@ -332,7 +361,8 @@ struct SortBufs {
 // index of the buffer pair holding the result.  st.gtot must be zero.
 int radix_sort(SortBufs b, Count cnt, int bits, SortState st, hipStream_t s) {
     int npass = (bits + RADIX_BITS - 1) / RADIX_BITS;
-    hipLaunchKernelGGL(k_sort_hist, dim3(st.nblocks), dim3(SORT_THREADS), 0, s, b.k[0], cnt, npass, st);
+    uint32_t hblocks = (uint32_t)(((size_t)st.nblocks * SORT_TILE + HIST_TILE - 1) / HIST_TILE);
+    hipLaunchKernelGGL(k_sort_hist, dim3(hblocks), dim3(SORT_THREADS), 0, s, b.k[0], cnt, npass, st);
     int cur = 0;
     for (int p = 0; p < npass; ++p) {
         hipLaunchKernelGGL(k_onesweep, dim3(st.nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], b.v[cur],
@@ -511,7 +541,8 @@ struct Layout {
 };
 
 // Cleared region: [depth gtot | tile gtot | depth tickets | tile tickets | error]
-constexpr int CLEAR_WORDS = 2 * MAX_PASSES * RADIX + 2 * MAX_PASSES + 1;
+constexpr int GTOT_WORDS = GTOT_COPIES * MAX_PASSES * RADIX;
+constexpr int CLEAR_WORDS = 2 * GTOT_WORDS + 2 * MAX_PASSES + 1;
 
 Layout layout(uint32_t P, uint32_t cap) {
     Layout L{};
@@ -586,10 +617,10 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     int ntiles = gx * gy;
 
     uint32_t *clear = U(L.clear);
-    SortState dst{clear, clear + 2 * MAX_PASSES * RADIX, U(L.dstatus),
-                  clear + 2 * MAX_PASSES * RADIX + 2 * MAX_PASSES, L.dblocks};
-    SortState tst{clear + MAX_PASSES * RADIX, clear + 2 * MAX_PASSES * RADIX + MAX_PASSES,
-                  U(L.tstatus), clear + 2 * MAX_PASSES * RADIX + 2 * MAX_PASSES, L.tblocks};
+    SortState dst{clear, clear + 2 * GTOT_WORDS, U(L.dstatus), clear + 2 * GTOT_WORDS + 2 * MAX_PASSES,
+                  L.dblocks};
+    SortState tst{clear + GTOT_WORDS, clear + 2 * GTOT_WORDS + MAX_PASSES, U(L.tstatus),
+                  clear + 2 * GTOT_WORDS + 2 * MAX_PASSES, L.tblocks};
     if (P == 0) {
         hipLaunchKernelGGL(k_depth_keys, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, 0,
                            (const float2 *)nullptr, (const int *)nullptr, (const float *)nullptr,
