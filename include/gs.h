@@ -168,6 +168,29 @@ gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_r
                            uint64_t *d_counters, void *stream);
 
 /*
+ * gs_rasterize_bwd -- gradients of a loss through gs_rasterize_fwd (the
+ * backward of Algorithm 1).  Given dL_dimg = dL/dC [3][H][W] (planar, the
+ * same layout as out_rgb) and the forward's out_T and out_ncontrib, walks
+ * each pixel's blended fragments in reverse, recovering the transmittance by
+ * division, and ADDS to (caller zeroes):
+ *   dL_dmeans2d [P][2], dL_dconics [P][3] (d/d(s11, s12, s22)),
+ *   dL_dopacities [P], dL_drgb [P][3].
+ * The derivative is that of alpha = min(0.99, o exp(beta)) with the clamp's
+ * zero slope where it is active; culled and skipped fragments contribute
+ * nothing.  `precision` must be the one the forward used: fragments are
+ * re-evaluated with the same arithmetic so every cull and termination
+ * decision agrees with the forward.  Results are summed with atomics, so the
+ * last bits may differ between runs.
+ * Errors: GS_ERR_INVALID_ARG for bad sizes, pointers or precision; GS_ERR_HIP.
+ */
+gs_status gs_rasterize_bwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
+                           const uint32_t *sorted_ids, const float *means2d, const float *conics,
+                           const float *opacities, const float *rgb, const float *background,
+                           int32_t precision, const float *out_T, const uint32_t *out_ncontrib,
+                           const float *dL_dimg, float *dL_dmeans2d, float *dL_dconics,
+                           float *dL_dopacities, float *dL_drgb, void *stream);
+
+/*
  * gs_rasterize_beta -- diagnostic: the exponent matrix B = U^T V (Sec. 4.2,
  * eq. MM) of one tile, exactly as the matrix-core path of gs_rasterize_fwd
  * computes it for `precision` (one of the FP16/BF16 variants), in log2

@@ -228,3 +228,22 @@ def beta_emulated(mode: int, mu, S, opac: float, p, tc) -> float:
     one fragment, with exact accumulation."""
     mu, S, p, tc = _f64(mu), _f64(S), _f64(p), _f64(tc)
     return float(lib().orc_beta_emulated(c_int(mode), _p(mu), _p(S), c_double(opac), _p(p), _p(tc)))
+
+
+def render_backward(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, dL_dC,
+                    bg=(0.0, 0.0, 0.0)) -> dict:
+    """FP64 gradients of a loss with respect to means2d, conics, opacities and
+    colours, given dL/dC per pixel (planar (3, H, W)), by reverse traversal of
+    Algorithm 1 (definition mode)."""
+    rg, idv = np.ascontiguousarray(ranges, np.uint32), np.ascontiguousarray(ids, np.uint32)
+    if idv.size == 0:
+        idv = np.zeros(1, np.uint32)
+    m, c, o, col, b = _f64(means2d), _f64(conics), _f64(opac), _f64(rgb), _f64(bg)
+    g = _f64(dL_dC)
+    P = m.shape[0]
+    out = dict(means2d=np.zeros((P, 2)), conics=np.zeros((P, 3)), opacities=np.zeros(P),
+               rgb=np.zeros((P, 3)))
+    lib().orc_render_backward(c_int(W), c_int(H), _p(rg), _p(idv), _p(m), _p(c), _p(o), _p(col),
+                              _p(b), _p(g), _p(out["means2d"]), _p(out["conics"]),
+                              _p(out["opacities"]), _p(out["rgb"]))
+    return out

@@ -629,6 +629,98 @@ void orc_render_alternatives(int W, int H, const uint32_t *ranges, const uint32_
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Gradients (definition mode).  For a loss L with dL/dC given per pixel    */
+/* (planar [3][H][W]), the derivative of Algorithm 1's output              */
+/*   C_out = sum_k c_k a_k T_k + T_final bg,  T_{k+1} = T_k (1 - a_k)       */
+/* over the blended fragments k of a pixel, with respect to each            */
+/* fragment's a_k and c_k:                                                  */
+/*   dC_out/dc_k = a_k T_k                                                  */
+/*   dC_out/da_k = T_k (c_k - B_k),  B_k = (sum_{i>k} c_i a_i T_i +         */
+/*                 T_final bg) / T_{k+1}                                    */
+/* and a_k = o exp(-q/2) unless clamped at 0.99 (zero derivative there):    */
+/*   da/do = exp(-q/2), da/dq = -a/2, dq/dmu = 2 S (mu - p),                */
+/*   dq/d(s11, s12, s22) = (dx^2, 2 dx dy, dy^2).                           */
+/* Culled and skipped fragments contribute nothing.  Accumulates into the   */
+/* gradient arrays (caller zeroes).  Pixels are visited in order, so the    */
+/* sums are deterministic.                                                  */
+/* ------------------------------------------------------------------------ */
+void orc_render_backward(int W, int H, const uint32_t *ranges, const uint32_t *ids,
+                         const double *means2d, const double *conics, const double *opac,
+                         const double *rgb, const double *bg, const double *dL_dC,
+                         double *g_means2d, double *g_conics, double *g_opac, double *g_rgb)
+{
+    int gx = (W + ORC_TILE - 1) / ORC_TILE;
+    size_t HW = (size_t)W * H;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int tile = (y / ORC_TILE) * gx + x / ORC_TILE;
+            uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+            size_t pi = (size_t)y * W + x;
+            double dC[3] = {dL_dC[pi], dL_dC[HW + pi], dL_dC[2 * HW + pi]};
+            /* forward pass of this pixel, recording its blended fragments */
+            int nbl = 0, cap = 64;
+            uint32_t *kk = (uint32_t *)malloc((size_t)cap * sizeof(uint32_t));
+            double *aa = (double *)malloc((size_t)cap * sizeof(double));
+            double *tt = (double *)malloc((size_t)cap * sizeof(double));
+            int *cl = (int *)malloc((size_t)cap * sizeof(int));
+            double T = 1.0;
+            for (uint32_t k = start; k < end; ++k) {
+                uint32_t g = ids[k];
+                const double *mu = means2d + 2 * g, *S = conics + 3 * g;
+                double dx = mu[0] - x, dy = mu[1] - y;
+                double q = S[0] * dx * dx + 2.0 * S[1] * dx * dy + S[2] * dy * dy;
+                double a = opac[g] * exp(-0.5 * q);
+                int clamped = a > 0.99;
+                if (clamped) a = 0.99;
+                if (a < 1.0 / 255.0) continue;
+                double test = T - a * T;
+                if (test < 1e-4) break;
+                if (nbl == cap) {
+                    cap *= 2;
+                    kk = (uint32_t *)realloc(kk, (size_t)cap * sizeof(uint32_t));
+                    aa = (double *)realloc(aa, (size_t)cap * sizeof(double));
+                    tt = (double *)realloc(tt, (size_t)cap * sizeof(double));
+                    cl = (int *)realloc(cl, (size_t)cap * sizeof(int));
+                }
+                kk[nbl] = g;
+                aa[nbl] = a;
+                tt[nbl] = T;
+                cl[nbl] = clamped;
+                ++nbl;
+                T = test;
+            }
+            /* reverse traversal */
+            double B[3] = {bg[0], bg[1], bg[2]};
+            for (int j = nbl - 1; j >= 0; --j) {
+                uint32_t g = kk[j];
+                double a = aa[j], Tk = tt[j];
+                const double *c = rgb + 3 * g;
+                double da = 0.0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    da += dC[ch] * Tk * (c[ch] - B[ch]);
+                    g_rgb[3 * g + ch] += dC[ch] * a * Tk;
+                    B[ch] = a * c[ch] + (1.0 - a) * B[ch];
+                }
+                if (cl[j]) continue;
+                const double *mu = means2d + 2 * g, *S = conics + 3 * g;
+                double dx = mu[0] - x, dy = mu[1] - y;
+                double q = S[0] * dx * dx + 2.0 * S[1] * dx * dy + S[2] * dy * dy;
+                g_opac[g] += da * exp(-0.5 * q);
+                double dq = da * (-0.5 * a);
+                g_means2d[2 * g] += dq * 2.0 * (S[0] * dx + S[1] * dy);
+                g_means2d[2 * g + 1] += dq * 2.0 * (S[1] * dx + S[2] * dy);
+                g_conics[3 * g] += dq * dx * dx;
+                g_conics[3 * g + 1] += dq * 2.0 * dx * dy;
+                g_conics[3 * g + 2] += dq * dy * dy;
+            }
+            free(kk);
+            free(aa);
+            free(tt);
+            free(cl);
+        }
+}
+
 /* Number of OpenMP threads the parallel loops use (1 without OpenMP). */
 int orc_num_threads(void)
 {

@@ -82,6 +82,9 @@ def lib() -> ctypes.CDLL:
         L.gs_rasterize_fwd.restype = ctypes.c_int
         L.gs_rasterize_fwd.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp,
                                        POINTER(c_float), c_int32, vp, vp, vp, vp, vp]
+        L.gs_rasterize_bwd.restype = ctypes.c_int
+        L.gs_rasterize_bwd.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp, POINTER(c_float),
+                                       c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.gs_rasterize_beta.restype = ctypes.c_int
         L.gs_rasterize_beta.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, c_int32,
                                         c_int32, vp, vp]
@@ -240,6 +243,51 @@ def rasterize_fwd(width, height, ranges, sorted_ids, means2d, conics, opacities,
     r = Rasterizer(width, height, device=means2d.device)
     r(ranges, sorted_ids, means2d, conics, opacities, rgb, precision, background, count)
     return r
+
+
+def rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, opacities, rgb, out_T,
+                  out_ncontrib, dL_dimg, precision="fp32", background=(0.0, 0.0, 0.0)):
+    """Gradients through rasterize_fwd (same precision as the forward): returns
+    dict(means2d, conics, opacities, rgb) of freshly zeroed-then-accumulated
+    tensors."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for n, t, dt in (("out_T", out_T, torch.float32), ("out_ncontrib", out_ncontrib, torch.int32),
+                     ("dL_dimg", dL_dimg, torch.float32)):
+        _dev(t, dt, n)
+    g = dict(means2d=torch.zeros_like(means2d), conics=torch.zeros_like(conics),
+             opacities=torch.zeros_like(opacities), rgb=torch.zeros_like(rgb))
+    bg = (c_float * 3)(*[float(b) for b in background])
+    st = lib().gs_rasterize_bwd(width, height, _ptr(ranges), _ptr(sorted_ids), _ptr(means2d),
+                                _ptr(conics), _ptr(opacities), _ptr(rgb), bg, prec, _ptr(out_T),
+                                _ptr(out_ncontrib), _ptr(dL_dimg), _ptr(g["means2d"]),
+                                _ptr(g["conics"]), _ptr(g["opacities"]), _ptr(g["rgb"]), _stream())
+    _check("gs_rasterize_bwd", st)
+    return g
+
+
+class RasterizeFn(torch.autograd.Function):
+    """Differentiable tile rasteriser: (means2d, conics, opacities, rgb) ->
+    image (3, H, W), for fixed per-tile lists.  Both directions run in
+    libgsmfma (gs_rasterize_fwd / gs_rasterize_bwd) with the same precision."""
+
+    @staticmethod
+    def forward(ctx, means2d, conics, opacities, rgb, ranges, sorted_ids, width, height,
+                precision="fp16_g2l_split", background=(0.0, 0.0, 0.0)):
+        r = Rasterizer(width, height, device=means2d.device)
+        means2d, conics = means2d.contiguous(), conics.contiguous()
+        opacities, rgb = opacities.contiguous(), rgb.contiguous()
+        r(ranges, sorted_ids, means2d, conics, opacities, rgb, precision, background)
+        ctx.save_for_backward(means2d, conics, opacities, rgb, ranges, sorted_ids, r.T, r.n_contrib)
+        ctx.cfg = (width, height, precision, tuple(background))
+        return r.rgb
+
+    @staticmethod
+    def backward(ctx, dL_dimg):
+        means2d, conics, opacities, rgb, ranges, sorted_ids, T, nc = ctx.saved_tensors
+        width, height, precision, background = ctx.cfg
+        g = rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, opacities, rgb, T, nc,
+                          dL_dimg.contiguous(), precision, background)
+        return g["means2d"], g["conics"], g["opacities"], g["rgb"], None, None, None, None, None, None
 
 
 def rasterize_beta(width, height, tile, ranges, sorted_ids, means2d, conics, opacities,

@@ -484,3 +484,60 @@ def test_bin_tiles_matches_full_binning(orc):
     r_t, i_t = orc.bin_tiles(sc.means2d, pre["radii"], sc.depths, W, H, tl)
     for j, t in enumerate(tl):
         assert np.array_equal(i_all[r_all[t, 0]:r_all[t, 1]], i_t[r_t[j, 0]:r_t[j, 1]])
+
+
+def _fd_case(orc, seed=1014, P=200, W=64, bg=(0.2, 0.1, 0.3)):
+    sc = scenegen.scene_2d(P, W, W, seed=seed, s_min=1.0, s_max=6.0)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, W)
+    ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, W)
+    params = dict(means2d=sc.means2d.astype(np.float64), conics=pre["conics"].copy(),
+                  opacities=sc.opacities.astype(np.float64), rgb=sc.rgb.astype(np.float64))
+    return sc, ranges, ids, params, bg
+
+
+def test_gradient_matches_finite_differences(orc):
+    """P11: the FP64 analytic gradient of L = sum w * C (random w) equals
+    central finite differences of the FP64 forward, for parameters whose
+    perturbation flips no cull/termination/clamp decision (detected by
+    comparing the decision counts and the smoothness of the difference
+    quotient at two step sizes)."""
+    W = 64
+    sc, ranges, ids, params, bg = _fd_case(orc)
+    w = np.random.default_rng(3).normal(0, 1, (3, W, W))
+
+    def loss(p):
+        out = orc.render(W, W, ranges, ids, p["means2d"], p["conics"], p["opacities"], p["rgb"], bg=bg)
+        return float(np.sum(w * out["rgb"])), out
+
+    grads = orc.render_backward(W, W, ranges, ids, params["means2d"], params["conics"],
+                                params["opacities"], params["rgb"], w, bg=bg)
+    _, nominal = loss(params)
+    rng = np.random.default_rng(4)
+    used = np.unique(ids)
+    checked = 0
+    for name, shape in (("means2d", 2), ("conics", 3), ("opacities", 1), ("rgb", 3)):
+        for _ in range(25):
+            g = int(rng.choice(used))
+            k = int(rng.integers(0, shape))
+            idx = (g, k) if shape > 1 else (g,)
+            val = params[name][idx]
+            h = 1e-6 * max(1.0, abs(val))
+            fd = []
+            ok = True
+            for hh in (h, 4 * h):
+                vals = []
+                for sgn in (1, -1):
+                    p2 = {kk: v.copy() for kk, v in params.items()}
+                    p2[name][idx] = val + sgn * hh
+                    L, out = loss(p2)
+                    for key in ("n_contrib", "f_blend", "f_cull", "term"):
+                        if not np.array_equal(out[key], nominal[key]):
+                            ok = False
+                    vals.append(L)
+                fd.append((vals[0] - vals[1]) / (2 * hh))
+            an = grads[name][idx]
+            if not ok or abs(fd[0] - fd[1]) > 1e-5 * max(1.0, abs(fd[0])):
+                continue  # a decision or the 0.99 clamp is crossed: not differentiable here
+            assert abs(an - fd[0]) <= 1e-5 * max(1.0, abs(fd[0])), (name, idx, an, fd)
+            checked += 1
+    assert checked >= 60
