@@ -148,99 +148,74 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of u32 keys with u32 values, one kernel per 8-bit
-// pass.  The global digit totals of every pass come from one histogram
-// kernel up front.  Within a pass, blocks take tickets in launch order (so a
-// block only ever waits for blocks that are already running), rank their
-// 4096 keys stably in LDS, publish their per-digit counts, and obtain the
-// exclusive prefix over earlier blocks by decoupled look-back on the
-// published words; then they write runs of equal digits to consecutive
-// global addresses.
+// Stable LSD radix sort pass (8-bit digit) of u32 keys with u32 values:
+// per-block digit histograms -> per-digit scan over blocks -> scatter.
 // ---------------------------------------------------------------------------
-constexpr int MAX_PASSES = 4;
-constexpr uint32_t ST_AGG = 1u << 30;       // word holds this block's count
-constexpr uint32_t ST_PREFIX = 1u << 31;    // word holds the inclusive prefix
-constexpr uint32_t ST_VALUE = (1u << 30) - 1u;
-constexpr uint32_t SPIN_LIMIT = 1u << 22;   // bounded wait; sets the error word
-constexpr int LOOKBACK = 16;                // predecessors read per look-back step
-constexpr int GTOT_COPIES = 8;              // histogram totals spread over 8 copies
-constexpr int HIST_ITEMS = 128;             // keys per thread in the histogram kernel
-constexpr int HIST_TILE = SORT_THREADS * HIST_ITEMS;
-
-__device__ __forceinline__ void st_store(uint32_t *p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t st_load(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Per-sort device state.  `gtot` is cleared by the stage's first kernel;
-// `status` and `tickets` by k_sort_hist, which runs before the passes.
-// The digit totals are accumulated into GTOT_COPIES copies (block b adds to
-// copy b mod 8) so that no counter takes more than a few dozen contended
-// device-scope atomics; readers sum the copies.
-struct SortState {
-    uint32_t *gtot;     // [GTOT_COPIES][MAX_PASSES][RADIX] global digit totals
-    uint32_t *tickets;  // [MAX_PASSES]
-    uint32_t *status;   // [MAX_PASSES][nblocks][RADIX] look-back words
-    uint32_t *error;    // [1] non-zero if a look-back wait hit its limit
-    uint32_t nblocks;
-};
-
-// Digit totals of every pass (HIST_TILE keys per block), and clearing of
-// the passes' look-back words and tickets (grid-stride).
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *__restrict__ keys,
-                                                            Count cnt, int npass, SortState st) {
-    __shared__ uint32_t h[MAX_PASSES][RADIX];
-#pragma unroll
-    for (int p = 0; p < MAX_PASSES; ++p) h[p][threadIdx.x] = 0;
-    const size_t nstatus = (size_t)npass * st.nblocks * RADIX;
-    for (size_t i = (size_t)blockIdx.x * SORT_THREADS + threadIdx.x; i < nstatus;
-         i += (size_t)gridDim.x * SORT_THREADS)
-        st.status[i] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x < MAX_PASSES) st.tickets[threadIdx.x] = 0u;
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                             Count cnt, int shift, uint32_t dmask,
+                                                             uint32_t *__restrict__ hist,
+                                                             uint32_t nblocks) {
+    __shared__ uint32_t h[RADIX];
+    uint32_t n = cnt.get();
+    h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t n = cnt.get();
-    const size_t base = (size_t)blockIdx.x * HIST_TILE;
+    size_t base = (size_t)blockIdx.x * SORT_TILE;
     if (base < n) {
-        for (int k = 0; k < HIST_ITEMS; ++k) {
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i >= n) break;
-            uint32_t key = keys[i];
-            for (int p = 0; p < npass; ++p) atomicAdd(&h[p][(key >> (RADIX_BITS * p)) & (RADIX - 1)], 1u);
+            if (i < n) atomicAdd(&h[(keys[i] >> shift) & dmask], 1u);
         }
     }
     __syncthreads();
-    uint32_t *g = st.gtot + (size_t)(blockIdx.x % GTOT_COPIES) * MAX_PASSES * RADIX;
-    for (int p = 0; p < npass; ++p) {
-        uint32_t c = h[p][threadIdx.x];
-        if (c) atomicAdd(&g[p * RADIX + threadIdx.x], c);
-    }
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
+// One block per digit: exclusive scan of that digit's counts over blocks, in
+// place; the digit total goes to totals[d].
+__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict__ hist,
+                                                            uint32_t nblocks,
+                                                            uint32_t *__restrict__ totals) {
+    __shared__ uint32_t lds[WAVES];
+    uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += SORT_THREADS) {
+        uint32_t i = b0 + threadIdx.x;
+        uint32_t v = i < nblocks ? row[i] : 0u;
+        uint32_t ex;
+        uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
+        if (i < nblocks) row[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, Count cnt, int pass, SortState st) {
+    uint32_t *__restrict__ vout, Count cnt, int shift, int dbits, const uint32_t *__restrict__ hist_scan,
+    const uint32_t *__restrict__ totals, uint32_t nblocks) {
     __shared__ uint32_t wcnt[WAVES][RADIX];
     __shared__ uint32_t gbase[RADIX];   // global position of this block's first key of digit d
     __shared__ uint32_t lstart[RADIX];  // local position of this block's first key of digit d
     __shared__ uint32_t skey[SORT_TILE];
     __shared__ uint32_t sval[SORT_TILE];
     __shared__ uint32_t lds_scan[WAVES];
-    __shared__ uint32_t s_ticket;
-    const int shift = RADIX_BITS * pass;
-    if (threadIdx.x == 0) s_ticket = atomicAdd(&st.tickets[pass], 1u);
+    uint32_t n = cnt.get();
+    size_t base = (size_t)blockIdx.x * SORT_TILE;
+    if (base >= n) return;  // whole block idle: uniform exit
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
+    {
+        // exclusive scan of the global digit totals -> digit base
+        uint32_t t = totals[threadIdx.x], ex;
+        block_excl_scan<uint32_t>(t, ex, lds_scan);
+        gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
+    }
     __syncthreads();
-    const uint32_t blk = s_ticket;
-    const uint32_t n = cnt.get();
-    const size_t base = (size_t)blk * SORT_TILE;
-    if (base >= n) return;  // this and every later ticket is empty: uniform exit
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 
     uint32_t key[WAVE_CHUNKS], val[WAVE_CHUNKS], pos[WAVE_CHUNKS];
-    const size_t wbase = base + (size_t)w * WAVE_ITEMS;
+    size_t wbase = base + (size_t)w * WAVE_ITEMS;
 #pragma unroll
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
@@ -248,19 +223,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
         key[c] = ok ? kin[i] : 0u;
         val[c] = ok ? vin[i] : 0u;
     }
-    // stable rank inside the block: per wave, chunk by chunk, lanes with
-    // equal digits found by 8 ballots
 #pragma unroll
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n;
-        uint32_t d = (key[c] >> shift) & (RADIX - 1);
-        uint64_t peers = __ballot(ok);
-#pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
+        const uint32_t dmask = (1u << dbits) - 1u;
+        uint32_t d = (key[c] >> shift) & dmask;
+        const uint64_t valid = __ballot(ok);
+        uint64_t peers = valid;
+        // lanes with equal digits: one ballot per digit bit; a bit that is the
+        // same in every valid lane (common: nearby keys) separates nothing
+        for (int b = 0; b < dbits; ++b) {
             bool bit = (d >> b) & 1u;
-            uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            uint64_t m = __ballot(bit) & valid;
+            if (m != 0ull && m != valid) peers &= bit ? m : ~m;
         }
         uint32_t rank = gs::lanes_below(peers);
         uint32_t before = ok ? wcnt[w][d] : 0u;
@@ -269,65 +245,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     }
     __syncthreads();
     {
-        const uint32_t d = threadIdx.x;
-        uint32_t cntd = 0;
+        // per digit: prefix over waves, and the block's digit-major local start
+        uint32_t d = threadIdx.x, off = 0;
 #pragma unroll
         for (int i = 0; i < WAVES; ++i) {
             uint32_t t = wcnt[i][d];
-            wcnt[i][d] = cntd;
-            cntd += t;
+            wcnt[i][d] = off;
+            off += t;
         }
-        // publish this block's count, then look back for the prefix:
-        // LOOKBACK predecessors are read at once and consumed in order until
-        // an inclusive prefix is found (done) or a word is still empty (wait
-        // and re-read from there)
-        const uint32_t *col = st.status + (size_t)pass * st.nblocks * RADIX + d;
-        uint32_t *my = st.status + ((size_t)pass * st.nblocks + blk) * RADIX + d;
-        uint32_t excl = 0;
-        if (blk == 0) {
-            st_store(my, ST_PREFIX | cntd);
-        } else {
-            st_store(my, ST_AGG | cntd);
-            int64_t j = (int64_t)blk - 1;
-            uint32_t spins = 0;
-            for (;;) {
-                uint32_t wv[LOOKBACK];
-#pragma unroll
-                for (int k = 0; k < LOOKBACK; ++k)
-                    wv[k] = (j - k >= 0) ? st_load(col + (size_t)(j - k) * RADIX) : ST_PREFIX;
-                int consumed = 0;
-                bool found = false;
-#pragma unroll
-                for (int k = 0; k < LOOKBACK; ++k) {
-                    if (found || consumed < k) continue;
-                    uint32_t w = wv[k];
-                    if ((w & (ST_AGG | ST_PREFIX)) == 0u) continue;  // empty: stop consuming here
-                    excl += w & ST_VALUE;
-                    consumed = k + 1;
-                    if (w & ST_PREFIX) found = true;
-                }
-                if (found) break;
-                j -= consumed;
-                if (consumed == 0) {
-                    if (++spins > SPIN_LIMIT) {
-                        atomicOr(st.error, 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            st_store(my, ST_PREFIX | (excl + cntd));
-        }
-        // digit base = exclusive scan of the global totals of this pass
-        uint32_t tot = 0;
-#pragma unroll
-        for (int c = 0; c < GTOT_COPIES; ++c) tot += st.gtot[((size_t)c * MAX_PASSES + pass) * RADIX + d];
         uint32_t ex;
-        block_excl_scan<uint32_t>(tot, ex, lds_scan);
-        gbase[d] = ex + excl;
-        uint32_t lex;
-        block_excl_scan<uint32_t>(cntd, lex, lds_scan);
-        lstart[d] = lex;
+        block_excl_scan<uint32_t>(off, ex, lds_scan);
+        lstart[d] = ex;
     }
     __syncthreads();
     // stage in LDS in (digit, original order) order ...
@@ -335,7 +263,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n) {
-            uint32_t d = (key[c] >> shift) & (RADIX - 1);
+            uint32_t d = (key[c] >> shift) & ((1u << dbits) - 1u);
             uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
             skey[lp] = key[c];
             sval[lp] = val[c];
@@ -343,10 +271,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     }
     __syncthreads();
     // ... and write runs of equal digits to consecutive global addresses
-    const uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
+    uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
-        uint32_t d = (k >> shift) & (RADIX - 1);
+        uint32_t d = (k >> shift) & ((1u << dbits) - 1u);
         uint32_t dst = gbase[d] + (lp - lstart[d]);
         kout[dst] = k;
         vout[dst] = sval[lp];
@@ -357,17 +285,26 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
-// Sorts on bits [0, bits) with ceil(bits/8) passes (at most 4); returns the
-// index of the buffer pair holding the result.  st.gtot must be zero.
-int radix_sort(SortBufs b, Count cnt, int bits, SortState st, hipStream_t s) {
-    int npass = (bits + RADIX_BITS - 1) / RADIX_BITS;
-    uint32_t hblocks = (uint32_t)(((size_t)st.nblocks * SORT_TILE + HIST_TILE - 1) / HIST_TILE);
-    hipLaunchKernelGGL(k_sort_hist, dim3(hblocks), dim3(SORT_THREADS), 0, s, b.k[0], cnt, npass, st);
-    int cur = 0;
+// Sorts on bits [0, bits) with ceil(bits/8) passes whose digit widths split
+// the bits evenly (13 tile bits: 7 + 6); returns the index of the buffer pair
+// holding the result.
+int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
+               hipStream_t s) {
+    uint32_t nblocks = (max_n + SORT_TILE - 1) / SORT_TILE;
+    if (nblocks == 0) nblocks = 1;
+    const int npass = (bits + RADIX_BITS - 1) / RADIX_BITS;
+    int cur = 0, shift = 0;
     for (int p = 0; p < npass; ++p) {
-        hipLaunchKernelGGL(k_onesweep, dim3(st.nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], b.v[cur],
-                           b.k[cur ^ 1], b.v[cur ^ 1], cnt, p, st);
+        const int dbits = (bits - shift + (npass - p) - 1) / (npass - p);
+        const uint32_t dmask = (1u << dbits) - 1u;
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], cnt,
+                           shift, dmask, hist, nblocks);
+        hipLaunchKernelGGL(k_hist_rows, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
+                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, dbits, hist, totals,
+                           nblocks);
         cur ^= 1;
+        shift += dbits;
     }
     return cur;
 }
@@ -389,11 +326,9 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     int gx, uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
                                                     uint2 *__restrict__ rects,
-                                                    uint32_t *__restrict__ ranges, int n2,
-                                                    uint32_t *__restrict__ clear, int nclear) {
+                                                    uint32_t *__restrict__ ranges, int n2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n2) ranges[i] = 0u;
-    if (i < nclear) clear[i] = 0u;
     if (i >= P) return;
     float d = depths[i];
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
@@ -535,14 +470,10 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
 
 // Workspace carve-up (every region 256-byte aligned).
 struct Layout {
-    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, tkey0, tkey1, tid, clear,
-        dstatus, tstatus, part, win, total;
-    uint32_t nwin, dblocks, tblocks;
+    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, tkey0, tkey1, tid, hist,
+        totals, part, win, total;
+    uint32_t nwin;
 };
-
-// Cleared region: [depth gtot | tile gtot | depth tickets | tile tickets | error]
-constexpr int GTOT_WORDS = GTOT_COPIES * MAX_PASSES * RADIX;
-constexpr int CLEAR_WORDS = 2 * GTOT_WORDS + 2 * MAX_PASSES + 1;
 
 Layout layout(uint32_t P, uint32_t cap) {
     Layout L{};
@@ -552,10 +483,8 @@ Layout layout(uint32_t P, uint32_t cap) {
         off = align_up(off + (bytes ? bytes : 4), 256);
         return o;
     };
-    L.dblocks = (P + SORT_TILE - 1) / SORT_TILE;
-    L.tblocks = (cap + SORT_TILE - 1) / SORT_TILE;
-    if (L.dblocks == 0) L.dblocks = 1;
-    if (L.tblocks == 0) L.tblocks = 1;
+    uint32_t maxn = P > cap ? P : cap;
+    uint32_t nblocks = (maxn + SORT_TILE - 1) / SORT_TILE + 1;
     L.nwin = (cap + EMIT_TILE - 1) / EMIT_TILE + 2;
     L.dkey0 = take(4ull * P);
     L.dkey1 = take(4ull * P);
@@ -568,9 +497,8 @@ Layout layout(uint32_t P, uint32_t cap) {
     L.tkey0 = take(4ull * cap);
     L.tkey1 = take(4ull * cap);
     L.tid = take(4ull * cap);
-    L.clear = take(4ull * CLEAR_WORDS);
-    L.dstatus = take(4ull * MAX_PASSES * L.dblocks * RADIX);
-    L.tstatus = take(4ull * MAX_PASSES * L.tblocks * RADIX);
+    L.hist = take(4ull * RADIX * nblocks);
+    L.totals = take(4ull * RADIX);
     L.part = take(8ull * ((P + SORT_TILE - 1) / SORT_TILE + 2));
     L.win = take(4ull * L.nwin);
     L.total = off;
@@ -588,7 +516,7 @@ int ceil_log2(uint32_t x) {
 extern "C" size_t gs_bin_sort_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
                                               int32_t height) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
-    if (capacity >= 0x40000000u || P >= 0x40000000) return 0;
+    if (capacity >= 0x80000000u) return 0;
     return layout((uint32_t)P, capacity).total;
 }
 
@@ -605,7 +533,7 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     if (P > 0 && (!means2d || !radii || !depths || !gs::aligned(means2d, 8) ||
                   !gs::aligned(radii, 4) || !gs::aligned(depths, 4)))
         return GS_ERR_INVALID_ARG;
-    if (capacity >= 0x40000000u || P >= 0x40000000) return GS_ERR_INVALID_ARG;
+    if (capacity >= 0x80000000u) return GS_ERR_INVALID_ARG;
     if (capacity > 0 && (!sorted_ids || !gs::aligned(sorted_ids, 4))) return GS_ERR_INVALID_ARG;
     Layout L = layout((uint32_t)P, capacity);
     if (workspace_bytes < L.total) return GS_ERR_CAPACITY;
@@ -616,28 +544,23 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     int gx = gs::grid_x(width), gy = gs::grid_y(height);
     int ntiles = gx * gy;
 
-    uint32_t *clear = U(L.clear);
-    SortState dst{clear, clear + 2 * GTOT_WORDS, U(L.dstatus), clear + 2 * GTOT_WORDS + 2 * MAX_PASSES,
-                  L.dblocks};
-    SortState tst{clear + GTOT_WORDS, clear + 2 * GTOT_WORDS + MAX_PASSES, U(L.tstatus),
-                  clear + 2 * GTOT_WORDS + 2 * MAX_PASSES, L.tblocks};
     if (P == 0) {
         hipLaunchKernelGGL(k_depth_keys, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, 0,
                            (const float2 *)nullptr, (const int *)nullptr, (const float *)nullptr,
                            width, height, gx, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                           (uint2 *)nullptr, tile_ranges, 2 * ntiles, clear, 0);
+                           (uint2 *)nullptr, tile_ranges, 2 * ntiles);
         hipMemsetAsync(d_num_splats, 0, 4, s);
         return gs::launch_status();
     }
     const float2 *m2 = (const float2 *)means2d;
     int nthr = P > 2 * ntiles ? P : 2 * ntiles;
-    if (nthr < CLEAR_WORDS) nthr = CLEAR_WORDS;
-    // 1. depth keys, rectangles, cleared ranges and sort state; depth order
+    // 1. depth keys, rectangles, cleared ranges; depth order of the Gaussians
     hipLaunchKernelGGL(k_depth_keys, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2, radii,
                        depths, width, height, gx, U(L.dkey0), U(L.did0), (uint2 *)(ws + L.rects),
-                       tile_ranges, 2 * ntiles, clear, CLEAR_WORDS);
+                       tile_ranges, 2 * ntiles);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
-    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, 32, dst, s);
+    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32, U(L.hist),
+                          U(L.totals), s);
     const uint32_t *order = db.v[dcur];
     // 2. counts in depth order, scan (+ window owners), expansion
     int pblocks = (P + 255) / 256;
@@ -665,7 +588,7 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     Count nc{0u, d_num_splats, capacity};
-    int tcur = radix_sort(tb, nc, tbits, tst, s);
+    int tcur = radix_sort(tb, nc, capacity, tbits, U(L.hist), U(L.totals), s);
     // 4. ranges
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
     hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
