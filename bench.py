@@ -102,6 +102,60 @@ def cpu_baseline(scene, cam, pre_gpu, total_pairs: int, budget_s: float = 20.0):
             "ms_per_frame": frame_s * 1e3}
 
 
+def train_step(args):
+    """Forward + backward of the rasteriser with an L1 loss (1600x1064,
+    1M Gaussians, forward exponent on FP16 matrix cores, FP32 gradients):
+    preprocess -> bin/sort -> rasterize_fwd -> L1 gradient -> rasterize_bwd."""
+    import torch
+
+    import paper_2505_24796_amd as gs
+    import scenegen
+    cfg = scenegen.CONFIGS["train_1600x1064_1M"]
+    W, H = cfg["width"], cfg["height"]
+    sc = scenegen.make_scene(cfg)
+    c = scenegen.make_camera(cfg)
+    cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    means, scales, quats, sh, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), dev(sc.opacities)
+    target = torch.rand(3, H, W, device="cuda")
+    pre = gs.preprocess(means, scales, quats, sh, cam)
+    probe = gs.BinSorter(sc.P, 0, W, H)
+    probe(pre["means2d"], pre["radii"], pre["depths"])
+    bs = gs.BinSorter(sc.P, int(probe.n_splats() * 1.1) + 1024, W, H)
+    rz = gs.Rasterizer(W, H)
+    prec = "fp16_g2l_split"
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        p = gs.preprocess(means, scales, quats, sh, cam)
+        bs(p["means2d"], p["radii"], p["depths"])
+        rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], prec)
+        if ev:
+            ev[1].record()
+        dimg = torch.sign(rz.rgb - target) / rz.rgb.numel()
+        if ev:
+            ev[2].record()
+        gs.rasterize_bwd(W, H, bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"],
+                         rz.T, rz.n_contrib, dimg, prec)
+        if ev:
+            ev[3].record()
+
+    for _ in range(3):
+        step()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(10)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in evs:
+        step(e)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / len(evs)
+    fwd = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    bwd = float(np.median([e[2].elapsed_time(e[3]) for e in evs]))
+    return {"workload": "train_1600x1064_1M", "ms_per_step": wall, "forward_ms": fwd,
+            "raster_bwd_ms": bwd, "splats": probe.n_splats(), "precision": prec}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +164,8 @@ def main():
     ap.add_argument("--workload", default="fwd_1080p_1M")
     ap.add_argument("--precision", default="fp16_g2l_split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -199,6 +255,28 @@ def main():
     log(f"[bench] timing fp32 baseline")
     wall32, med32, mean32 = timed("fp32")
     torch.cuda.synchronize()
+
+    # precision sweep (the paper's EarlyCull / precision ablations): raster
+    # kernel only, same lists, PSNR against the FP32 path's image
+    sweep = {}
+    if not args.no_sweep:
+        p2 = gs.preprocess(means, scales, quats, sh, cam)
+        bs(p2["means2d"], p2["radii"], p2["depths"])
+        for prec in gs.PRECISIONS:
+            for _ in range(3):
+                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], opac, p2["rgb"], prec)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ts = []
+            for _ in range(10):
+                ev0.record()
+                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], opac, p2["rgb"], prec)
+                ev1.record()
+                torch.cuda.synchronize()
+                ts.append(ev0.elapsed_time(ev1))
+            m = float(torch.mean((rz.rgb - ref_img) ** 2))
+            sweep[prec] = {"raster_ms": float(np.median(ts)),
+                           "psnr_vs_fp32_db": 10 * np.log10(1.0 / m) if m > 0 else float("inf")}
+        log(f"[bench] sweep {sweep}")
     mse = float(torch.mean((img - ref_img) ** 2))
     psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
     assert int(bs.n_splats()) <= capacity
@@ -238,7 +316,10 @@ def main():
         "speedup_raster_vs_fp32": mean32[2] / mean[2],
         "psnr_vs_fp32_db": psnr,
         "raster_pairs_per_s": pairs / raster_s,
+        "sweep": sweep,
     }
+    if not args.no_train:
+        out["train_step"] = train_step(args)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(scene, cam_np, pre, pairs)
