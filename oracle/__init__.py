@@ -137,41 +137,61 @@ def preprocess_2d(means2d, cov2d, W: int, H: int) -> dict:
     return out
 
 
-def bin_splats(means2d, radii, depths, W: int, H: int):
-    """Per-tile splat lists: returns (ranges (ntiles, 2) uint32, ids (N,) uint32)."""
+def _precise_args(conics, opac):
+    if conics is None:
+        return None, None, c_void_p(0), c_void_p(0)
+    c, o = _f64(conics), _f64(opac)
+    return c, o, _p(c), _p(o)
+
+
+def bin_splats(means2d, radii, depths, W: int, H: int, conics=None, opac=None):
+    """Per-tile splat lists: returns (ranges (ntiles, 2) uint32, ids (N,) uint32).
+    With ``conics`` and ``opac`` the precise Gaussian-tile test is applied
+    inside the 3-sigma rectangle."""
     m, r, d = _f32(means2d), _i32(radii), _f32(depths)
+    keep = _precise_args(conics, opac)
     P = m.shape[0]
     gx, gy = grid(W, H)
     ranges = np.zeros((gx * gy, 2), np.uint32)
     # first call counts (capacity 0), second fills
     N = int(lib().orc_bin(c_int(P), _p(m), _p(r), _p(d), c_int(W), c_int(H), _p(ranges),
-                          c_void_p(0), c_int64(0)))
+                          c_void_p(0), c_int64(0), keep[2], keep[3]))
     if N < 0:
         raise MemoryError("oracle binning: allocation failed")
     ids = np.zeros(max(N, 1), np.uint32)
     N2 = int(lib().orc_bin(c_int(P), _p(m), _p(r), _p(d), c_int(W), c_int(H), _p(ranges),
-                           _p(ids), c_int64(N)))
+                           _p(ids), c_int64(N), keep[2], keep[3]))
     assert N2 == N
     return ranges, ids[:N]
 
 
-def bin_tiles(means2d, radii, depths, W: int, H: int, tiles):
+def bin_tiles(means2d, radii, depths, W: int, H: int, tiles, conics=None, opac=None):
     """Per-tile splat lists for the listed tiles only (same rule and order as
     bin_splats): returns (ranges (len(tiles), 2) uint32, ids uint32)."""
     m, r, d = _f32(means2d), _i32(radii), _f32(depths)
+    keep = _precise_args(conics, opac)
     tl = _i32(tiles)
     P = m.shape[0]
     ranges = np.zeros((len(tl), 2), np.uint32)
     L = lib()
     L.orc_bin_tiles.restype = c_int64
     N = int(L.orc_bin_tiles(c_int(P), _p(m), _p(r), _p(d), c_int(W), c_int(H), c_int(len(tl)),
-                            _p(tl), _p(ranges), c_void_p(0), c_int64(0)))
+                            _p(tl), _p(ranges), c_void_p(0), c_int64(0), keep[2], keep[3]))
     if N < 0:
         raise MemoryError("oracle binning: allocation failed")
     ids = np.zeros(max(N, 1), np.uint32)
     L.orc_bin_tiles(c_int(P), _p(m), _p(r), _p(d), c_int(W), c_int(H), c_int(len(tl)), _p(tl),
-                    _p(ranges), _p(ids), c_int64(N))
+                    _p(ranges), _p(ids), c_int64(N), keep[2], keep[3])
     return ranges, ids[:N]
+
+
+def tile_slack(mx: float, my: float, conic, opac: float, tx: int, ty: int, W: int, H: int) -> float:
+    """ln o - qmin/2 + ln 255 of the precise Gaussian-tile test (>= 0: kept)."""
+    L = lib()
+    L.orc_tile_slack.restype = ctypes.c_double
+    S = _f64(conic)
+    return float(L.orc_tile_slack(ctypes.c_double(mx), ctypes.c_double(my), _p(S),
+                                  ctypes.c_double(opac), c_int(tx), c_int(ty), c_int(W), c_int(H)))
 
 
 def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0, 0.0),

@@ -331,10 +331,80 @@ static int splat_cmp(const void *pa, const void *pb)
     return 0;
 }
 
+/* Precise Gaussian-tile intersection (the tighter binning of the pipelines
+ * TC-GS composes with, Sec. 2 and Table 4): keep a tile of the 3-sigma
+ * rectangle only if the raw opacity o exp(-q/2), q = d^T S d, d = p - mu',
+ * reaches the culling threshold 1/255 of Algorithm 1 somewhere in the
+ * tile's pixel box [16 tx, min(16 tx + 15, W - 1)] x [same in y] (the
+ * convex hull of its pixel coordinates).  A tile that fails is culled at
+ * each of its pixels, so dropping it changes no output.
+ * The largest o exp(-q/2) over the box is at the box minimum of the convex
+ * form q: zero if mu' is inside; otherwise on an edge, where q restricted to
+ * the edge is a 1D quadratic minimised at its vertex clamped to the edge. */
+static double box_min_q(double mx, double my, const double *S, double X0, double X1, double Y0,
+                        double Y1)
+{
+    double a = S[0], b = S[1], c = S[2];
+    if (mx >= X0 && mx <= X1 && my >= Y0 && my <= Y1) return 0.0;
+    double best = INFINITY;
+    for (int e = 0; e < 4; ++e) {
+        double dx, dy;
+        if (e < 2) {              /* vertical edge x = X0 or X1 */
+            dx = (e == 0 ? X0 : X1) - mx;
+            dy = -b * dx / c;
+            if (dy < Y0 - my) dy = Y0 - my;
+            if (dy > Y1 - my) dy = Y1 - my;
+        } else {                  /* horizontal edge y = Y0 or Y1 */
+            dy = (e == 2 ? Y0 : Y1) - my;
+            dx = -b * dy / a;
+            if (dx < X0 - mx) dx = X0 - mx;
+            if (dx > X1 - mx) dx = X1 - mx;
+        }
+        double q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
+        if (q < best) best = q;
+    }
+    return best;
+}
+
+static int tile_reaches_cull(double mx, double my, const double *S, double o, int tx, int ty,
+                             int W, int H)
+{
+    double X0 = ORC_TILE * tx, Y0 = ORC_TILE * ty;
+    double X1 = X0 + ORC_TILE - 1, Y1 = Y0 + ORC_TILE - 1;
+    if (X1 > W - 1) X1 = W - 1;
+    if (Y1 > H - 1) Y1 = H - 1;
+    double q = box_min_q(mx, my, S, X0, X1, Y0, Y1);
+    return o * exp(-0.5 * q) >= 1.0 / 255.0;
+}
+
+/* Slack of the precise test for one (Gaussian, tile): ln o - qmin/2 + ln 255
+ * (>= 0: kept).  For tests that compare near-threshold decisions. */
+double orc_tile_slack(double mx, double my, const double *S, double o, int tx, int ty, int W, int H)
+{
+    double X0 = ORC_TILE * tx, Y0 = ORC_TILE * ty;
+    double X1 = X0 + ORC_TILE - 1, Y1 = Y0 + ORC_TILE - 1;
+    if (X1 > W - 1) X1 = W - 1;
+    if (Y1 > H - 1) Y1 = H - 1;
+    return log(o) - 0.5 * box_min_q(mx, my, S, X0, X1, Y0, Y1) + log(255.0);
+}
+
+/* Does Gaussian i cover tile (tx, ty)?  3-sigma rectangle rule, plus the
+ * precise test when conics/opac are given. */
+static int covers(const float *means2d, const double *conics, const double *opac, int i, int tx,
+                  int ty, int W, int H)
+{
+    if (!conics) return 1;
+    return tile_reaches_cull(means2d[2 * i], means2d[2 * i + 1], conics + 3 * i, opac[i], tx, ty,
+                             W, H);
+}
+
 /* Returns N (total splats).  Writes min(N, capacity) sorted ids and, when
- * N <= capacity, ranges[2*tile] = start, ranges[2*tile+1] = end. */
+ * N <= capacity, ranges[2*tile] = start, ranges[2*tile+1] = end.  With
+ * conics (s11, s12, s22 per Gaussian) and opac non-NULL, a rectangle tile is
+ * kept only if it passes the precise intersection test above. */
 int64_t orc_bin(int P, const float *means2d, const int32_t *radii, const float *depths,
-                int W, int H, uint32_t *ranges, uint32_t *ids, int64_t capacity)
+                int W, int H, uint32_t *ranges, uint32_t *ids, int64_t capacity,
+                const double *conics, const double *opac)
 {
     int gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
     int ntiles = gx * gy;
@@ -342,7 +412,10 @@ int64_t orc_bin(int P, const float *means2d, const int32_t *radii, const float *
     for (int i = 0; i < P; ++i) {
         int tx0, tx1, ty0, ty1;
         if (!isfinite(depths[i])) continue;
-        N += tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], W, H, &tx0, &tx1, &ty0, &ty1);
+        if (!tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], W, H, &tx0, &tx1, &ty0, &ty1)) continue;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx)
+                N += covers(means2d, conics, opac, i, tx, ty, W, H);
     }
     for (int t = 0; t < 2 * ntiles; ++t) ranges[t] = 0;
     if (N == 0 || capacity <= 0) return N;
@@ -355,6 +428,7 @@ int64_t orc_bin(int P, const float *means2d, const int32_t *radii, const float *
         if (!tile_rect(means2d[2 * i], means2d[2 * i + 1], radii[i], W, H, &tx0, &tx1, &ty0, &ty1)) continue;
         for (int ty = ty0; ty <= ty1; ++ty)
             for (int tx = tx0; tx <= tx1; ++tx) {
+                if (!covers(means2d, conics, opac, i, tx, ty, W, H)) continue;
                 sp[k].tile = ty * gx + tx;
                 sp[k].depth = depths[i] == 0.0f ? 0.0f : depths[i]; /* -0 equals +0 */
                 sp[k].id = i;
@@ -381,7 +455,7 @@ int64_t orc_bin(int P, const float *means2d, const int32_t *radii, const float *
  * in ids.  Returns the number of kept splats (writes at most capacity ids). */
 int64_t orc_bin_tiles(int P, const float *means2d, const int32_t *radii, const float *depths,
                       int W, int H, int ntl, const int32_t *tile_list, uint32_t *ranges,
-                      uint32_t *ids, int64_t capacity)
+                      uint32_t *ids, int64_t capacity, const double *conics, const double *opac)
 {
     int gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
     int ntiles = gx * gy;
@@ -400,6 +474,7 @@ int64_t orc_bin_tiles(int P, const float *means2d, const int32_t *radii, const f
             for (int tx = tx0; tx <= tx1; ++tx) {
                 int j = slot[ty * gx + tx];
                 if (j < 0) continue;
+                if (!covers(means2d, conics, opac, i, tx, ty, W, H)) continue;
                 if (k == cap) {
                     cap *= 2;
                     splat_t *n2 = (splat_t *)realloc(sp, (size_t)cap * sizeof(splat_t));

@@ -486,6 +486,82 @@ def test_bin_tiles_matches_full_binning(orc):
         assert np.array_equal(i_all[r_all[t, 0]:r_all[t, 1]], i_t[r_t[j, 0]:r_t[j, 1]])
 
 
+def _subsequence(a, b):
+    """a is a subsequence of b (same relative order)."""
+    it = iter(b.tolist())
+    return all(x in it for x in a.tolist())
+
+
+def test_precise_binning_brute_force(orc):
+    """Precise Gaussian-tile intersection: every tile list is an ordered
+    subsequence of the 3-sigma list, and it keeps every Gaussian whose raw
+    opacity o exp(-q/2) reaches 1/255 at some pixel of the tile (brute force
+    over the tile's pixels in FP64), so nothing that can contribute is lost."""
+    W, H = 96, 80
+    sc = scenegen.scene_2d(300, W, H, seed=61, o_min=0.01, o_max=0.99)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+    r3, i3 = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+    rp, ip = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H, conics=pre["conics"],
+                            opac=sc.opacities)
+    assert 0 < len(ip) < 0.8 * len(i3)
+    gx = (W + 15) // 16
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    for t in range(r3.shape[0]):
+        full, kept = i3[r3[t, 0]:r3[t, 1]], ip[rp[t, 0]:rp[t, 1]]
+        assert _subsequence(kept, full)
+        tx, ty = t % gx, t // gx
+        px = xs[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16].ravel()
+        py = ys[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16].ravel()
+        for i in full:
+            a, b, c = pre["conics"][i]
+            dx, dy = px - sc.means2d[i, 0], py - sc.means2d[i, 1]
+            q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+            reaches = np.any(sc.opacities[i] * np.exp(-0.5 * q) >= 1.0 / 255.0)
+            if reaches:
+                assert i in kept, (t, i)
+
+
+def test_precise_binning_render_invariant(orc):
+    """Dropping the tiles that fail the precise test changes no pixel of the
+    FP64 render (the dropped fragments are culled everywhere)."""
+    W, H = 256, 256
+    sc = scenegen.scene_2d(2000, W, H, seed=1001)
+    pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+    r3, i3 = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+    rp, ip = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H, conics=pre["conics"],
+                            opac=sc.opacities)
+    assert len(ip) < len(i3)
+    a = orc.render(W, H, r3, i3, sc.means2d, pre["conics"], sc.opacities, sc.rgb)
+    b = orc.render(W, H, rp, ip, sc.means2d, pre["conics"], sc.opacities, sc.rgb)
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["T"], b["T"])
+
+
+@pytest.mark.parametrize("sigma,keeps_right", [(3.2, True), (3.1, False)])
+def test_precise_binning_closed_form(orc, sigma, keeps_right):
+    """Isotropic Gaussian at (8, 8), opacity 0.1: the raw opacity reaches
+    1/255 out to radius R = sigma sqrt(2 ln 25.5) = 2.5456 sigma, so the tile
+    to its right (x >= 16) is kept iff 8 + R >= 16 (sigma 3.2: R = 8.146;
+    3.1: R = 7.891); the diagonal tile (box corner at distance 8 sqrt 2) is
+    never kept; the 3-sigma rectangle (r = 10) covers all four tiles."""
+    W = H = 48
+    mu = np.array([[8.0, 8.0]], np.float32)
+    cov = np.array([[sigma * sigma, 0.0, sigma * sigma]], np.float32)
+    o = np.array([0.1], np.float32)
+    pre = orc.preprocess_2d(mu, cov, W, H)
+    assert pre["radii"][0] == 10
+    d = np.array([1.0], np.float32)
+    r3, _ = orc.bin_splats(mu, pre["radii"], d, W, H)
+    rp, _ = orc.bin_splats(mu, pre["radii"], d, W, H, conics=pre["conics"], opac=o)
+    n3 = r3[:, 1] - r3[:, 0]
+    npr = rp[:, 1] - rp[:, 0]
+    assert list(np.nonzero(n3)[0]) == [0, 1, 3, 4]
+    expect = [0, 1, 3] if keeps_right else [0]
+    assert list(np.nonzero(npr)[0]) == expect
+    R = sigma * math.sqrt(2 * math.log(25.5))
+    assert (8 + R >= 16) == keeps_right
+    assert (orc.tile_slack(8.0, 8.0, pre["conics"][0], 0.1, 1, 0, W, H) >= 0) == keeps_right
+
+
 def _fd_case(orc, seed=1014, P=200, W=64, bg=(0.2, 0.1, 0.3)):
     sc = scenegen.scene_2d(P, W, W, seed=seed, s_min=1.0, s_max=6.0)
     pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, W)
