@@ -47,7 +47,8 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-RASTER_SOURCES = ["paper_2505_24796_amd/csrc/raster.hip", "paper_2505_24796_amd/csrc/common.h"]
+RASTER_SOURCES = ["paper_2505_24796_amd/csrc/raster.hip", "paper_2505_24796_amd/csrc/raster_tile.h",
+                  "paper_2505_24796_amd/csrc/raster_common.h", "paper_2505_24796_amd/csrc/common.h"]
 
 
 def read_traffic(precision: str):
@@ -156,6 +157,95 @@ def train_step(args):
             "raster_bwd_ms": bwd, "splats": probe.n_splats(), "precision": prec}
 
 
+def multiview(args):
+    """Serving many cameras of one scene (2M Gaussians, 16 orbit cameras at
+    640x480 / 1280x720 / 1920x1080 / 2560x1440): one multi-view preprocess,
+    per-view bin/sort and ONE persistent batched raster launch per frame,
+    the whole frame captured in a hipGraph; the launch shape is autotuned
+    first.  Per-view latency = device wall clock from the frame's start to
+    the view's last tile."""
+    import torch
+
+    import paper_2505_24796_amd as gs
+    from paper_2505_24796_amd import autotune
+    import scenegen
+    cfg = scenegen.CONFIGS["multiview_2M_16"]
+    log(f"[bench] multiview: generating P={cfg['P']}, {cfg['n_views']} views")
+    sc = scenegen.make_scene(cfg)
+    cams = [gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, c.width, c.height, campos=c.campos)
+            for c in scenegen.multiview_cameras(cfg)]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    scene = dict(means3d=dev(sc.means), scales=dev(sc.scales), quats=dev(sc.quats),
+                 sh=dev(sc.sh), opacities=dev(sc.opacities))
+    del sc
+    mv = gs.MultiViewRenderer(scene, cams, precision=args.precision)
+    tuned = autotune.tune_batched(mv, reps=3, warmup=1)
+    log(f"[bench] multiview tuned shape {tuned['best']}")
+
+    # stage split (eager, HIP events)
+    def stage_times(n=5):
+        rows = []
+        for _ in range(n):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            mv.preprocess()
+            ev[1].record()
+            mv.bin_sort()
+            ev[2].record()
+            mv.raster()
+            ev[3].record()
+            torch.cuda.synchronize()
+            rows.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]),
+                         ev[2].elapsed_time(ev[3])])
+        return np.median(np.array(rows), axis=0)
+
+    st = stage_times()
+    per_view_raster = float(np.median(autotune.time_ms(mv.raster_per_view, reps=5, warmup=1)))
+    single_pre = float(np.median(autotune.time_ms(
+        lambda: [gs.preprocess(scene["means3d"], scene["scales"], scene["quats"], scene["sh"], c)
+                 for c in cams], reps=3, warmup=1)))
+
+    g = mv.capture()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    # latency: one replay at a time, clocks read after each
+    lat = []
+    for _ in range(10):
+        g.replay()
+        torch.cuda.synchronize()
+        lat.extend(mv.latencies_ms())
+    # throughput: back-to-back replays
+    K = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(K):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / K
+    ms = e0.elapsed_time(e1) / K
+    eager = float(np.median(autotune.time_ms(mv.frame, reps=5, warmup=1)))
+    assert not any(mv.overflowed())
+    lat = np.array(lat)
+    return {"workload": "multiview_2M_16", "gaussians": cfg["P"], "views": mv.V,
+            "resolutions": [f"{c.width}x{c.height}" for c in cams],
+            "splats_per_view": mv.n_splats(), "precision": args.precision,
+            "tuned_shape": tuned["best"], "tune_table": tuned["table"],
+            "graph_ms_per_frame": ms, "graph_wall_ms_per_frame": wall,
+            "frames_per_s": 1e3 / ms, "views_per_s": mv.V * 1e3 / ms,
+            "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_max": float(lat.max()),
+            "eager_ms_per_frame": eager,
+            "stages_ms": {"preprocess_multiview": st[0], "bin_sort_all_views": st[1],
+                          "raster_batched": st[2]},
+            "raster_one_launch_per_view_ms": per_view_raster,
+            "preprocess_one_call_per_view_ms": single_pre}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +256,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--no-precise", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -277,6 +369,50 @@ def main():
             sweep[prec] = {"raster_ms": float(np.median(ts)),
                            "psnr_vs_fp32_db": 10 * np.log10(1.0 / m) if m > 0 else float("inf")}
         log(f"[bench] sweep {sweep}")
+    # the same frame with precise Gaussian-tile intersection in the binning
+    # (fewer splats; same image up to near-threshold fragments)
+    precise = None
+    if not args.no_precise:
+        pp = gs.preprocess(means, scales, quats, sh, cam)
+        probe_p = gs.BinSorter(P, 0, W, H, precise=True)
+        probe_p(pp["means2d"], pp["radii"], pp["depths"], pp["conics"], opac)
+        Np = probe_p.n_splats()
+        bsp = gs.BinSorter(P, int(Np * 1.1) + 1024, W, H, precise=True)
+        rzp = gs.Rasterizer(W, H)
+
+        def frame_p(ev=None):
+            if ev is not None:
+                ev[0].record()
+            p = gs.preprocess(means, scales, quats, sh, cam)
+            if ev is not None:
+                ev[1].record()
+            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], opac)
+            if ev is not None:
+                ev[2].record()
+            rzp(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"],
+                args.precision)
+            if ev is not None:
+                ev[3].record()
+
+        for _ in range(args.warmup):
+            frame_p()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in evs:
+            frame_p(e)
+        torch.cuda.synchronize()
+        wallp = (time.perf_counter() - t0) * 1e3 / args.steps
+        stp = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]),
+                         e[2].elapsed_time(e[3])] for e in evs]).mean(axis=0)
+        mp = float(torch.mean((rzp.rgb - ref_img) ** 2))
+        precise = {"splats": Np, "splats_3sigma": N, "ms_per_frame": wallp,
+                   "stages_ms": {"preprocess": stp[0], "bin_sort": stp[1], "raster": stp[2]},
+                   "speedup_frame_vs_3sigma": wall / wallp,
+                   "speedup_frame_vs_fp32": wall32 / wallp,
+                   "pairs_per_s_same_numerator": pairs / (wallp / 1e3),
+                   "psnr_vs_fp32_db": 10 * np.log10(1.0 / mp) if mp > 0 else float("inf")}
+        log(f"[bench] precise binning {precise}")
     mse = float(torch.mean((img - ref_img) ** 2))
     psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
     assert int(bs.n_splats()) <= capacity
@@ -317,9 +453,13 @@ def main():
         "psnr_vs_fp32_db": psnr,
         "raster_pairs_per_s": pairs / raster_s,
         "sweep": sweep,
+        "precise_binning": precise,
     }
     if not args.no_train:
         out["train_step"] = train_step(args)
+    if not args.no_multiview:
+        out["multiview"] = multiview(args)
+        log(f"[bench] multiview {out['multiview']['graph_ms_per_frame']:.2f} ms/frame")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(scene, cam_np, pre, pairs)

@@ -143,6 +143,34 @@ gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t *radii, con
                       size_t workspace_bytes, uint32_t *sorted_ids, uint32_t *tile_ranges,
                       uint32_t *d_num_splats, void *stream);
 
+/* Workspace bytes gs_bin_sort_precise needs (0 for invalid sizes). */
+size_t gs_bin_sort_precise_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
+                                           int32_t height);
+
+/*
+ * gs_bin_sort_precise -- gs_bin_sort with a precise Gaussian-tile
+ * intersection (the tighter binning of the pipelines TC-GS composes with,
+ * Sec. 2 and Table 4): of the tiles the 3-sigma rectangle covers, a
+ * Gaussian is listed only on those whose pixel box [16 tx, min(16 tx + 15,
+ * W - 1)] x [same in y] holds a point where its raw opacity
+ * o exp(-1/2 d^T S d) reaches the 1/255 culling threshold of Algorithm 1
+ * (S = conic, d = point - mean).  Every dropped fragment is culled at each
+ * pixel of its tile, so the rendered image is that of gs_bin_sort's lists;
+ * fewer splats are sorted and visited.  Per tile row the kept tiles form one
+ * contiguous run, computed in FP64 with the threshold enlarged by a
+ * relative 1e-9 (rounding can keep a boundary tile, never drop one).
+ *   conics [P][3] (s11, s12, s22) and opacities [P] as for gs_rasterize_fwd;
+ *   everything else exactly as gs_bin_sort (order within a tile, capacity
+ *   and overflow behaviour, d_num_splats).
+ * Errors: as gs_bin_sort; GS_ERR_CAPACITY if workspace_bytes <
+ * gs_bin_sort_precise_workspace_bytes(...).
+ */
+gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const int32_t *radii,
+                              const float *depths, const float *conics, const float *opacities,
+                              int32_t width, int32_t height, uint32_t capacity, void *workspace,
+                              size_t workspace_bytes, uint32_t *sorted_ids, uint32_t *tile_ranges,
+                              uint32_t *d_num_splats, void *stream);
+
 /*
  * gs_rasterize_fwd -- conditional alpha-blending (Algorithm 1) per 16x16
  * tile.  For each pixel, front to back over its tile's list:
@@ -202,6 +230,99 @@ gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t tile, const u
                             const uint32_t *sorted_ids, const float *means2d, const float *conics,
                             const float *opacities, int32_t precision, int32_t count,
                             float *out_beta, void *stream);
+
+/*
+ * gs_preprocess_multiview -- gs_preprocess for `nviews` cameras of one scene
+ * in one pass: each Gaussian's means3d, scales, quats and (if it is visible
+ * in some view) sh are read once and projected into every camera.  `cams`
+ * is a HOST array of nviews cameras (1 <= nviews <= 64).  Every output is
+ * view-major with a stride of P entries: view v's means2d start at
+ * means2d + 2 * v * P, conics at conics + 3 * v * P, depths/radii/
+ * tiles_touched at + v * P, rgb at rgb + 3 * v * P; each view's slice is
+ * what gs_preprocess with that camera writes.
+ * Errors: as gs_preprocess, plus GS_ERR_INVALID_ARG for nviews out of range.
+ */
+gs_status gs_preprocess_multiview(int32_t P, const float *means3d, const float *scales,
+                                  const float *quats, const float *sh, int32_t sh_degree,
+                                  int32_t nviews, const gs_camera *cams, float *means2d,
+                                  float *conics, float *depths, int32_t *radii, float *rgb,
+                                  uint32_t *tiles_touched, void *stream);
+
+/* One view of a batched frame: its image size, its own gs_bin_sort lists,
+ * its gs_preprocess outputs and its output images, laid out exactly as for
+ * gs_rasterize_fwd.  All pointers are DEVICE pointers. */
+typedef struct {
+    int32_t width, height;
+    const uint32_t *tile_ranges; /* [ntiles][2]                              */
+    const uint32_t *sorted_ids;  /* tile-major splat list of this view       */
+    const float *means2d;        /* [P][2]                                   */
+    const float *conics;         /* [P][3]                                   */
+    const float *opacities;      /* [P]                                      */
+    const float *rgb;            /* [P][3]                                   */
+    float background[3];         /* composited as C + T * bg                 */
+    float *out_rgb;              /* [3][H][W]                                */
+    float *out_T;                /* [H][W]                                   */
+    uint32_t *out_ncontrib;      /* [H][W]                                   */
+} gs_view;
+
+/* Launch shape of gs_rasterize_fwd_batched (chosen by an autotuner).
+ *   batch          splats gathered and staged per round: 64, 128 or 256
+ *   blocks_per_cu  persistent workgroups per compute unit, 1..16 (the grid
+ *                  is the CU count times this, rounded up to a multiple of 8)
+ *   xcd_queues     1: eight work queues, one per XCD, holding bands of two
+ *                  tile rows (band b -> queue b mod 8), with stealing once a
+ *                  queue is empty; 0: one queue of row-major tiles */
+typedef struct {
+    int32_t batch;
+    int32_t blocks_per_cu;
+    int32_t xcd_queues;
+} gs_batch_tune;
+
+/* Bytes of the device plan for nviews views (0 if nviews is not 1..64). */
+size_t gs_batch_plan_bytes(int32_t nviews);
+
+/* Bytes of the device workspace gs_rasterize_fwd_batched needs (queue heads
+ * and per-view tile counters; 0 if nviews is not 1..64). */
+size_t gs_batch_workspace_bytes(int32_t nviews);
+
+/*
+ * gs_batch_plan_write -- build the device plan of a batched frame from a
+ * HOST array of nviews gs_view and copy it to `plan` (device, 256-byte
+ * aligned, gs_batch_plan_bytes(nviews) bytes).  SYNCHRONOUS (a blocking
+ * host-to-device copy): call it once at set-up, outside stream capture; the
+ * plan stays valid while the buffers it names do.
+ * Errors: GS_ERR_INVALID_ARG (bad view or pointer), GS_ERR_CAPACITY (plan
+ * too small), GS_ERR_HIP.
+ */
+gs_status gs_batch_plan_write(int32_t nviews, const gs_view *views, void *plan, size_t plan_bytes);
+
+/*
+ * gs_rasterize_fwd_batched -- gs_rasterize_fwd for every view of a plan in
+ * ONE persistent launch (after a one-workgroup launch that clears the
+ * workspace).  Workgroups take (view, tile) items from device work queues
+ * until all are empty; each tile is rendered exactly as gs_rasterize_fwd
+ * renders it, so every view's outputs are bit-identical to a one-view call.
+ * Only the matrix-core precisions are served (GS_ERR_UNSUPPORTED for FP32).
+ *   tune        HOST pointer, NULL = {256, 5, 1}
+ *   workspace   device, gs_batch_workspace_bytes(nviews) bytes; a call
+ *               overwrites it, so two calls in flight need two workspaces
+ *   d_view_clock NULL, or device uint64[nviews] receiving, per view, the
+ *               device wall clock (gs_wall_clock_khz ticks) at which its
+ *               last tile finished
+ * The call enqueues no memset and no host synchronisation, so it can be
+ * captured in a hipGraph.
+ * Errors: GS_ERR_INVALID_ARG, GS_ERR_CAPACITY (workspace), GS_ERR_UNSUPPORTED,
+ * GS_ERR_HIP.
+ */
+gs_status gs_rasterize_fwd_batched(int32_t nviews, const void *plan, int32_t precision,
+                                   const gs_batch_tune *tune, void *workspace,
+                                   size_t workspace_bytes, uint64_t *d_view_clock, void *stream);
+
+/* Enqueue a write of the device wall clock to *d_dst (device uint64). */
+gs_status gs_clock_stamp(uint64_t *d_dst, void *stream);
+
+/* Frequency of the device wall clock in kHz (host call, current device). */
+gs_status gs_wall_clock_khz(int32_t *khz);
 
 #ifdef __cplusplus
 }

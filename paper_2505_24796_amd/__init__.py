@@ -54,6 +54,24 @@ class gs_camera(ctypes.Structure):
                 ("frustum_guard", c_float), ("lowpass", c_float), ("campos", c_float * 3)]
 
 
+class gs_view(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("tile_ranges", c_void_p),
+                ("sorted_ids", c_void_p), ("means2d", c_void_p), ("conics", c_void_p),
+                ("opacities", c_void_p), ("rgb", c_void_p), ("background", c_float * 3),
+                ("out_rgb", c_void_p), ("out_T", c_void_p), ("out_ncontrib", c_void_p)]
+
+
+class gs_batch_tune(ctypes.Structure):
+    _fields_ = [("batch", c_int32), ("blocks_per_cu", c_int32), ("xcd_queues", c_int32)]
+
+    def as_tuple(self):
+        return (self.batch, self.blocks_per_cu, self.xcd_queues)
+
+
+def make_tune(batch=256, blocks_per_cu=5, xcd_queues=1) -> gs_batch_tune:
+    return gs_batch_tune(int(batch), int(blocks_per_cu), int(xcd_queues))
+
+
 _lib = None
 
 
@@ -88,6 +106,27 @@ def lib() -> ctypes.CDLL:
         L.gs_rasterize_beta.restype = ctypes.c_int
         L.gs_rasterize_beta.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, c_int32,
                                         c_int32, vp, vp]
+        L.gs_bin_sort_precise_workspace_bytes.restype = c_size_t
+        L.gs_bin_sort_precise_workspace_bytes.argtypes = [c_int32, c_uint32, c_int32, c_int32]
+        L.gs_bin_sort_precise.restype = ctypes.c_int
+        L.gs_bin_sort_precise.argtypes = [c_int32, vp, vp, vp, vp, vp, c_int32, c_int32, c_uint32,
+                                          vp, c_size_t, vp, vp, vp, vp]
+        L.gs_preprocess_multiview.restype = ctypes.c_int
+        L.gs_preprocess_multiview.argtypes = [c_int32, vp, vp, vp, vp, c_int32, c_int32,
+                                              POINTER(gs_camera), vp, vp, vp, vp, vp, vp, vp]
+        L.gs_batch_plan_bytes.restype = c_size_t
+        L.gs_batch_plan_bytes.argtypes = [c_int32]
+        L.gs_batch_workspace_bytes.restype = c_size_t
+        L.gs_batch_workspace_bytes.argtypes = [c_int32]
+        L.gs_batch_plan_write.restype = ctypes.c_int
+        L.gs_batch_plan_write.argtypes = [c_int32, POINTER(gs_view), vp, c_size_t]
+        L.gs_rasterize_fwd_batched.restype = ctypes.c_int
+        L.gs_rasterize_fwd_batched.argtypes = [c_int32, vp, c_int32, POINTER(gs_batch_tune), vp,
+                                               c_size_t, vp, vp]
+        L.gs_clock_stamp.restype = ctypes.c_int
+        L.gs_clock_stamp.argtypes = [vp, vp]
+        L.gs_wall_clock_khz.restype = ctypes.c_int
+        L.gs_wall_clock_khz.argtypes = [POINTER(c_int32)]
         _lib = L
     return _lib
 
@@ -168,28 +207,51 @@ def preprocess_2d(means2d, cov2d, width: int, height: int) -> dict:
 class BinSorter:
     """Owns a workspace and output buffers for gs_bin_sort at a fixed
     (P, capacity, width, height); reusable across frames (no allocation per
-    call)."""
+    call).  With ``precise`` it runs gs_bin_sort_precise (then the call
+    also takes the conics and opacities)."""
 
-    def __init__(self, P: int, capacity: int, width: int, height: int, device="cuda"):
+    def __init__(self, P: int, capacity: int, width: int, height: int, device="cuda",
+                 workspace: torch.Tensor | None = None, precise: bool = False):
         self.P, self.capacity, self.width, self.height = P, int(capacity), width, height
-        nbytes = lib().gs_bin_sort_workspace_bytes(P, self.capacity, width, height)
+        self.precise = bool(precise)
+        wsb = (lib().gs_bin_sort_precise_workspace_bytes if self.precise
+               else lib().gs_bin_sort_workspace_bytes)
+        nbytes = wsb(P, self.capacity, width, height)
         if nbytes == 0:
             raise ValueError("invalid bin_sort sizes")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        elif workspace.numel() < nbytes or workspace.dtype != torch.uint8:
+            raise ValueError(f"shared workspace needs {nbytes} uint8 bytes")
+        # a shared workspace serves several sorters whose calls are ordered on
+        # one stream
+        self.workspace = workspace
         gx, gy = grid(width, height)
         self.sorted_ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
         self.ranges = torch.empty(gx * gy, 2, dtype=torch.int32, device=device)
         self.num_splats = torch.zeros(1, dtype=torch.int32, device=device)
 
-    def __call__(self, means2d, radii, depths):
+    def __call__(self, means2d, radii, depths, conics=None, opacities=None):
         _dev(means2d, torch.float32, "means2d")
         _dev(radii, torch.int32, "radii")
         _dev(depths, torch.float32, "depths")
-        st = lib().gs_bin_sort(self.P, _ptr(means2d), _ptr(radii), _ptr(depths), self.width,
-                               self.height, self.capacity, _ptr(self.workspace),
-                               self.workspace.numel(), _ptr(self.sorted_ids), _ptr(self.ranges),
-                               _ptr(self.num_splats), _stream())
-        _check("gs_bin_sort", st)
+        if self.precise:
+            if conics is None or opacities is None:
+                raise ValueError("precise binning needs conics and opacities")
+            _dev(conics, torch.float32, "conics")
+            _dev(opacities, torch.float32, "opacities")
+            st = lib().gs_bin_sort_precise(self.P, _ptr(means2d), _ptr(radii), _ptr(depths),
+                                           _ptr(conics), _ptr(opacities), self.width, self.height,
+                                           self.capacity, _ptr(self.workspace),
+                                           self.workspace.numel(), _ptr(self.sorted_ids),
+                                           _ptr(self.ranges), _ptr(self.num_splats), _stream())
+            _check("gs_bin_sort_precise", st)
+        else:
+            st = lib().gs_bin_sort(self.P, _ptr(means2d), _ptr(radii), _ptr(depths), self.width,
+                                   self.height, self.capacity, _ptr(self.workspace),
+                                   self.workspace.numel(), _ptr(self.sorted_ids),
+                                   _ptr(self.ranges), _ptr(self.num_splats), _stream())
+            _check("gs_bin_sort", st)
         return self.sorted_ids, self.ranges, self.num_splats
 
     def n_splats(self) -> int:
@@ -197,16 +259,42 @@ class BinSorter:
         return int(self.num_splats.item()) & 0xFFFFFFFF
 
 
-def bin_sort(means2d, radii, depths, width: int, height: int, capacity: int | None = None):
+def preprocess_multiview(means3d, scales, quats, sh, cams, sh_degree: int = 3, out: dict | None = None) -> dict:
+    """gs_preprocess for several cameras in one pass; every output has a
+    leading view axis (V, P, ...)."""
+    P, V = means3d.shape[0], len(cams)
+    f32 = torch.float32
+    for n, t in (("means3d", means3d), ("scales", scales), ("quats", quats), ("sh", sh)):
+        _dev(t, f32, n)
+    dev = means3d.device
+    if out is None:
+        out = dict(means2d=torch.empty(V, P, 2, dtype=f32, device=dev),
+                   conics=torch.empty(V, P, 3, dtype=f32, device=dev),
+                   depths=torch.empty(V, P, dtype=f32, device=dev),
+                   radii=torch.empty(V, P, dtype=torch.int32, device=dev),
+                   rgb=torch.empty(V, P, 3, dtype=f32, device=dev),
+                   tiles_touched=torch.empty(V, P, dtype=torch.int32, device=dev))
+    arr = (gs_camera * V)(*cams)
+    st = lib().gs_preprocess_multiview(P, _ptr(means3d), _ptr(scales), _ptr(quats), _ptr(sh),
+                                       sh_degree, V, arr, _ptr(out["means2d"]),
+                                       _ptr(out["conics"]), _ptr(out["depths"]),
+                                       _ptr(out["radii"]), _ptr(out["rgb"]),
+                                       _ptr(out["tiles_touched"]), _stream())
+    _check("gs_preprocess_multiview", st)
+    return out
+
+
+def bin_sort(means2d, radii, depths, width: int, height: int, capacity: int | None = None,
+             conics=None, opacities=None, precise: bool = False):
     """One-shot binning.  Without ``capacity`` the splat count is computed by
     a first call with capacity 0 (one host synchronisation)."""
     P = means2d.shape[0]
     if capacity is None:
-        probe = BinSorter(P, 0, width, height, device=means2d.device)
-        probe(means2d, radii, depths)
+        probe = BinSorter(P, 0, width, height, device=means2d.device, precise=precise)
+        probe(means2d, radii, depths, conics, opacities)
         capacity = max(probe.n_splats(), 1)
-    bs = BinSorter(P, capacity, width, height, device=means2d.device)
-    bs(means2d, radii, depths)
+    bs = BinSorter(P, capacity, width, height, device=means2d.device, precise=precise)
+    bs(means2d, radii, depths, conics, opacities)
     return bs
 
 
@@ -310,3 +398,131 @@ def render(means3d, scales, quats, sh, opacities, cam: gs_camera, precision="fp1
     r(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opacities, pre["rgb"], precision,
       background)
     return r, bs, pre
+
+
+def wall_clock_khz() -> int:
+    k = c_int32(0)
+    _check("gs_wall_clock_khz", lib().gs_wall_clock_khz(ctypes.byref(k)))
+    return int(k.value)
+
+
+class MultiViewRenderer:
+    """Renders one scene to several cameras per frame: one multi-view
+    preprocess, one bin/sort per view (sharing a workspace), and ONE
+    persistent batched rasteriser launch over every (view, tile) pair.
+    Buffers are sized once (splat capacity per view from a probe frame times
+    ``slack``); a frame allocates nothing, so it can be captured in a
+    hipGraph (:meth:`capture`).  Per-view latency inside a frame comes from
+    device wall-clock stamps (frame start, last tile of each view)."""
+
+    def __init__(self, scene: dict, cams, precision="fp16_g2l_split", slack=1.15,
+                 background=(0.0, 0.0, 0.0), sh_degree=3, precise=False):
+        self.scene = {k: _dev(scene[k], torch.float32, k)
+                      for k in ("means3d", "scales", "quats", "sh", "opacities")}
+        self.cams = list(cams)
+        self.V, self.P = len(self.cams), self.scene["means3d"].shape[0]
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.sh_degree = sh_degree
+        self.precise = bool(precise)
+        dev = self.scene["means3d"].device
+        self.device = dev
+        self.pre = preprocess_multiview(self.scene["means3d"], self.scene["scales"],
+                                        self.scene["quats"], self.scene["sh"], self.cams, sh_degree)
+        # probe frame: splat count per view
+        counts = []
+        for v, c in enumerate(self.cams):
+            probe = BinSorter(self.P, 0, c.width, c.height, device=dev, precise=self.precise)
+            probe(*self._bin_inputs(v))
+            counts.append(probe.n_splats())
+        self.probe_counts = counts
+        self.capacity = [int(n * slack) + 1024 for n in counts]
+        wsb = (lib().gs_bin_sort_precise_workspace_bytes if self.precise
+               else lib().gs_bin_sort_workspace_bytes)
+        ws = max(wsb(self.P, cap, c.width, c.height) for cap, c in zip(self.capacity, self.cams))
+        self.bin_workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.sorters = [BinSorter(self.P, cap, c.width, c.height, device=dev,
+                                  workspace=self.bin_workspace, precise=self.precise)
+                        for cap, c in zip(self.capacity, self.cams)]
+        self.images = [Rasterizer(c.width, c.height, device=dev) for c in self.cams]
+        views = (gs_view * self.V)()
+        for v, (c, bs, r) in enumerate(zip(self.cams, self.sorters, self.images)):
+            g = views[v]
+            g.width, g.height = c.width, c.height
+            g.tile_ranges, g.sorted_ids = bs.ranges.data_ptr(), bs.sorted_ids.data_ptr()
+            g.means2d = self.pre["means2d"][v].data_ptr()
+            g.conics = self.pre["conics"][v].data_ptr()
+            g.opacities = self.scene["opacities"].data_ptr()
+            g.rgb = self.pre["rgb"][v].data_ptr()
+            g.background[:] = [float(b) for b in background]
+            g.out_rgb, g.out_T = r.rgb.data_ptr(), r.T.data_ptr()
+            g.out_ncontrib = r.n_contrib.data_ptr()
+        self.views = views
+        L = lib()
+        self.plan = torch.empty(L.gs_batch_plan_bytes(self.V), dtype=torch.uint8, device=dev)
+        _check("gs_batch_plan_write",
+               L.gs_batch_plan_write(self.V, views, _ptr(self.plan), self.plan.numel()))
+        self.batch_ws = torch.empty(L.gs_batch_workspace_bytes(self.V), dtype=torch.uint8,
+                                    device=dev)
+        self.clock = torch.zeros(self.V + 1, dtype=torch.int64, device=dev)  # [0] frame start
+        self.tune = make_tune()
+
+    # -- stages -----------------------------------------------------------
+    def preprocess(self):
+        preprocess_multiview(self.scene["means3d"], self.scene["scales"], self.scene["quats"],
+                             self.scene["sh"], self.cams, self.sh_degree, out=self.pre)
+
+    def _bin_inputs(self, v):
+        return (self.pre["means2d"][v], self.pre["radii"][v], self.pre["depths"][v],
+                self.pre["conics"][v], self.scene["opacities"])
+
+    def bin_sort(self):
+        for v, bs in enumerate(self.sorters):
+            bs(*self._bin_inputs(v))
+
+    def raster(self, tune: gs_batch_tune | None = None, stamp=True):
+        t = self.tune if tune is None else tune
+        st = lib().gs_rasterize_fwd_batched(self.V, _ptr(self.plan), self.precision,
+                                            ctypes.byref(t), _ptr(self.batch_ws),
+                                            self.batch_ws.numel(),
+                                            c_void_p(self.clock.data_ptr() + 8) if stamp
+                                            else c_void_p(0), _stream())
+        _check("gs_rasterize_fwd_batched", st)
+
+    def raster_per_view(self):
+        """The same images with one gs_rasterize_fwd launch per view."""
+        for v, (bs, r) in enumerate(zip(self.sorters, self.images)):
+            r(bs.ranges, bs.sorted_ids, self.pre["means2d"][v], self.pre["conics"][v],
+              self.scene["opacities"], self.pre["rgb"][v], self.precision,
+              tuple(self.views[v].background))
+
+    def frame(self, tune: gs_batch_tune | None = None):
+        _check("gs_clock_stamp", lib().gs_clock_stamp(_ptr(self.clock), _stream()))
+        self.preprocess()
+        self.bin_sort()
+        self.raster(tune)
+
+    def capture(self, tune: gs_batch_tune | None = None) -> "torch.cuda.CUDAGraph":
+        """A hipGraph of one whole frame (replay with ``g.replay()``)."""
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.frame(tune)  # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.frame(tune)
+        return g
+
+    # -- results ----------------------------------------------------------
+    def n_splats(self):
+        return [bs.n_splats() for bs in self.sorters]
+
+    def overflowed(self):
+        return [n > cap for n, cap in zip(self.n_splats(), self.capacity)]
+
+    def latencies_ms(self):
+        """Per-view time from the frame-start stamp to the view's last tile
+        (host read; synchronises)."""
+        c = self.clock.cpu().tolist()
+        khz = wall_clock_khz()
+        return [(c[1 + v] - c[0]) / khz for v in range(self.V)]

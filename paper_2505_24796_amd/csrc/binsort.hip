@@ -152,7 +152,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 // per-block digit histograms -> per-digit scan over blocks -> scatter.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
-                                                             Count cnt, int shift, uint32_t dmask,
+                                                             Count cnt, int shift,
                                                              uint32_t *__restrict__ hist,
                                                              uint32_t nblocks) {
     __shared__ uint32_t h[RADIX];
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
 #pragma unroll
         for (int k = 0; k < SORT_ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & dmask], 1u);
+            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
         }
     }
     __syncthreads();
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
 
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, Count cnt, int shift, int dbits, const uint32_t *__restrict__ hist_scan,
+    uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
     const uint32_t *__restrict__ totals, uint32_t nblocks) {
     __shared__ uint32_t wcnt[WAVES][RADIX];
     __shared__ uint32_t gbase[RADIX];   // global position of this block's first key of digit d
@@ -227,16 +227,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n;
-        const uint32_t dmask = (1u << dbits) - 1u;
-        uint32_t d = (key[c] >> shift) & dmask;
-        const uint64_t valid = __ballot(ok);
-        uint64_t peers = valid;
-        // lanes with equal digits: one ballot per digit bit; a bit that is the
-        // same in every valid lane (common: nearby keys) separates nothing
-        for (int b = 0; b < dbits; ++b) {
+        uint32_t d = (key[c] >> shift) & (RADIX - 1);
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
             bool bit = (d >> b) & 1u;
-            uint64_t m = __ballot(bit) & valid;
-            if (m != 0ull && m != valid) peers &= bit ? m : ~m;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
         }
         uint32_t rank = gs::lanes_below(peers);
         uint32_t before = ok ? wcnt[w][d] : 0u;
@@ -263,7 +260,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < WAVE_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n) {
-            uint32_t d = (key[c] >> shift) & ((1u << dbits) - 1u);
+            uint32_t d = (key[c] >> shift) & (RADIX - 1);
             uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
             skey[lp] = key[c];
             sval[lp] = val[c];
@@ -274,7 +271,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
-        uint32_t d = (k >> shift) & ((1u << dbits) - 1u);
+        uint32_t d = (k >> shift) & (RADIX - 1);
         uint32_t dst = gbase[d] + (lp - lstart[d]);
         kout[dst] = k;
         vout[dst] = sval[lp];
@@ -285,26 +282,20 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
-// Sorts on bits [0, bits) with ceil(bits/8) passes whose digit widths split
-// the bits evenly (13 tile bits: 7 + 6); returns the index of the buffer pair
-// holding the result.
+// Sorts on bits [0, bits) with ceil(bits/8) passes; returns the index of the
+// buffer pair holding the result.
 int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
                hipStream_t s) {
     uint32_t nblocks = (max_n + SORT_TILE - 1) / SORT_TILE;
     if (nblocks == 0) nblocks = 1;
-    const int npass = (bits + RADIX_BITS - 1) / RADIX_BITS;
-    int cur = 0, shift = 0;
-    for (int p = 0; p < npass; ++p) {
-        const int dbits = (bits - shift + (npass - p) - 1) / (npass - p);
-        const uint32_t dmask = (1u << dbits) - 1u;
+    int cur = 0;
+    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
         hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], cnt,
-                           shift, dmask, hist, nblocks);
+                           shift, hist, nblocks);
         hipLaunchKernelGGL(k_hist_rows, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
-                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, dbits, hist, totals,
-                           nblocks);
+                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals, nblocks);
         cur ^= 1;
-        shift += dbits;
     }
     return cur;
 }
@@ -318,14 +309,107 @@ __device__ __forceinline__ uint32_t depth_key(float d) {
     return (f & 0x80000000u) ? ~f : (f | 0x80000000u);
 }
 
-// Depth keys and the packed tile rectangle of every Gaussian (coalesced);
-// also clears the tile ranges.
+__global__ void k_set_word(uint32_t *__restrict__ dst, uint32_t v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+// Precise Gaussian-tile intersection: inside the 3-sigma rectangle, keep a
+// tile only if the raw opacity o exp(-q/2), q = d^T S d, reaches the 1/255
+// culling threshold of Algorithm 1 somewhere in the tile's pixel box, i.e.
+// the box meets the ellipse E = {d : q(d) <= tq}, tq = 2 (ln o + ln 255).
+// E is convex, so the tiles of one tile row that meet it are a contiguous
+// run: the row's y-band [y0, y1] cuts E in a convex piece whose x-extent is
+// [mx + xl, mx + xr], with
+//   left(dy)  = (-b dy - sqrt(a tq - det dy^2)) / a  (convex, least at the
+//               ellipse's leftmost point dy = b s, dx = -c s, s = sqrt(tq / (c det)))
+//   right(dy) = (-b dy + sqrt(a tq - det dy^2)) / a  (concave, largest at
+//               dy = -b s, dx = c s)
+// evaluated at the extreme point if it lies in the band, else at the band's
+// ends.  FP64 throughout, tq enlarged by a relative 1e-9 so that rounding can
+// only keep a tile, never drop one; contraction is off so the count pass and
+// the emission pass compute identical spans.
+struct PGauss {
+    float mx, my, a, b, c, pad;
+    double tq;
+};
+
+__device__ __forceinline__ double precise_tq(float o) {
+    if (!(o > 0.0f)) return -1.0;
+    double t = 2.0 * (log((double)o) + 5.541263545158426);  // ln 255
+    return t + 1e-9 * fabs(t) + 1e-12;
+}
+
+// Columns [c0, c1] of tile row ty that meet E, clipped to [tx0, tx1];
+// returns the count (0 when none).
+__device__ __forceinline__ uint32_t row_span(const PGauss &g, int ty, int tx0, int tx1, int W, int H,
+                                          int &c0, int &c1) {
+#pragma clang fp contract(off)
+    const double a = g.a, b = g.b, c = g.c, T = g.tq;
+    if (!(T >= 0.0)) return 0u;
+    const double det = a * c - b * b;
+    if (!(a > 0.0) || !(c > 0.0) || !(det > 0.0)) {  // not positive definite: keep the rectangle row
+        c0 = tx0;
+        c1 = tx1;
+        return (uint32_t)(tx1 - tx0 + 1);
+    }
+    const double y0 = (double)(GS_TILE * ty) - g.my;
+    const double y1 = (double)min(GS_TILE * ty + GS_TILE - 1, H - 1) - g.my;
+    const double ymax = sqrt(T * a / det);
+    const double ya = fmax(y0, -ymax), yb = fmin(y1, ymax);
+    if (ya > yb) return 0u;
+    const double s = sqrt(T / (c * det));
+    const double dyl = b * s, dyr = -b * s;
+    double xl, xr;
+    if (dyl >= ya && dyl <= yb) {
+        xl = -c * s;
+    } else {
+        const double la = (-b * ya - sqrt(fmax(a * T - det * ya * ya, 0.0))) / a;
+        const double lb = (-b * yb - sqrt(fmax(a * T - det * yb * yb, 0.0))) / a;
+        xl = fmin(la, lb);
+    }
+    if (dyr >= ya && dyr <= yb) {
+        xr = c * s;
+    } else {
+        const double ra = (-b * ya + sqrt(fmax(a * T - det * ya * ya, 0.0))) / a;
+        const double rb = (-b * yb + sqrt(fmax(a * T - det * yb * yb, 0.0))) / a;
+        xr = fmax(ra, rb);
+    }
+    const double XL = g.mx + xl, XR = g.mx + xr;
+    // tile column c spans pixels [16c, min(16c + 15, W - 1)]
+    if (XR < (double)(GS_TILE * tx0) || XL > (double)(W - 1)) return 0u;
+    int lo = (int)ceil((XL - (double)(GS_TILE - 1)) / (double)GS_TILE);
+    int hi = (int)floor(XR / (double)GS_TILE);
+    lo = max(lo, tx0);
+    hi = min(hi, tx1);
+    if (lo > hi) return 0u;
+    c0 = lo;
+    c1 = hi;
+    return (uint32_t)(hi - lo + 1);
+}
+
+struct RectDec {
+    int tx0, ty0, w, h;
+};
+__device__ __forceinline__ RectDec dec_rect(uint2 r) {
+    return RectDec{(int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu), (int)(r.y >> 16)};
+}
+
+// Depth keys, the packed tile rectangle and the splat count of every
+// Gaussian (coalesced; with PRECISE the count is that of the precise rule
+// and the ellipse parameters are kept for the emission); also clears the
+// tile ranges.  A Gaussian without splats gets the largest key, so it sorts
+// after every Gaussian that has splats.
+template <bool PRECISE>
 __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restrict__ means2d,
                                                     const int *__restrict__ radii,
-                                                    const float *__restrict__ depths, int W, int H,
+                                                    const float *__restrict__ depths,
+                                                    const float *__restrict__ conics,
+                                                    const float *__restrict__ opac, int W, int H,
                                                     int gx, uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
                                                     uint2 *__restrict__ rects,
+                                                    uint32_t *__restrict__ cnt_g,
+                                                    PGauss *__restrict__ pg,
                                                     uint32_t *__restrict__ ranges, int n2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n2) ranges[i] = 0u;
@@ -333,26 +417,48 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
     float d = depths[i];
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
     int n = 0;
+    float2 m = make_float2(0.f, 0.f);
     if (isfinite(d)) {
-        float2 m = means2d[i];
+        m = means2d[i];
         n = gs::tile_rect(m.x, m.y, radii[i], W, H, gx, tx0, tx1, ty0, ty1);
     }
-    keys[i] = n > 0 ? depth_key(d) : 0xFFFFFFFFu;
+    uint32_t c = (uint32_t)n;
+    if (PRECISE) {
+        PGauss q{};
+        c = 0;
+        if (n > 0) {
+            q.mx = m.x;
+            q.my = m.y;
+            q.a = conics[3 * i];
+            q.b = conics[3 * i + 1];
+            q.c = conics[3 * i + 2];
+            q.tq = precise_tq(opac[i]);
+            for (int ty = ty0; ty <= ty1; ++ty) {
+                int c0, c1;
+                c += row_span(q, ty, tx0, tx1, W, H, c0, c1);
+            }
+        }
+        pg[i] = q;
+    }
+    keys[i] = c > 0 ? depth_key(d) : 0xFFFFFFFFu;
     ids[i] = (uint32_t)i;
-    rects[i] = n > 0 ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
+    rects[i] = c > 0 ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
                                   (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16))
                      : make_uint2(0u, 0u);
+    cnt_g[i] = c;
 }
 
+// Rectangle and splat count of each Gaussian in depth order.
 __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restrict__ order,
                                                 const uint2 *__restrict__ rects,
+                                                const uint32_t *__restrict__ cnt_g,
                                                 uint2 *__restrict__ rects_sorted,
                                                 uint32_t *__restrict__ cnt) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= P) return;
-    uint2 r = rects[order[j]];
-    rects_sorted[j] = r;
-    cnt[j] = (r.y & 0xFFFFu) * (r.y >> 16);
+    const uint32_t g = order[j];
+    rects_sorted[j] = rects[g];
+    cnt[j] = cnt_g[g];
 }
 
 // Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
@@ -360,13 +466,16 @@ __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restric
 // j1 = owner of the next window's first slot (or of the last slot); their
 // offsets and rectangles are staged in LDS.  Each thread locates the owner
 // of its first of EMIT_ITEMS consecutive slots by binary search and walks
-// the rectangle(s) from there in row-major order; results are staged in LDS
-// and written out coalesced.
+// the Gaussian's tiles from there in row-major order (the whole rectangle,
+// or with PRECISE the run of each row that meets the ellipse); results are
+// staged in LDS and written out coalesced.
+template <bool PRECISE>
 __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ offs,
                                                        const uint2 *__restrict__ rects_sorted,
+                                                       const PGauss *__restrict__ pg,
                                                        const uint32_t *__restrict__ win_start,
-                                                       uint32_t nwin, int gx,
+                                                       uint32_t nwin, int gx, int W, int H,
                                                        const uint32_t *__restrict__ n_splats,
                                                        uint32_t cap, uint32_t *__restrict__ tkey,
                                                        uint32_t *__restrict__ tid) {
@@ -402,24 +511,70 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
             else hi = mid;
         }
         uint32_t k = lo;
-        uint2 r = s_rect[k];
-        uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
         uint32_t l = s0 - s_off[k];
-        uint32_t row = l / w, col = l - row * w;
-        for (int i = 0; i < EMIT_ITEMS; ++i) {
-            uint32_t o = s0 + (uint32_t)i;
-            if (o >= oend) break;
-            uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
-            s_tk[o - o0] = ty * (uint32_t)gx + tx;
-            s_tg[o - o0] = s_id[k];
-            if (++col == w) {
-                col = 0;
-                if (++row == h && k + 1 < m) {
-                    row = 0;
-                    ++k;
-                    r = s_rect[k];
-                    w = max(r.y & 0xFFFFu, 1u);
-                    h = max(r.y >> 16, 1u);
+        if (!PRECISE) {
+            uint2 r = s_rect[k];
+            uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
+            uint32_t row = l / w, col = l - row * w;
+            for (int i = 0; i < EMIT_ITEMS; ++i) {
+                uint32_t o = s0 + (uint32_t)i;
+                if (o >= oend) break;
+                uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
+                s_tk[o - o0] = ty * (uint32_t)gx + tx;
+                s_tg[o - o0] = s_id[k];
+                if (++col == w) {
+                    col = 0;
+                    if (++row == h && k + 1 < m) {
+                        row = 0;
+                        ++k;
+                        r = s_rect[k];
+                        w = max(r.y & 0xFFFFu, 1u);
+                        h = max(r.y >> 16, 1u);
+                    }
+                }
+            }
+        } else {
+            // placeholders (tile 0, Gaussian 0: in bounds) for slots the walk
+            // below would leave unwritten if the two passes ever disagreed
+            for (int i = 0; i < EMIT_ITEMS && s0 + (uint32_t)i < oend; ++i) {
+                s_tk[s0 + i - o0] = 0u;
+                s_tg[s0 + i - o0] = 0u;
+            }
+            // current Gaussian k: rectangle, ellipse, row ty and its run [c0, c1]
+            PGauss q = pg[s_id[k]];
+            RectDec d = dec_rect(s_rect[k]);
+            int ty = d.ty0, c0 = 0, c1 = -1;
+            uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+            while (l >= n && ty < d.ty0 + d.h - 1) {  // row holding local slot l
+                l -= n;
+                ++ty;
+                n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+            }
+            for (int i = 0; i < EMIT_ITEMS; ++i) {
+                uint32_t o = s0 + (uint32_t)i;
+                if (o >= oend || l >= n) break;  // (l >= n only if the counts disagree)
+                s_tk[o - o0] = (uint32_t)ty * (uint32_t)gx + (uint32_t)(c0 + (int)l);
+                s_tg[o - o0] = s_id[k];
+                if (++l < n) continue;
+                l = 0;
+                n = 0;
+                while (n == 0 && ty < d.ty0 + d.h - 1) {  // next row with tiles
+                    ++ty;
+                    n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+                }
+                if (n > 0) continue;
+                // next Gaussian: the owner of slot o + 1 is the last one whose
+                // offset is <= o + 1 (Gaussians without splats share offsets)
+                ++k;
+                while (k + 1 < m && s_off[k + 1] <= o + 1) ++k;
+                if (k >= m) break;
+                q = pg[s_id[k]];
+                d = dec_rect(s_rect[k]);
+                ty = d.ty0;
+                n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+                while (n == 0 && ty < d.ty0 + d.h - 1) {
+                    ++ty;
+                    n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
                 }
             }
         }
@@ -470,12 +625,13 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
 
 // Workspace carve-up (every region 256-byte aligned).
 struct Layout {
-    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, tkey0, tkey1, tid, hist,
+    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt_g, cnt, offs, pg, tkey0, tkey1, tid,
+        hist,
         totals, part, win, total;
     uint32_t nwin;
 };
 
-Layout layout(uint32_t P, uint32_t cap) {
+Layout layout(uint32_t P, uint32_t cap, bool precise) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -494,6 +650,8 @@ Layout layout(uint32_t P, uint32_t cap) {
     L.rects_sorted = take(8ull * P);
     L.cnt = take(4ull * P);
     L.offs = take(4ull * P);
+    L.cnt_g = take(4ull * P);
+    L.pg = take(precise ? sizeof(PGauss) * (size_t)P : 0);
     L.tkey0 = take(4ull * cap);
     L.tkey1 = take(4ull * cap);
     L.tid = take(4ull * cap);
@@ -517,14 +675,23 @@ extern "C" size_t gs_bin_sort_workspace_bytes(int32_t P, uint32_t capacity, int3
                                               int32_t height) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
     if (capacity >= 0x80000000u) return 0;
-    return layout((uint32_t)P, capacity).total;
+    return layout((uint32_t)P, capacity, false).total;
 }
 
-extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t *radii,
-                                 const float *depths, int32_t width, int32_t height,
-                                 uint32_t capacity, void *workspace, size_t workspace_bytes,
-                                 uint32_t *sorted_ids, uint32_t *tile_ranges,
-                                 uint32_t *d_num_splats, void *stream) {
+extern "C" size_t gs_bin_sort_precise_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
+                                                      int32_t height) {
+    if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
+    if (capacity >= 0x80000000u) return 0;
+    return layout((uint32_t)P, capacity, true).total;
+}
+
+namespace {
+
+gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const float *depths,
+                   const float *conics, const float *opacities, bool precise, int32_t width,
+                   int32_t height, uint32_t capacity, void *workspace, size_t workspace_bytes,
+                   uint32_t *sorted_ids, uint32_t *tile_ranges, uint32_t *d_num_splats,
+                   void *stream) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM)
         return GS_ERR_INVALID_ARG;
     if (!tile_ranges || !d_num_splats || !workspace || !gs::aligned(workspace, 256) ||
@@ -533,31 +700,45 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     if (P > 0 && (!means2d || !radii || !depths || !gs::aligned(means2d, 8) ||
                   !gs::aligned(radii, 4) || !gs::aligned(depths, 4)))
         return GS_ERR_INVALID_ARG;
+    if (precise && P > 0 && (!conics || !opacities || !gs::aligned(conics, 4) ||
+                             !gs::aligned(opacities, 4)))
+        return GS_ERR_INVALID_ARG;
     if (capacity >= 0x80000000u) return GS_ERR_INVALID_ARG;
     if (capacity > 0 && (!sorted_ids || !gs::aligned(sorted_ids, 4))) return GS_ERR_INVALID_ARG;
-    Layout L = layout((uint32_t)P, capacity);
+    Layout L = layout((uint32_t)P, capacity, precise);
     if (workspace_bytes < L.total) return GS_ERR_CAPACITY;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     auto U = [&](size_t o) { return (uint32_t *)(ws + o); };
     uint64_t *part = (uint64_t *)(ws + L.part);
+    PGauss *pg = (PGauss *)(ws + L.pg);
     int gx = gs::grid_x(width), gy = gs::grid_y(height);
     int ntiles = gx * gy;
 
     if (P == 0) {
-        hipLaunchKernelGGL(k_depth_keys, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s, 0,
-                           (const float2 *)nullptr, (const int *)nullptr, (const float *)nullptr,
+        hipLaunchKernelGGL(k_depth_keys<false>, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s,
+                           0, (const float2 *)nullptr, (const int *)nullptr,
+                           (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
                            width, height, gx, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                           (uint2 *)nullptr, tile_ranges, 2 * ntiles);
-        hipMemsetAsync(d_num_splats, 0, 4, s);
+                           (uint2 *)nullptr, (uint32_t *)nullptr, (PGauss *)nullptr, tile_ranges,
+                           2 * ntiles);
+        // a kernel rather than a memset node, so the call can be graph-captured
+        hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, s, d_num_splats, 0u);
         return gs::launch_status();
     }
     const float2 *m2 = (const float2 *)means2d;
     int nthr = P > 2 * ntiles ? P : 2 * ntiles;
     // 1. depth keys, rectangles, cleared ranges; depth order of the Gaussians
-    hipLaunchKernelGGL(k_depth_keys, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2, radii,
-                       depths, width, height, gx, U(L.dkey0), U(L.did0), (uint2 *)(ws + L.rects),
-                       tile_ranges, 2 * ntiles);
+    if (precise)
+        hipLaunchKernelGGL(k_depth_keys<true>, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2,
+                           radii, depths, conics, opacities, width, height, gx, U(L.dkey0),
+                           U(L.did0), (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges,
+                           2 * ntiles);
+    else
+        hipLaunchKernelGGL(k_depth_keys<false>, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2,
+                           radii, depths, conics, opacities, width, height, gx, U(L.dkey0),
+                           U(L.did0), (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges,
+                           2 * ntiles);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
     int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32, U(L.hist),
                           U(L.totals), s);
@@ -565,7 +746,8 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     // 2. counts in depth order, scan (+ window owners), expansion
     int pblocks = (P + 255) / 256;
     hipLaunchKernelGGL(k_counts, dim3(pblocks), dim3(256), 0, s, P, order,
-                       (const uint2 *)(ws + L.rects), (uint2 *)(ws + L.rects_sorted), U(L.cnt));
+                       (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
+                       (uint2 *)(ws + L.rects_sorted), U(L.cnt));
     uint32_t sblocks = (P + SORT_TILE - 1) / SORT_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt),
                        (uint32_t)P, part);
@@ -581,10 +763,18 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     uint32_t *other_ids = (npass % 2 == 0) ? U(L.tid) : sorted_ids;
     if (capacity == 0) emit_ids = other_ids = U(L.tid);  // nothing fits
     uint32_t eblocks = (capacity + EMIT_TILE - 1) / EMIT_TILE;
-    if (eblocks > 0)
-        hipLaunchKernelGGL(k_emit, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order, U(L.offs),
-                           (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, gx,
-                           d_num_splats, capacity, U(L.tkey0), emit_ids);
+    if (eblocks > 0) {
+        if (precise)
+            hipLaunchKernelGGL(k_emit<true>, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
+                               U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
+                               U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
+                               U(L.tkey0), emit_ids);
+        else
+            hipLaunchKernelGGL(k_emit<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
+                               U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
+                               U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
+                               U(L.tkey0), emit_ids);
+    }
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     Count nc{0u, d_num_splats, capacity};
@@ -594,4 +784,26 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
     hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
                        tile_ranges);
     return gs::launch_status();
+}
+
+}  // namespace
+
+extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t *radii,
+                                 const float *depths, int32_t width, int32_t height,
+                                 uint32_t capacity, void *workspace, size_t workspace_bytes,
+                                 uint32_t *sorted_ids, uint32_t *tile_ranges,
+                                 uint32_t *d_num_splats, void *stream) {
+    return bin_sort(P, means2d, radii, depths, nullptr, nullptr, false, width, height, capacity,
+                    workspace, workspace_bytes, sorted_ids, tile_ranges, d_num_splats, stream);
+}
+
+extern "C" gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const int32_t *radii,
+                                         const float *depths, const float *conics,
+                                         const float *opacities, int32_t width, int32_t height,
+                                         uint32_t capacity, void *workspace,
+                                         size_t workspace_bytes, uint32_t *sorted_ids,
+                                         uint32_t *tile_ranges, uint32_t *d_num_splats,
+                                         void *stream) {
+    return bin_sort(P, means2d, radii, depths, conics, opacities, true, width, height, capacity,
+                    workspace, workspace_bytes, sorted_ids, tile_ranges, d_num_splats, stream);
 }

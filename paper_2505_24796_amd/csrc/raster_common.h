@@ -221,11 +221,11 @@ __device__ __forceinline__ void exponents(const uint8_t *a1, const uint8_t *a2, 
     }
 }
 
-// LDS footprint of one staged batch.
-template <int VAR> struct Stage {
-    static constexpr int A1 = BATCH * VarTraits<VAR>::ROW1;
-    static constexpr int A2 = BATCH * VarTraits<VAR>::ROW2;
-    static constexpr int RGB = BATCH * 16;
+// LDS footprint of one staged batch of NB splats.
+template <int VAR, int NB = BATCH> struct Stage {
+    static constexpr int A1 = NB * VarTraits<VAR>::ROW1;
+    static constexpr int A2 = NB * VarTraits<VAR>::ROW2;
+    static constexpr int RGB = NB * 16;
     static constexpr int BYTES = A1 + A2 + RGB;
 };
 
@@ -256,14 +256,14 @@ __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bo
     return s;
 }
 
-template <int VAR>
+template <int VAR, int NB = BATCH>
 __device__ __forceinline__ void stage_splat(uint8_t *stage, int j, const SplatRegs &s, float ox,
                                             float oy, uint32_t list_pos) {
     int sub = j / SUB, row = row_of_splat(j % SUB);
     uint8_t *row1 = stage + sub * SUB * VarTraits<VAR>::ROW1 + row * VarTraits<VAR>::ROW1;
-    uint8_t *row2 = stage + Stage<VAR>::A1 + sub * SUB * VarTraits<VAR>::ROW2 + row * VarTraits<VAR>::ROW2;
+    uint8_t *row2 = stage + Stage<VAR, NB>::A1 + sub * SUB * VarTraits<VAR>::ROW2 + row * VarTraits<VAR>::ROW2;
     build_row<VAR>(s.valid, s.mu, s.s11, s.s12, s.s22, s.o, ox, oy, row1, row2);
-    float4 *rgb = (float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
+    float4 *rgb = (float4 *)(stage + Stage<VAR, NB>::A1 + Stage<VAR, NB>::A2);
     // w: 1-based position of the splat in the tile list (for n_contrib)
     rgb[j] = make_float4(s.r, s.g, s.b, __uint_as_float(list_pos + 1u));
 }
@@ -304,10 +304,6 @@ __device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y
     float margin = 1e-3f * (1.0f + fmin) + 1e-5f * fabs_terms;
     return __logf(s.o) - fmin >= CULL_LN - margin;
 }
-
-// At least 5 resident waves per SIMD (the compiler then fits the kernel in
-// <= 80 VGPRs, i.e. 6 waves): the blend's exp / LDS / gather latencies are
-// hidden by other waves rather than by instruction-level parallelism.
 
 inline bool valid_inputs(int32_t width, int32_t height, const void *const *p, int n) {
     if (width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return false;

@@ -172,7 +172,18 @@ CONFIGS = {
                       pose=0, n_poses=10),
     "train_1600x1064_1M": dict(kind="3d", P=1_000_000, width=1600, height=1064, seed=1004,
                                pose=0, n_poses=1),
+    # one scene, 16 cameras on the orbit; camera k has resolution k mod 4
+    "multiview_2M_16": dict(kind="3d", P=2_000_000, seed=1005, n_views=16,
+                            resolutions=((640, 480), (1280, 720), (1920, 1080), (2560, 1440))),
 }
+
+
+def multiview_cameras(cfg: dict, n_views: int | None = None) -> list:
+    """Cameras of a multi-view workload: pose k of n_views on the orbit, at
+    resolution index k mod len(resolutions)."""
+    n = cfg["n_views"] if n_views is None else n_views
+    res = cfg["resolutions"]
+    return [orbit_camera(k, n, *res[k % len(res)]) for k in range(n)]
 
 
 def make_camera(cfg: dict, pose: int | None = None) -> Camera:

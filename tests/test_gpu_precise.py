@@ -1,0 +1,132 @@
+"""Precise Gaussian-tile intersection (gs_bin_sort_precise) against the FP64
+oracle's precise binning: exact lists on small scenes and on sampled tiles
+of the 1080p/1M frame, unchanged images, and the edge cases."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2505_24796_amd as gs  # noqa: E402
+from gpu_helpers import dev, fp32_check, host, quality  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def lists_equal(bs, r_o, i_o):
+    n = bs.n_splats()
+    assert n == len(i_o), (n, len(i_o))
+    assert np.array_equal(host(bs.ranges).astype(np.int64), r_o.astype(np.int64))
+    assert np.array_equal(host(bs.sorted_ids)[:n].astype(np.uint32), i_o)
+
+
+@pytest.mark.parametrize("W,H,P,seed,smax", [(256, 256, 2000, 1001, 8.0), (250, 190, 3000, 7, 40.0),
+                                             (96, 80, 400, 3, 60.0), (1000, 600, 20000, 21, 20.0)])
+def test_precise_lists_match_oracle(W, H, P, seed, smax):
+    say(f"precise binning {W}x{H} P={P}")
+    sc = scenegen.scene_2d(P, W, H, seed, o_min=0.002, o_max=0.99, s_max=smax)
+    m2, cov, op = dev(sc.means2d), dev(sc.cov2d), dev(sc.opacities)
+    pre = gs.preprocess_2d(m2, cov, W, H)
+    bs = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, conics=pre["conics"], opacities=op,
+                     precise=True)
+    con = host(pre["conics"]).astype(np.float64)
+    r_o, i_o = oracle.bin_splats(sc.means2d, host(pre["radii"]), sc.depths, W, H, conics=con,
+                                 opac=sc.opacities)
+    lists_equal(bs, r_o, i_o)
+    full = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H)
+    say(f"  N precise {bs.n_splats()} vs 3-sigma {full.n_splats()}")
+    assert bs.n_splats() < full.n_splats()
+    # same images: FP32 path against the oracle on the precise lists, and
+    # (nearly always bit-identical) against the 3-sigma lists' render
+    rgb = dev(sc.rgb)
+    a = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, m2, pre["conics"], op, rgb, "fp32")
+    b = gs.rasterize_fwd(W, H, full.ranges, full.sorted_ids, m2, pre["conics"], op, rgb, "fp32")
+    ia, ib = host(a.rgb), host(b.rgb)
+    same = np.all(ia == ib, axis=0).mean()
+    say(f"  fp32 pixels bit-identical to the 3-sigma render: {same:.6f}")
+    assert same >= 0.999
+    fp32_check(W, H, r_o, i_o, sc.means2d, con, sc.opacities, sc.rgb, ia, host(a.T))
+    ref = oracle.render(W, H, r_o, i_o, sc.means2d, con, sc.opacities, sc.rgb)
+    for prec in ("fp16_g2l_split", "bf16_g2l_split"):
+        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, m2, pre["conics"], op, rgb, prec)
+        q = quality(host(r.rgb), ref["rgb"])
+        assert q["psnr"] >= 50.0 and q["frac_2_255"] >= 0.999, (prec, q)
+
+
+def test_precise_edge_cases():
+    W, H = 64, 48
+    z = torch.zeros(0, 2, dtype=torch.float32, device="cuda")
+    bs = gs.BinSorter(0, 16, W, H, precise=True)
+    bs(z, torch.zeros(0, dtype=torch.int32, device="cuda"),
+       torch.zeros(0, dtype=torch.float32, device="cuda"),
+       torch.zeros(0, 3, dtype=torch.float32, device="cuda"),
+       torch.zeros(0, dtype=torch.float32, device="cuda"))
+    assert bs.n_splats() == 0 and int(host(bs.ranges).max()) == 0
+    # every opacity below 1/255: nothing can reach the culling threshold
+    sc = scenegen.scene_2d(300, W, H, 5, o_min=0.001, o_max=0.0035)
+    m2 = dev(sc.means2d)
+    pre = gs.preprocess_2d(m2, dev(sc.cov2d), W, H)
+    bs = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, capacity=64,
+                     conics=pre["conics"], opacities=dev(sc.opacities), precise=True)
+    assert bs.n_splats() == 0 and int(host(bs.ranges).max()) == 0
+    # overflow: N > capacity leaves every range empty and reports N
+    sc = scenegen.scene_2d(300, W, H, 6)
+    m2, op = dev(sc.means2d), dev(sc.opacities)
+    pre = gs.preprocess_2d(m2, dev(sc.cov2d), W, H)
+    ok = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, conics=pre["conics"], opacities=op,
+                     precise=True)
+    N = ok.n_splats()
+    small = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, capacity=N - 1,
+                        conics=pre["conics"], opacities=op, precise=True)
+    assert small.n_splats() == N and int(host(small.ranges).max()) == 0
+
+
+def test_precise_fullsize_sampled():
+    cfg = scenegen.CONFIGS["fwd_1080p_1M"]
+    W, H = cfg["width"], cfg["height"]
+    gx, gy = (W + 15) // 16, (H + 15) // 16
+    say("precise binning at 1080p/1M")
+    sc = scenegen.make_scene(cfg)
+    c = scenegen.make_camera(cfg)
+    cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
+    op = dev(sc.opacities)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    full = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
+    bs = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, conics=pre["conics"],
+                     opacities=op, precise=True)
+    Np, N3 = bs.n_splats(), full.n_splats()
+    say(f"  N precise {Np} vs 3-sigma {N3} ({Np / N3:.3f})")
+    assert Np < N3
+    m2, rad, dep = host(pre["means2d"]), host(pre["radii"]), host(pre["depths"])
+    con = host(pre["conics"]).astype(np.float64)
+    rg, ig = host(bs.ranges).astype(np.int64), host(bs.sorted_ids)
+    counts = rg[:, 1] - rg[:, 0]
+    tiles = np.unique(np.concatenate([np.argsort(-counts, kind="stable")[:6],
+                                      np.random.default_rng(3).choice(gx * gy, 20, replace=False),
+                                      [gx * gy - 1, gx - 1]])).astype(np.int32)
+    r_o, i_o = oracle.bin_tiles(m2, rad, dep, W, H, tiles, conics=con, opac=sc.opacities)
+    for j, t in enumerate(tiles):
+        assert np.array_equal(ig[rg[t, 0]:rg[t, 1]].astype(np.uint32), i_o[r_o[j, 0]:r_o[j, 1]]), t
+    # the MFMA image from the precise lists equals the 3-sigma lists' image
+    # except where a dropped splat sits within rounding of the threshold
+    rgb = pre["rgb"]
+    a = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], op, rgb,
+                         "fp16_g2l_split")
+    b = gs.rasterize_fwd(W, H, full.ranges, full.sorted_ids, pre["means2d"], pre["conics"], op,
+                         rgb, "fp16_g2l_split")
+    ia, ib = host(a.rgb), host(b.rgb)
+    same = np.all(ia == ib, axis=0).mean()
+    q = quality(ia, ib)
+    say(f"  fp16 split: bit-identical pixels {same:.6f}, PSNR vs 3-sigma lists {q['psnr']:.1f} dB")
+    assert same >= 0.999 and q["psnr"] >= 60.0
