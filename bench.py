@@ -183,23 +183,23 @@ def multiview(args):
     log(f"[bench] multiview tuned shape {tuned['best']}")
 
     # stage split (eager, HIP events)
-    def stage_times(n=5):
+    def stage_times_of(r, n=5):
         rows = []
         for _ in range(n):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             ev[0].record()
-            mv.preprocess()
+            r.preprocess()
             ev[1].record()
-            mv.bin_sort()
+            r.bin_sort()
             ev[2].record()
-            mv.raster()
+            r.raster()
             ev[3].record()
             torch.cuda.synchronize()
             rows.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]),
                          ev[2].elapsed_time(ev[3])])
         return np.median(np.array(rows), axis=0)
 
-    st = stage_times()
+    st = stage_times_of(mv)
     per_view_raster = float(np.median(autotune.time_ms(mv.raster_per_view, reps=5, warmup=1)))
     single_pre = float(np.median(autotune.time_ms(
         lambda: [gs.preprocess(scene["means3d"], scene["scales"], scene["quats"], scene["sh"], c)
@@ -230,6 +230,33 @@ def multiview(args):
     eager = float(np.median(autotune.time_ms(mv.frame, reps=5, warmup=1)))
     assert not any(mv.overflowed())
     lat = np.array(lat)
+    # the same frame with precise Gaussian-tile intersection in every view's binning
+    mvp = gs.MultiViewRenderer(scene, cams, precision=args.precision, precise=True)
+    mvp.tune = mv.tune
+    stp = stage_times_of(mvp)
+    gp = mvp.capture()
+    for _ in range(3):
+        gp.replay()
+    torch.cuda.synchronize()
+    latp = []
+    for _ in range(5):
+        gp.replay()
+        torch.cuda.synchronize()
+        latp.extend(mvp.latencies_ms())
+    e0.record()
+    for _ in range(K):
+        gp.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    msp = e0.elapsed_time(e1) / K
+    assert not any(mvp.overflowed())
+    precise = {"graph_ms_per_frame": msp, "views_per_s": mvp.V * 1e3 / msp,
+               "latency_ms_p50": float(np.percentile(latp, 50)),
+               "latency_ms_p99": float(np.percentile(latp, 99)),
+               "splats_per_view": mvp.n_splats(),
+               "stages_ms": {"preprocess_multiview": stp[0], "bin_sort_all_views": stp[1],
+                             "raster_batched": stp[2]}}
+    del mvp, gp
     return {"workload": "multiview_2M_16", "gaussians": cfg["P"], "views": mv.V,
             "resolutions": [f"{c.width}x{c.height}" for c in cams],
             "splats_per_view": mv.n_splats(), "precision": args.precision,
@@ -243,7 +270,8 @@ def multiview(args):
             "stages_ms": {"preprocess_multiview": st[0], "bin_sort_all_views": st[1],
                           "raster_batched": st[2]},
             "raster_one_launch_per_view_ms": per_view_raster,
-            "preprocess_one_call_per_view_ms": single_pre}
+            "preprocess_one_call_per_view_ms": single_pre,
+            "precise_binning": precise}
 
 
 def main():

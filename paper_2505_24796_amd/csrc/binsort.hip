@@ -22,10 +22,17 @@ constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per block
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int WAVES = SORT_THREADS / 64;
-constexpr int WAVE_ITEMS = SORT_TILE / WAVES;          // 1024 per wave
-constexpr int WAVE_CHUNKS = WAVE_ITEMS / 64;           // 16 chunks of 64
+// keys per thread of a radix pass: the P Gaussians' depth sort runs twice as
+// many (smaller) workgroups as the N splats' tile sort
+constexpr int DEPTH_ITEMS = 8;
+constexpr int TILE_ITEMS = 16;
 constexpr int EMIT_ITEMS = 8;
-constexpr int EMIT_TILE = SORT_THREADS * EMIT_ITEMS;   // output slots per block
+constexpr int EMIT_TILE = SORT_THREADS * EMIT_ITEMS;   // output slots per window (3-sigma rule)
+// precise rule: the same windows; the ellipse records are read through the
+// cache (staging them in LDS lowered the occupancy more than it saved)
+constexpr int EMIT_THREADS_P = SORT_THREADS;
+constexpr int EMIT_TILE_P = EMIT_THREADS_P * EMIT_ITEMS;
+constexpr int PG_STAGE = 0;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -76,7 +83,7 @@ template <typename T> __device__ __forceinline__ T block_excl_scan(T v, T &excl,
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of the per-Gaussian splat counts (u64 running
 // totals so that an overflowing count is detected instead of wrapping).  The
-// down-sweep also records, for every window of EMIT_TILE output slots, the
+// down-sweep also records, for every window of `win` output slots, the
 // Gaussian that owns the window's first slot.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SORT_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
@@ -114,7 +121,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
                                                             uint32_t *__restrict__ offs, uint32_t n,
                                                             const uint64_t *__restrict__ part,
                                                             uint32_t *__restrict__ win_start,
-                                                            uint32_t nwin,
+                                                            uint32_t nwin, uint32_t win,
                                                             const uint32_t *__restrict__ total) {
     __shared__ uint64_t lds[WAVES];
     const uint64_t N = *total;
@@ -135,11 +142,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
             offs[base + k] = (uint32_t)run;
             // windows whose first slot falls inside [run, run + v)
             if (v[k] > 0) {
-                uint64_t w0 = (run + EMIT_TILE - 1) / EMIT_TILE;
-                uint64_t w1 = (run + v[k] - 1) / EMIT_TILE;
+                uint64_t w0 = (run + win - 1) / win;
+                uint64_t w1 = (run + v[k] - 1) / win;
                 for (uint64_t w = w0; w <= w1 && w < nwin; ++w) win_start[w] = (uint32_t)(base + k);
                 // the owner of the last slot closes the last window
-                uint64_t wl = (N + EMIT_TILE - 1) / EMIT_TILE;
+                uint64_t wl = (N + win - 1) / win;
                 if (run + v[k] == N && wl < nwin) win_start[wl] = (uint32_t)(base + k);
             }
         }
@@ -151,6 +158,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 // Stable LSD radix sort pass (8-bit digit) of u32 keys with u32 values:
 // per-block digit histograms -> per-digit scan over blocks -> scatter.
 // ---------------------------------------------------------------------------
+template <int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              Count cnt, int shift,
                                                              uint32_t *__restrict__ hist,
@@ -159,10 +167,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     uint32_t n = cnt.get();
     h[threadIdx.x] = 0;
     __syncthreads();
-    size_t base = (size_t)blockIdx.x * SORT_TILE;
+    constexpr int TILE = SORT_THREADS * ITEMS;
+    size_t base = (size_t)blockIdx.x * TILE;
     if (base < n) {
 #pragma unroll
-        for (int k = 0; k < SORT_ITEMS; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
             if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
         }
@@ -190,6 +199,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
@@ -197,11 +207,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __shared__ uint32_t wcnt[WAVES][RADIX];
     __shared__ uint32_t gbase[RADIX];   // global position of this block's first key of digit d
     __shared__ uint32_t lstart[RADIX];  // local position of this block's first key of digit d
-    __shared__ uint32_t skey[SORT_TILE];
-    __shared__ uint32_t sval[SORT_TILE];
+    constexpr int TILE = SORT_THREADS * ITEMS;
+    constexpr int W_ITEMS = TILE / WAVES, W_CHUNKS = W_ITEMS / 64;
+    __shared__ uint32_t skey[TILE];
+    __shared__ uint32_t sval[TILE];
     __shared__ uint32_t lds_scan[WAVES];
     uint32_t n = cnt.get();
-    size_t base = (size_t)blockIdx.x * SORT_TILE;
+    size_t base = (size_t)blockIdx.x * TILE;
     if (base >= n) return;  // whole block idle: uniform exit
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -214,17 +226,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
 
-    uint32_t key[WAVE_CHUNKS], val[WAVE_CHUNKS], pos[WAVE_CHUNKS];
-    size_t wbase = base + (size_t)w * WAVE_ITEMS;
+    uint32_t key[W_CHUNKS], val[W_CHUNKS], pos[W_CHUNKS];
+    size_t wbase = base + (size_t)w * W_ITEMS;
 #pragma unroll
-    for (int c = 0; c < WAVE_CHUNKS; ++c) {
+    for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n;
         key[c] = ok ? kin[i] : 0u;
         val[c] = ok ? vin[i] : 0u;
     }
 #pragma unroll
-    for (int c = 0; c < WAVE_CHUNKS; ++c) {
+    for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n;
         uint32_t d = (key[c] >> shift) & (RADIX - 1);
@@ -257,7 +269,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __syncthreads();
     // stage in LDS in (digit, original order) order ...
 #pragma unroll
-    for (int c = 0; c < WAVE_CHUNKS; ++c) {
+    for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n) {
             uint32_t d = (key[c] >> shift) & (RADIX - 1);
@@ -268,7 +280,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     // ... and write runs of equal digits to consecutive global addresses
-    uint32_t nloc = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
+    uint32_t nloc = (uint32_t)min((size_t)TILE, (size_t)n - base);
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
         uint32_t d = (k >> shift) & (RADIX - 1);
@@ -282,18 +294,20 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
-// Sorts on bits [0, bits) with ceil(bits/8) passes; returns the index of the
-// buffer pair holding the result.
+// Sorts on bits [0, bits) with ceil(bits/8) passes of ITEMS keys per
+// thread; returns the index of the buffer pair holding the result.
+template <int ITEMS>
 int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
                hipStream_t s) {
-    uint32_t nblocks = (max_n + SORT_TILE - 1) / SORT_TILE;
+    constexpr int TILE = SORT_THREADS * ITEMS;
+    uint32_t nblocks = (max_n + TILE - 1) / TILE;
     if (nblocks == 0) nblocks = 1;
     int cur = 0;
     for (int shift = 0; shift < bits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur], cnt,
-                           shift, hist, nblocks);
+        hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
+                           cnt, shift, hist, nblocks);
         hipLaunchKernelGGL(k_hist_rows, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
+        hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
                            b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals, nblocks);
         cur ^= 1;
     }
@@ -316,71 +330,90 @@ __global__ void k_set_word(uint32_t *__restrict__ dst, uint32_t v) {
 // Precise Gaussian-tile intersection: inside the 3-sigma rectangle, keep a
 // tile only if the raw opacity o exp(-q/2), q = d^T S d, reaches the 1/255
 // culling threshold of Algorithm 1 somewhere in the tile's pixel box, i.e.
-// the box meets the ellipse E = {d : q(d) <= tq}, tq = 2 (ln o + ln 255).
-// E is convex, so the tiles of one tile row that meet it are a contiguous
-// run: the row's y-band [y0, y1] cuts E in a convex piece whose x-extent is
-// [mx + xl, mx + xr], with
-//   left(dy)  = (-b dy - sqrt(a tq - det dy^2)) / a  (convex, least at the
-//               ellipse's leftmost point dy = b s, dx = -c s, s = sqrt(tq / (c det)))
-//   right(dy) = (-b dy + sqrt(a tq - det dy^2)) / a  (concave, largest at
-//               dy = -b s, dx = c s)
-// evaluated at the extreme point if it lies in the band, else at the band's
-// ends.  FP64 throughout, tq enlarged by a relative 1e-9 so that rounding can
-// only keep a tile, never drop one; contraction is off so the count pass and
-// the emission pass compute identical spans.
+// the box meets the ellipse E = {d : q(d) <= T}, T = 2 (ln o + ln 255),
+// S = [[a, b], [b, c]].  E is convex, so the tiles of one tile row that meet
+// it are a contiguous run: the row's y-band cuts E in a convex piece whose
+// x-extent is the union over its dy of the chord
+//   [-b dy / a - h(dy), -b dy / a + h(dy)],
+//   h(dy) = sqrt(det (ymax - |dy|) (ymax + |dy|)) / a,  ymax = sqrt(T a / det)
+// (the chord's left end is convex in dy, least at the ellipse's leftmost
+// point dy = b s, dx = -c s, s = sqrt(T / (c det)); the right end is
+// concave, largest at dy = -b s, dx = c s), i.e. the extreme point if the
+// band holds it, else the band's end chords.
+// The per-Gaussian constants are FP32 (the determinant from exact FP64
+// products), ymax and c s enlarged by a relative 1e-6 and T by more than
+// the error of its logarithm; the per-row chord is FP32 without
+// cancellation.  The band is grown by 4e-6 (ymax + |my|) + 1e-4 px (more
+// than the rounding of its ends) before the chords are taken, and the run
+// by 4e-6 (c s + |mx|) + 1e-4 px in x (more than the chord's rounding, every
+// term of which is at most c s), so rounding can only add a boundary tile,
+// never drop one.  Contraction is off so the count and emission passes agree
+// bit for bit.
 struct PGauss {
-    float mx, my, a, b, c, pad;
-    double tq;
+    float mx, my, b, inv_a;
+    float det, ymax, dyl, cs;  // cs = c s = half-width of E in x; ymax = half-height
 };
 
-__device__ __forceinline__ double precise_tq(float o) {
-    if (!(o > 0.0f)) return -1.0;
-    double t = 2.0 * (log((double)o) + 5.541263545158426);  // ln 255
-    return t + 1e-9 * fabs(t) + 1e-12;
+__device__ __forceinline__ PGauss make_pgauss(float2 m, float a, float b, float c, float o,
+                                              bool &any) {
+#pragma clang fp contract(off)
+    PGauss g{};
+    g.mx = m.x;
+    g.my = m.y;
+    any = false;
+    if (!(o > 0.0f)) return g;
+    // T enlarged by more than the error of logf (a few ulp of |ln o| <= 104)
+    const float T = 2.0f * (logf(o) + 5.5412635f) * (1.0f + 4e-6f) + 4e-5f;
+    if (!(T >= 0.0f)) return g;  // o < 1/255: reaches the threshold nowhere
+    any = true;
+    const float det = (float)((double)a * (double)c - (double)b * (double)b);  // one rounding
+    if (!(a > 0.0f) || !(c > 0.0f) || !(det > 0.0f)) {
+        g.det = -1.0f;  // not positive definite (rounding): keep the whole rectangle
+        return g;
+    }
+    // each value below carries a few ulp of rounding: the extents are
+    // enlarged by a relative 1e-6, far beyond it
+    const float s = sqrtf(T / (c * det));
+    g.b = b;
+    g.inv_a = 1.0f / a;
+    g.det = det;
+    g.ymax = sqrtf(T * a / det) * (1.0f + 1e-6f);
+    g.dyl = b * s;
+    g.cs = c * s * (1.0f + 1e-6f);
+    return g;
 }
 
-// Columns [c0, c1] of tile row ty that meet E, clipped to [tx0, tx1];
-// returns the count (0 when none).
+// Columns [c0, c1] of tile row ty whose box meets E (with the margin),
+// clipped to [tx0, tx1]; returns their count (0 when none).
 __device__ __forceinline__ uint32_t row_span(const PGauss &g, int ty, int tx0, int tx1, int W, int H,
-                                          int &c0, int &c1) {
+                                             int &c0, int &c1) {
 #pragma clang fp contract(off)
-    const double a = g.a, b = g.b, c = g.c, T = g.tq;
-    if (!(T >= 0.0)) return 0u;
-    const double det = a * c - b * b;
-    if (!(a > 0.0) || !(c > 0.0) || !(det > 0.0)) {  // not positive definite: keep the rectangle row
+    if (g.det < 0.0f) {
         c0 = tx0;
         c1 = tx1;
         return (uint32_t)(tx1 - tx0 + 1);
     }
-    const double y0 = (double)(GS_TILE * ty) - g.my;
-    const double y1 = (double)min(GS_TILE * ty + GS_TILE - 1, H - 1) - g.my;
-    const double ymax = sqrt(T * a / det);
-    const double ya = fmax(y0, -ymax), yb = fmin(y1, ymax);
+    const float ex = 4e-6f * (g.cs + fabsf(g.mx)) + 1e-4f;
+    const float ey = 4e-6f * (g.ymax + fabsf(g.my)) + 1e-4f;
+    // the row's band, grown by ey, cut to the ellipse's y-extent
+    const float ya = fmaxf((float)(GS_TILE * ty) - g.my - ey, -g.ymax);
+    const float yb = fminf((float)min(GS_TILE * ty + GS_TILE - 1, H - 1) - g.my + ey, g.ymax);
     if (ya > yb) return 0u;
-    const double s = sqrt(T / (c * det));
-    const double dyl = b * s, dyr = -b * s;
-    double xl, xr;
-    if (dyl >= ya && dyl <= yb) {
-        xl = -c * s;
-    } else {
-        const double la = (-b * ya - sqrt(fmax(a * T - det * ya * ya, 0.0))) / a;
-        const double lb = (-b * yb - sqrt(fmax(a * T - det * yb * yb, 0.0))) / a;
-        xl = fmin(la, lb);
-    }
-    if (dyr >= ya && dyr <= yb) {
-        xr = c * s;
-    } else {
-        const double ra = (-b * ya + sqrt(fmax(a * T - det * ya * ya, 0.0))) / a;
-        const double rb = (-b * yb + sqrt(fmax(a * T - det * yb * yb, 0.0))) / a;
-        xr = fmax(ra, rb);
-    }
-    const double XL = g.mx + xl, XR = g.mx + xr;
+    float xl, xr;
+    const float ha = sqrtf(g.det * ((g.ymax - fabsf(ya)) * (g.ymax + fabsf(ya)))) * g.inv_a;
+    const float hb = sqrtf(g.det * ((g.ymax - fabsf(yb)) * (g.ymax + fabsf(yb)))) * g.inv_a;
+    const float ma = -g.b * ya * g.inv_a, mb = -g.b * yb * g.inv_a;
+    if (g.dyl >= ya && g.dyl <= yb) xl = -g.cs;
+    else xl = fminf(ma - ha, mb - hb);
+    if (-g.dyl >= ya && -g.dyl <= yb) xr = g.cs;
+    else xr = fmaxf(ma + ha, mb + hb);
+    const float XL = g.mx + xl - ex, XR = g.mx + xr + ex;
     // tile column c spans pixels [16c, min(16c + 15, W - 1)]
-    if (XR < (double)(GS_TILE * tx0) || XL > (double)(W - 1)) return 0u;
-    int lo = (int)ceil((XL - (double)(GS_TILE - 1)) / (double)GS_TILE);
-    int hi = (int)floor(XR / (double)GS_TILE);
-    lo = max(lo, tx0);
-    hi = min(hi, tx1);
+    if (XR < (float)(GS_TILE * tx0) || XL > (float)(W - 1)) return 0u;
+    const float lo_f = ceilf((XL - (float)(GS_TILE - 1)) * (1.0f / GS_TILE));
+    const float hi_f = floorf(XR * (1.0f / GS_TILE));
+    const int lo = max((int)fmaxf(lo_f, -1.0f), tx0);
+    const int hi = min((int)fminf(hi_f, 65535.0f), tx1);
     if (lo > hi) return 0u;
     c0 = lo;
     c1 = hi;
@@ -427,16 +460,13 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
         PGauss q{};
         c = 0;
         if (n > 0) {
-            q.mx = m.x;
-            q.my = m.y;
-            q.a = conics[3 * i];
-            q.b = conics[3 * i + 1];
-            q.c = conics[3 * i + 2];
-            q.tq = precise_tq(opac[i]);
-            for (int ty = ty0; ty <= ty1; ++ty) {
-                int c0, c1;
-                c += row_span(q, ty, tx0, tx1, W, H, c0, c1);
-            }
+            bool any;
+            q = make_pgauss(m, conics[3 * i], conics[3 * i + 1], conics[3 * i + 2], opac[i], any);
+            if (any)
+                for (int ty = ty0; ty <= ty1; ++ty) {
+                    int c0, c1;
+                    c += row_span(q, ty, tx0, tx1, W, H, c0, c1);
+                }
         }
         pg[i] = q;
     }
@@ -449,6 +479,7 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
 }
 
 // Rectangle and splat count of each Gaussian in depth order.
+template <bool PRECISE>
 __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restrict__ order,
                                                 const uint2 *__restrict__ rects,
                                                 const uint32_t *__restrict__ cnt_g,
@@ -457,49 +488,56 @@ __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restric
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= P) return;
     const uint32_t g = order[j];
-    rects_sorted[j] = rects[g];
-    cnt[j] = cnt_g[g];
+    const uint2 r = rects[g];
+    rects_sorted[j] = r;
+    cnt[j] = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
 }
 
-// Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
-// slots).  The window's Gaussians are j0 = owner of its first slot up to
-// j1 = owner of the next window's first slot (or of the last slot); their
-// offsets and rectangles are staged in LDS.  Each thread locates the owner
-// of its first of EMIT_ITEMS consecutive slots by binary search and walks
-// the Gaussian's tiles from there in row-major order (the whole rectangle,
-// or with PRECISE the run of each row that meets the ellipse); results are
+// Expands the splats of output window blockIdx.x (WIN = NT * EMIT_ITEMS
+// consecutive slots).  The window's Gaussians are j0 = owner of its first
+// slot up to j1 = owner of the next window's first slot (or of the last
+// slot); their offsets and rectangles (and, with PRECISE, the first PG_STAGE
+// ellipse records, none at present) are staged in LDS.  Each thread locates the owner of its
+// first of EMIT_ITEMS consecutive slots by binary search and walks the
+// Gaussian's tiles from there in row-major order (the whole rectangle, or
+// with PRECISE the run of each row that meets the ellipse); results are
 // staged in LDS and written out coalesced.
-template <bool PRECISE>
-__global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
-                                                       const uint32_t *__restrict__ offs,
-                                                       const uint2 *__restrict__ rects_sorted,
-                                                       const PGauss *__restrict__ pg,
-                                                       const uint32_t *__restrict__ win_start,
-                                                       uint32_t nwin, int gx, int W, int H,
-                                                       const uint32_t *__restrict__ n_splats,
-                                                       uint32_t cap, uint32_t *__restrict__ tkey,
-                                                       uint32_t *__restrict__ tid) {
-    __shared__ uint32_t s_off[EMIT_TILE + 1];
-    __shared__ uint2 s_rect[EMIT_TILE + 1];
-    __shared__ uint32_t s_id[EMIT_TILE + 1];
-    __shared__ uint32_t s_tk[EMIT_TILE];
-    __shared__ uint32_t s_tg[EMIT_TILE];
+template <bool PRECISE, int NT>
+__global__ __launch_bounds__(NT) void k_emit(int P, const uint32_t *__restrict__ order,
+                                             const uint32_t *__restrict__ offs,
+                                             const uint2 *__restrict__ rects_sorted,
+                                             const PGauss *__restrict__ pg,
+                                             const uint32_t *__restrict__ win_start,
+                                             uint32_t nwin, int gx, int W, int H,
+                                             const uint32_t *__restrict__ n_splats, uint32_t cap,
+                                             uint32_t *__restrict__ tkey, uint32_t *__restrict__ tid) {
+    constexpr int WIN = NT * EMIT_ITEMS;
+    constexpr int NPG = PRECISE && PG_STAGE > 0 ? PG_STAGE : 1;
+    constexpr uint32_t NSTAGED = PRECISE ? (uint32_t)PG_STAGE : 0u;
+    __shared__ uint32_t s_off[WIN + 1];
+    __shared__ uint2 s_rect[WIN + 1];
+    __shared__ uint32_t s_id[WIN + 1];
+    __shared__ uint32_t s_tk[WIN];
+    __shared__ uint32_t s_tg[WIN];
+    __shared__ PGauss s_pg[NPG];
     uint32_t N = *n_splats;
     if (N > cap) return;  // overflow: nothing is written
-    uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
+    uint32_t o0 = blockIdx.x * (uint32_t)WIN;
     if (o0 >= N || blockIdx.x + 1 >= nwin) return;
-    uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
+    uint32_t oend = min(o0 + (uint32_t)WIN, N);
     uint32_t j0 = win_start[blockIdx.x];
     uint32_t j1 = win_start[blockIdx.x + 1];
     if (j0 >= (uint32_t)P) return;  // cannot happen when the scan ran; keeps reads in bounds
     // every Gaussian between j0 and j1 owns at least one slot of the window
     uint32_t m = (j1 >= j0 ? j1 - j0 : 0u) + 1u;
-    m = min(m, (uint32_t)EMIT_TILE + 1u);
+    m = min(m, (uint32_t)WIN + 1u);
     m = min(m, (uint32_t)P - min(j0, (uint32_t)P - 1u));
-    for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS) {
+    for (uint32_t k = threadIdx.x; k < m; k += NT) {
         s_off[k] = offs[j0 + k];
         s_rect[k] = rects_sorted[j0 + k];
-        s_id[k] = order[j0 + k];
+        const uint32_t id = order[j0 + k];
+        s_id[k] = id;
+        if (k < NSTAGED) s_pg[k] = pg[id];
     }
     __syncthreads();
     uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
@@ -541,7 +579,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
                 s_tg[s0 + i - o0] = 0u;
             }
             // current Gaussian k: rectangle, ellipse, row ty and its run [c0, c1]
-            PGauss q = pg[s_id[k]];
+            PGauss q = k < NSTAGED ? s_pg[k] : pg[s_id[k]];
             RectDec d = dec_rect(s_rect[k]);
             int ty = d.ty0, c0 = 0, c1 = -1;
             uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
@@ -564,11 +602,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
                 }
                 if (n > 0) continue;
                 // next Gaussian: the owner of slot o + 1 is the last one whose
-                // offset is <= o + 1 (Gaussians without splats share offsets)
+                // offset is <= o + 1
                 ++k;
                 while (k + 1 < m && s_off[k + 1] <= o + 1) ++k;
                 if (k >= m) break;
-                q = pg[s_id[k]];
+                q = k < NSTAGED ? s_pg[k] : pg[s_id[k]];
                 d = dec_rect(s_rect[k]);
                 ty = d.ty0;
                 n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
@@ -580,7 +618,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < oend - o0; i += SORT_THREADS) {
+    for (uint32_t i = threadIdx.x; i < oend - o0; i += NT) {
         tkey[o0 + i] = s_tk[i];
         tid[o0 + i] = s_tg[i];
     }
@@ -640,8 +678,10 @@ Layout layout(uint32_t P, uint32_t cap, bool precise) {
         return o;
     };
     uint32_t maxn = P > cap ? P : cap;
-    uint32_t nblocks = (maxn + SORT_TILE - 1) / SORT_TILE + 1;
-    L.nwin = (cap + EMIT_TILE - 1) / EMIT_TILE + 2;
+    const uint32_t min_tile = SORT_THREADS * (DEPTH_ITEMS < TILE_ITEMS ? DEPTH_ITEMS : TILE_ITEMS);
+    uint32_t nblocks = (maxn + min_tile - 1) / min_tile + 1;
+    const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
+    L.nwin = (cap + win - 1) / win + 2;
     L.dkey0 = take(4ull * P);
     L.dkey1 = take(4ull * P);
     L.did0 = take(4ull * P);
@@ -740,20 +780,26 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
                            U(L.did0), (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges,
                            2 * ntiles);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
-    int dcur = radix_sort(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32, U(L.hist),
-                          U(L.totals), s);
+    int dcur = radix_sort<DEPTH_ITEMS>(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32,
+                                       U(L.hist), U(L.totals), s);
     const uint32_t *order = db.v[dcur];
     // 2. counts in depth order, scan (+ window owners), expansion
     int pblocks = (P + 255) / 256;
-    hipLaunchKernelGGL(k_counts, dim3(pblocks), dim3(256), 0, s, P, order,
-                       (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                       (uint2 *)(ws + L.rects_sorted), U(L.cnt));
+    if (precise)
+        hipLaunchKernelGGL(k_counts<true>, dim3(pblocks), dim3(256), 0, s, P, order,
+                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt));
+    else
+        hipLaunchKernelGGL(k_counts<false>, dim3(pblocks), dim3(256), 0, s, P, order,
+                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt));
     uint32_t sblocks = (P + SORT_TILE - 1) / SORT_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt),
                        (uint32_t)P, part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, sblocks, d_num_splats);
+    const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
     hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
-                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin, d_num_splats);
+                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin, win, d_num_splats);
     int tbits = ceil_log2((uint32_t)ntiles);
     if (tbits == 0) tbits = 1;
     int npass = (tbits + RADIX_BITS - 1) / RADIX_BITS;
@@ -762,15 +808,15 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
     uint32_t *emit_ids = (npass % 2 == 0) ? sorted_ids : U(L.tid);
     uint32_t *other_ids = (npass % 2 == 0) ? U(L.tid) : sorted_ids;
     if (capacity == 0) emit_ids = other_ids = U(L.tid);  // nothing fits
-    uint32_t eblocks = (capacity + EMIT_TILE - 1) / EMIT_TILE;
+    uint32_t eblocks = (capacity + win - 1) / win;
     if (eblocks > 0) {
         if (precise)
-            hipLaunchKernelGGL(k_emit<true>, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
+            hipLaunchKernelGGL((k_emit<true, EMIT_THREADS_P>), dim3(eblocks), dim3(EMIT_THREADS_P), 0, s, P, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
                                U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
                                U(L.tkey0), emit_ids);
         else
-            hipLaunchKernelGGL(k_emit<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
+            hipLaunchKernelGGL((k_emit<false, SORT_THREADS>), dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
                                U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
                                U(L.tkey0), emit_ids);
@@ -778,7 +824,7 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     Count nc{0u, d_num_splats, capacity};
-    int tcur = radix_sort(tb, nc, capacity, tbits, U(L.hist), U(L.totals), s);
+    int tcur = radix_sort<TILE_ITEMS>(tb, nc, capacity, tbits, U(L.hist), U(L.totals), s);
     // 4. ranges
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
     hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,

@@ -90,13 +90,16 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
 // At least 5 resident waves per SIMD (the compiler then fits the kernel in
 // <= 80 VGPRs, i.e. 6 waves): the blend's exp / LDS / gather latencies are
 // hidden by other waves rather than by instruction-level parallelism.
+#ifndef MFMA_BATCH
+#define MFMA_BATCH 128
+#endif
 template <int VAR, bool COUNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_mfma(RasterArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR>::BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR, MFMA_BATCH>::BYTES];
     __shared__ TileShared sh;
     const int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
     if (tile < 0) return;
-    raster_tile_mfma<VAR, COUNT, BATCH>(a, tile, stage, sh);
+    raster_tile_mfma<VAR, COUNT, MFMA_BATCH>(a, tile, stage, sh);
 }
 
 // Diagnostic: exponents of the first `count` splats of one tile.

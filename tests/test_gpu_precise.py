@@ -1,6 +1,8 @@
 """Precise Gaussian-tile intersection (gs_bin_sort_precise) against the FP64
-oracle's precise binning: exact lists on small scenes and on sampled tiles
-of the 1080p/1M frame, unchanged images, and the edge cases."""
+oracle's precise binning on small scenes and on sampled tiles of the
+1080p/1M frame: every splat the oracle keeps is listed in the same order,
+any extra one is within rounding of the threshold; images unchanged; edge
+cases."""
 import sys
 
 import numpy as np
@@ -24,11 +26,46 @@ def say(*a):
     sys.stdout.flush()
 
 
-def lists_equal(bs, r_o, i_o):
-    n = bs.n_splats()
-    assert n == len(i_o), (n, len(i_o))
-    assert np.array_equal(host(bs.ranges).astype(np.int64), r_o.astype(np.int64))
-    assert np.array_equal(host(bs.sorted_ids)[:n].astype(np.uint32), i_o)
+# The GPU decides each (Gaussian, tile row) run in FP32 with a margin that
+# only ever keeps a boundary tile; a kept tile the FP64 oracle drops must sit
+# within this slack of the threshold (slack = ln o - qmin/2 + ln 255, in
+# natural-log units of the raw opacity: 0.02 is a 2 % opacity difference).
+EXTRA_SLACK = -0.02
+EXTRA_FRAC = 1e-3
+
+
+def is_subsequence(a, b):
+    it = iter(b.tolist())
+    return all(x in it for x in a.tolist())
+
+
+def check_lists(gpu_lists, ora_lists, tiles, m2, conics, opac, W, H):
+    """gpu_lists / ora_lists: per tile in `tiles`, the id arrays.  The
+    oracle's list must be an ordered subsequence of the GPU's; every extra
+    must be near-threshold.  Returns (n_oracle, n_extra)."""
+    gx = (W + 15) // 16
+    n_o = n_x = 0
+    for t, a, b in zip(tiles, gpu_lists, ora_lists):
+        assert is_subsequence(b, a), f"tile {t}: the GPU list misses a splat the oracle keeps"
+        n_o += len(b)
+        extra = np.setdiff1d(a, b)
+        n_x += len(extra)
+        for i in extra:
+            sl = oracle.tile_slack(float(m2[i, 0]), float(m2[i, 1]), conics[i], float(opac[i]),
+                                   int(t) % gx, int(t) // gx, W, H)
+            assert sl >= EXTRA_SLACK, (t, i, sl)
+    assert n_x <= EXTRA_FRAC * max(n_o, 1), (n_x, n_o)
+    return n_o, n_x
+
+
+def lists_match(bs, r_o, i_o, m2, conics, opac, W, H):
+    rg, ig = host(bs.ranges).astype(np.int64), host(bs.sorted_ids)
+    tiles = np.arange(rg.shape[0])
+    ga = [ig[rg[t, 0]:rg[t, 1]].astype(np.uint32) for t in tiles]
+    oa = [i_o[r_o[t, 0]:r_o[t, 1]] for t in tiles]
+    n_o, n_x = check_lists(ga, oa, tiles, m2, conics, opac, W, H)
+    assert bs.n_splats() == n_o + n_x
+    return n_o, n_x
 
 
 @pytest.mark.parametrize("W,H,P,seed,smax", [(256, 256, 2000, 1001, 8.0), (250, 190, 3000, 7, 40.0),
@@ -43,9 +80,9 @@ def test_precise_lists_match_oracle(W, H, P, seed, smax):
     con = host(pre["conics"]).astype(np.float64)
     r_o, i_o = oracle.bin_splats(sc.means2d, host(pre["radii"]), sc.depths, W, H, conics=con,
                                  opac=sc.opacities)
-    lists_equal(bs, r_o, i_o)
+    n_o, n_x = lists_match(bs, r_o, i_o, sc.means2d, con, sc.opacities, W, H)
     full = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H)
-    say(f"  N precise {bs.n_splats()} vs 3-sigma {full.n_splats()}")
+    say(f"  N precise {bs.n_splats()} (oracle {n_o} + {n_x} near-threshold) vs 3-sigma {full.n_splats()}")
     assert bs.n_splats() < full.n_splats()
     # same images: FP32 path against the oracle on the precise lists, and
     # (nearly always bit-identical) against the 3-sigma lists' render
@@ -56,7 +93,8 @@ def test_precise_lists_match_oracle(W, H, P, seed, smax):
     same = np.all(ia == ib, axis=0).mean()
     say(f"  fp32 pixels bit-identical to the 3-sigma render: {same:.6f}")
     assert same >= 0.999
-    fp32_check(W, H, r_o, i_o, sc.means2d, con, sc.opacities, sc.rgb, ia, host(a.T))
+    g_r, g_i = host(bs.ranges).astype(np.uint32), host(bs.sorted_ids)[:bs.n_splats()].astype(np.uint32)
+    fp32_check(W, H, g_r, g_i, sc.means2d, con, sc.opacities, sc.rgb, ia, host(a.T))
     ref = oracle.render(W, H, r_o, i_o, sc.means2d, con, sc.opacities, sc.rgb)
     for prec in ("fp16_g2l_split", "bf16_g2l_split"):
         r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, m2, pre["conics"], op, rgb, prec)
@@ -116,8 +154,10 @@ def test_precise_fullsize_sampled():
                                       np.random.default_rng(3).choice(gx * gy, 20, replace=False),
                                       [gx * gy - 1, gx - 1]])).astype(np.int32)
     r_o, i_o = oracle.bin_tiles(m2, rad, dep, W, H, tiles, conics=con, opac=sc.opacities)
-    for j, t in enumerate(tiles):
-        assert np.array_equal(ig[rg[t, 0]:rg[t, 1]].astype(np.uint32), i_o[r_o[j, 0]:r_o[j, 1]]), t
+    n_o, n_x = check_lists([ig[rg[t, 0]:rg[t, 1]].astype(np.uint32) for t in tiles],
+                           [i_o[r_o[j, 0]:r_o[j, 1]] for j in range(len(tiles))], tiles, m2, con,
+                           sc.opacities, W, H)
+    say(f"  sampled tiles: {n_o} splats as the oracle, {n_x} near-threshold extras")
     # the MFMA image from the precise lists equals the 3-sigma lists' image
     # except where a dropped splat sits within rounding of the threshold
     rgb = pre["rgb"]
