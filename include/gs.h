@@ -150,7 +150,7 @@ size_t gs_bin_sort_precise_workspace_bytes(int32_t P, uint32_t capacity, int32_t
 /*
  * gs_bin_sort_precise -- gs_bin_sort with a precise Gaussian-tile
  * intersection (the tighter binning of the pipelines TC-GS composes with,
- * Sec. 2 and Table 4): of the tiles the 3-sigma rectangle covers, a
+ * Sec. 2.1, Tables 3 and 4): of the tiles the 3-sigma rectangle covers, a
  * Gaussian is listed only on those whose pixel box [16 tx, min(16 tx + 15,
  * W - 1)] x [same in y] holds a point where its raw opacity
  * o exp(-1/2 d^T S d) reaches the 1/255 culling threshold of Algorithm 1

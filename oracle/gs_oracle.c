@@ -332,7 +332,7 @@ static int splat_cmp(const void *pa, const void *pb)
 }
 
 /* Precise Gaussian-tile intersection (the tighter binning of the pipelines
- * TC-GS composes with, Sec. 2 and Table 4): keep a tile of the 3-sigma
+ * TC-GS composes with, Sec. 2.1, Tables 3 and 4): keep a tile of the 3-sigma
  * rectangle only if the raw opacity o exp(-q/2), q = d^T S d, d = p - mu',
  * reaches the culling threshold 1/255 of Algorithm 1 somewhere in the
  * tile's pixel box [16 tx, min(16 tx + 15, W - 1)] x [same in y] (the
