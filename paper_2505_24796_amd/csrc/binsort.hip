@@ -28,11 +28,11 @@ constexpr int DEPTH_ITEMS = 8;
 constexpr int TILE_ITEMS = 16;
 constexpr int EMIT_ITEMS = 8;
 constexpr int EMIT_TILE = SORT_THREADS * EMIT_ITEMS;   // output slots per window (3-sigma rule)
-// precise rule: the same windows; the ellipse records are read through the
-// cache (staging them in LDS lowered the occupancy more than it saved)
-constexpr int EMIT_THREADS_P = SORT_THREADS;
-constexpr int EMIT_TILE_P = EMIT_THREADS_P * EMIT_ITEMS;
-constexpr int PG_STAGE = 0;
+// precise rule: windows of 256 threads x 4 slots, with a table of up to
+// RCAP (Gaussian, tile row) runs per window
+constexpr int EMIT_ITEMS_P = 4;
+constexpr int EMIT_TILE_P = SORT_THREADS * EMIT_ITEMS_P;
+constexpr int RCAP = 1280;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -121,8 +121,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
                                                             uint32_t *__restrict__ offs, uint32_t n,
                                                             const uint64_t *__restrict__ part,
                                                             uint32_t *__restrict__ win_start,
-                                                            uint32_t nwin, uint32_t win,
+                                                            uint32_t nwin, int wshift,
                                                             const uint32_t *__restrict__ total) {
+    const uint64_t win = 1ull << wshift;  // window size (a power of two)
     __shared__ uint64_t lds[WAVES];
     const uint64_t N = *total;
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
@@ -142,11 +143,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
             offs[base + k] = (uint32_t)run;
             // windows whose first slot falls inside [run, run + v)
             if (v[k] > 0) {
-                uint64_t w0 = (run + win - 1) / win;
-                uint64_t w1 = (run + v[k] - 1) / win;
+                uint64_t w0 = (run + win - 1) >> wshift;
+                uint64_t w1 = (run + v[k] - 1) >> wshift;
                 for (uint64_t w = w0; w <= w1 && w < nwin; ++w) win_start[w] = (uint32_t)(base + k);
                 // the owner of the last slot closes the last window
-                uint64_t wl = (N + win - 1) / win;
+                uint64_t wl = (N + win - 1) >> wshift;
                 if (run + v[k] == N && wl < nwin) win_start[wl] = (uint32_t)(base + k);
             }
         }
@@ -235,6 +236,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         key[c] = ok ? kin[i] : 0u;
         val[c] = ok ? vin[i] : 0u;
     }
+    // Rank of each key among the wave's keys of its digit, in input order:
+    // within a chunk of 64 from the lanes below with the same digit (one
+    // ballot per digit bit); across chunks from a per-wave digit counter
+    // that the chunk's lowest lane of each digit advances with an LDS
+    // atomic returning the count so far.  LDS operations of one wave
+    // execute in issue order, so the atomics of all chunks are issued back
+    // to back and still see the chunks in order; one wait, then each lane
+    // takes its digit's base from that lowest lane.
+    uint32_t lead[W_CHUNKS];
 #pragma unroll
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
@@ -248,9 +258,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
             peers &= bit ? m : ~m;
         }
         uint32_t rank = gs::lanes_below(peers);
-        uint32_t before = ok ? wcnt[w][d] : 0u;
-        pos[c] = before + rank;
-        if (ok && rank == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        pos[c] = rank;
+        lead[c] = ok ? (uint32_t)__builtin_ctzll(peers) : (uint32_t)lane;
+        if (ok && rank == 0) pos[c] = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(peers)) | 0x80000000u;
+    }
+#pragma unroll
+    for (int c = 0; c < W_CHUNKS; ++c) {
+        // the leader holds (count before | flag); the others their rank
+        const uint32_t b = (uint32_t)__shfl((int)pos[c], (int)lead[c], 64) & 0x7FFFFFFFu;
+        pos[c] = (pos[c] & 0x80000000u) ? b : b + pos[c];
     }
     __syncthreads();
     {
@@ -446,29 +462,72 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     uint32_t *__restrict__ ranges, int n2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n2) ranges[i] = 0u;
-    if (i >= P) return;
-    float d = depths[i];
+    // (with PRECISE every lane of a wave takes part in the row loop, so
+    // lanes past P stay, as Gaussians without tiles)
+    if (!PRECISE && i >= P) return;
+    const bool live = i < P;
+    float d = live ? depths[i] : 0.0f;
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
     int n = 0;
     float2 m = make_float2(0.f, 0.f);
-    if (isfinite(d)) {
+    if (live && isfinite(d)) {
         m = means2d[i];
         n = gs::tile_rect(m.x, m.y, radii[i], W, H, gx, tx0, tx1, ty0, ty1);
     }
     uint32_t c = (uint32_t)n;
     if (PRECISE) {
+        // The wave's (Gaussian, tile row) pairs are spread over its 64 lanes
+        // (a Gaussian spans 1 to ~100 rows; one lane per Gaussian would make
+        // the wave wait for its tallest one); each pair adds its run length
+        // to its Gaussian's count in LDS.
+        __shared__ PGauss s_q[256];
+        __shared__ int s_rows[256][3];  // tx0, tx1, ty0 of the rectangle
+        __shared__ uint32_t s_start[256];
+        __shared__ uint32_t s_cnt[256];
+        const int lane = threadIdx.x & 63, wb = threadIdx.x & ~63;
         PGauss q{};
-        c = 0;
+        uint32_t h = 0;
         if (n > 0) {
             bool any;
             q = make_pgauss(m, conics[3 * i], conics[3 * i + 1], conics[3 * i + 2], opac[i], any);
-            if (any)
-                for (int ty = ty0; ty <= ty1; ++ty) {
-                    int c0, c1;
-                    c += row_span(q, ty, tx0, tx1, W, H, c0, c1);
-                }
+            if (any) h = (uint32_t)(ty1 - ty0 + 1);
         }
-        pg[i] = q;
+        if (live) pg[i] = q;
+        s_q[threadIdx.x] = q;
+        s_rows[threadIdx.x][0] = tx0;
+        s_rows[threadIdx.x][1] = tx1;
+        s_rows[threadIdx.x][2] = ty0;
+        s_cnt[threadIdx.x] = 0u;
+        // exclusive prefix of h over the wave
+        uint32_t incl = h;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        s_start[threadIdx.x] = incl - h;
+        const uint32_t total = __shfl(incl, 63, 64);
+        __builtin_amdgcn_wave_barrier();  // the wave's LDS entries are written
+        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+            const uint32_t p = p0 + (uint32_t)lane;
+            if (p < total) {
+                uint32_t lo = 0, hi = 64;  // last lane whose first pair is <= p
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_start[wb + mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                const int o = wb + (int)lo;
+                int c0, c1;
+                const uint32_t r = row_span(s_q[o], s_rows[o][2] + (int)(p - s_start[o]),
+                                            s_rows[o][0], s_rows[o][1], W, H, c0, c1);
+                if (r) atomicAdd(&s_cnt[o], r);
+            }
+        }
+        // LDS operations of a wave complete in order: the sums are final
+        __builtin_amdgcn_wave_barrier();
+        c = s_cnt[threadIdx.x];
+        if (!live) return;
     }
     keys[i] = c > 0 ? depth_key(d) : 0xFFFFFFFFu;
     ids[i] = (uint32_t)i;
@@ -493,132 +552,239 @@ __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restric
     cnt[j] = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
 }
 
-// Expands the splats of output window blockIdx.x (WIN = NT * EMIT_ITEMS
-// consecutive slots).  The window's Gaussians are j0 = owner of its first
-// slot up to j1 = owner of the next window's first slot (or of the last
-// slot); their offsets and rectangles (and, with PRECISE, the first PG_STAGE
-// ellipse records, none at present) are staged in LDS.  Each thread locates the owner of its
-// first of EMIT_ITEMS consecutive slots by binary search and walks the
-// Gaussian's tiles from there in row-major order (the whole rectangle, or
-// with PRECISE the run of each row that meets the ellipse); results are
-// staged in LDS and written out coalesced.
-template <bool PRECISE, int NT>
-__global__ __launch_bounds__(NT) void k_emit(int P, const uint32_t *__restrict__ order,
-                                             const uint32_t *__restrict__ offs,
-                                             const uint2 *__restrict__ rects_sorted,
-                                             const PGauss *__restrict__ pg,
-                                             const uint32_t *__restrict__ win_start,
-                                             uint32_t nwin, int gx, int W, int H,
-                                             const uint32_t *__restrict__ n_splats, uint32_t cap,
-                                             uint32_t *__restrict__ tkey, uint32_t *__restrict__ tid) {
-    constexpr int WIN = NT * EMIT_ITEMS;
-    constexpr int NPG = PRECISE && PG_STAGE > 0 ? PG_STAGE : 1;
-    constexpr uint32_t NSTAGED = PRECISE ? (uint32_t)PG_STAGE : 0u;
-    __shared__ uint32_t s_off[WIN + 1];
-    __shared__ uint2 s_rect[WIN + 1];
-    __shared__ uint32_t s_id[WIN + 1];
-    __shared__ uint32_t s_tk[WIN];
-    __shared__ uint32_t s_tg[WIN];
-    __shared__ PGauss s_pg[NPG];
-    uint32_t N = *n_splats;
-    if (N > cap) return;  // overflow: nothing is written
-    uint32_t o0 = blockIdx.x * (uint32_t)WIN;
-    if (o0 >= N || blockIdx.x + 1 >= nwin) return;
-    uint32_t oend = min(o0 + (uint32_t)WIN, N);
-    uint32_t j0 = win_start[blockIdx.x];
-    uint32_t j1 = win_start[blockIdx.x + 1];
-    if (j0 >= (uint32_t)P) return;  // cannot happen when the scan ran; keeps reads in bounds
-    // every Gaussian between j0 and j1 owns at least one slot of the window
+// Stages the Gaussians of output window `blk` (slots [blk * WIN, +WIN)):
+// j0 = owner of its first slot up to j1 = owner of the next window's first
+// slot (or of the last slot); every Gaussian in between owns at least one
+// slot of the window, so there are at most WIN + 1.  Returns m, or 0 when
+// the window is idle (overflow, past N).  All threads of the block call it.
+template <int WIN, int NT>
+__device__ __forceinline__ uint32_t stage_window(int P, const uint32_t *__restrict__ order,
+                                                 const uint32_t *__restrict__ offs,
+                                                 const uint2 *__restrict__ rects_sorted,
+                                                 const uint32_t *__restrict__ win_start,
+                                                 uint32_t nwin, uint32_t N, uint32_t cap,
+                                                 uint32_t *s_off, uint2 *s_rect, uint32_t *s_id) {
+    const uint32_t o0 = blockIdx.x * (uint32_t)WIN;
+    if (N > cap || o0 >= N || blockIdx.x + 1 >= nwin) return 0u;
+    const uint32_t j0 = win_start[blockIdx.x];
+    const uint32_t j1 = win_start[blockIdx.x + 1];
+    if (j0 >= (uint32_t)P) return 0u;  // cannot happen when the scan ran; keeps reads in bounds
     uint32_t m = (j1 >= j0 ? j1 - j0 : 0u) + 1u;
     m = min(m, (uint32_t)WIN + 1u);
-    m = min(m, (uint32_t)P - min(j0, (uint32_t)P - 1u));
+    m = min(m, (uint32_t)P - j0);
     for (uint32_t k = threadIdx.x; k < m; k += NT) {
         s_off[k] = offs[j0 + k];
         s_rect[k] = rects_sorted[j0 + k];
-        const uint32_t id = order[j0 + k];
-        s_id[k] = id;
-        if (k < NSTAGED) s_pg[k] = pg[id];
+        s_id[k] = order[j0 + k];
     }
+    return m;
+}
+
+// Largest i in [0, n) with a[i] <= x (a non-decreasing, a[0] <= x).
+__device__ __forceinline__ uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
+// slots) under the 3-sigma rule: each thread locates the owner of its first
+// of EMIT_ITEMS consecutive slots by binary search and walks the rectangles
+// in row-major order; results are staged in LDS and written out coalesced.
+__global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
+                                                       const uint32_t *__restrict__ offs,
+                                                       const uint2 *__restrict__ rects_sorted,
+                                                       const uint32_t *__restrict__ win_start,
+                                                       uint32_t nwin, int gx,
+                                                       const uint32_t *__restrict__ n_splats,
+                                                       uint32_t cap, uint32_t *__restrict__ tkey,
+                                                       uint32_t *__restrict__ tid) {
+    __shared__ uint32_t s_off[EMIT_TILE + 1];
+    __shared__ uint2 s_rect[EMIT_TILE + 1];
+    __shared__ uint32_t s_id[EMIT_TILE + 1];
+    __shared__ uint32_t s_tk[EMIT_TILE];
+    __shared__ uint32_t s_tg[EMIT_TILE];
+    const uint32_t N = *n_splats;
+    const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS>(P, order, offs, rects_sorted, win_start,
+                                                             nwin, N, cap, s_off, s_rect, s_id);
+    if (m == 0) return;  // block-uniform
     __syncthreads();
-    uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
+    const uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
+    const uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
+    const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
     if (s0 < oend) {
-        uint32_t lo = 0, hi = m;  // invariant: s_off[lo] <= s0
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (s_off[mid] <= s0) lo = mid;
-            else hi = mid;
-        }
-        uint32_t k = lo;
-        uint32_t l = s0 - s_off[k];
-        if (!PRECISE) {
-            uint2 r = s_rect[k];
-            uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
-            uint32_t row = l / w, col = l - row * w;
-            for (int i = 0; i < EMIT_ITEMS; ++i) {
-                uint32_t o = s0 + (uint32_t)i;
-                if (o >= oend) break;
-                uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
-                s_tk[o - o0] = ty * (uint32_t)gx + tx;
-                s_tg[o - o0] = s_id[k];
-                if (++col == w) {
-                    col = 0;
-                    if (++row == h && k + 1 < m) {
-                        row = 0;
-                        ++k;
-                        r = s_rect[k];
-                        w = max(r.y & 0xFFFFu, 1u);
-                        h = max(r.y >> 16, 1u);
-                    }
+        uint32_t k = last_le(s_off, m, s0);
+        const uint32_t l = s0 - s_off[k];
+        uint2 r = s_rect[k];
+        uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
+        uint32_t row = l / w, col = l - row * w;
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            const uint32_t o = s0 + (uint32_t)i;
+            if (o >= oend) break;
+            const uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
+            s_tk[o - o0] = ty * (uint32_t)gx + tx;
+            s_tg[o - o0] = s_id[k];
+            if (++col == w) {
+                col = 0;
+                if (++row == h && k + 1 < m) {
+                    row = 0;
+                    ++k;
+                    r = s_rect[k];
+                    w = max(r.y & 0xFFFFu, 1u);
+                    h = max(r.y >> 16, 1u);
                 }
             }
-        } else {
-            // placeholders (tile 0, Gaussian 0: in bounds) for slots the walk
-            // below would leave unwritten if the two passes ever disagreed
-            for (int i = 0; i < EMIT_ITEMS && s0 + (uint32_t)i < oend; ++i) {
-                s_tk[s0 + i - o0] = 0u;
-                s_tg[s0 + i - o0] = 0u;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < oend - o0; i += SORT_THREADS) {
+        tkey[o0 + i] = s_tk[i];
+        tid[o0 + i] = s_tg[i];
+    }
+}
+
+// Exclusive prefix sum of a[0, n) in place (n <= NT * 8); returns the total.
+// All threads of the block call it; `lds` holds NT / 64 entries.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t n, uint32_t *lds) {
+    const uint32_t per = (n + NT - 1) / NT;
+    const uint32_t b = threadIdx.x * per, e = min(b + per, n);
+    uint32_t sum = 0;
+    for (uint32_t i = b; i < e; ++i) sum += a[i];
+    uint32_t ex;
+    const uint32_t tot = block_excl_scan<uint32_t>(sum, ex, lds);
+    for (uint32_t i = b; i < e; ++i) {
+        const uint32_t v = a[i];
+        a[i] = ex;
+        ex += v;
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Precise rule: expands window blockIdx.x (EMIT_TILE_P slots).  The window's
+// Gaussians' tile rows are listed as (Gaussian, row) pairs; each pair's run
+// of tiles [c0, c0 + n) is computed once (one row_span per pair, spread over
+// the block), the runs' first slots come from a prefix sum over n, and every
+// thread then finds the run holding its first slot by binary search and
+// writes its EMIT_ITEMS_P tiles directly.  A window with more than RCAP
+// pairs (several very tall Gaussians) walks the rows per thread instead.
+__global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
+    int P, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offs,
+    const uint2 *__restrict__ rects_sorted, const PGauss *__restrict__ pg,
+    const uint32_t *__restrict__ win_start, uint32_t nwin, int gx, int W, int H,
+    const uint32_t *__restrict__ n_splats, uint32_t cap, uint32_t *__restrict__ tkey,
+    uint32_t *__restrict__ tid) {
+    constexpr int WIN = EMIT_TILE_P;
+    __shared__ uint32_t s_off[WIN + 1];
+    __shared__ uint2 s_rect[WIN + 1];
+    __shared__ uint32_t s_id[WIN + 1];
+    __shared__ uint32_t s_hoff[WIN + 1];   // first pair of each Gaussian
+    __shared__ uint32_t s_pslot[RCAP];     // first slot of each pair's run
+    __shared__ uint16_t s_pk[RCAP], s_pty[RCAP], s_pc0[RCAP], s_pn[RCAP];
+    __shared__ uint32_t s_tk[WIN];
+    __shared__ uint32_t s_tg[WIN];
+    __shared__ uint32_t s_scan[WAVES];
+    const uint32_t N = *n_splats;
+    const uint32_t m = stage_window<WIN, SORT_THREADS>(P, order, offs, rects_sorted, win_start,
+                                                       nwin, N, cap, s_off, s_rect, s_id);
+    if (m == 0) return;  // block-uniform
+    __syncthreads();
+    const uint32_t o0 = blockIdx.x * (uint32_t)WIN;
+    const uint32_t oend = min(o0 + (uint32_t)WIN, N);
+    const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS_P;
+    // placeholders (tile 0, Gaussian 0: in bounds) for slots a disagreement
+    // between the count and this pass would leave unwritten
+    for (int i = 0; i < EMIT_ITEMS_P && s0 + (uint32_t)i < oend; ++i) {
+        s_tk[s0 + i - o0] = 0u;
+        s_tg[s0 + i - o0] = 0u;
+    }
+    for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS) s_hoff[k] = s_rect[k].y >> 16;
+    __syncthreads();
+    const uint32_t R = block_scan_array<SORT_THREADS>(s_hoff, m, s_scan);
+    if (R <= (uint32_t)RCAP) {
+        for (uint32_t p = threadIdx.x; p < R; p += SORT_THREADS) {
+            const uint32_t k = last_le(s_hoff, m, p);
+            const RectDec d = dec_rect(s_rect[k]);
+            const int ty = d.ty0 + (int)(p - s_hoff[k]);
+            const PGauss q = pg[s_id[k]];
+            int c0 = 0, c1 = -1;
+            const uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+            s_pk[p] = (uint16_t)k;
+            s_pty[p] = (uint16_t)ty;
+            s_pc0[p] = (uint16_t)c0;
+            s_pn[p] = (uint16_t)n;
+            s_pslot[p] = n;
+        }
+        __syncthreads();
+        block_scan_array<SORT_THREADS>(s_pslot, R, s_scan);
+        // absolute first slots: Gaussian k's first run starts at s_off[k]
+        for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS)
+            s_hoff[k] = s_off[k] - s_pslot[s_hoff[k]];
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < R; p += SORT_THREADS) s_pslot[p] += s_hoff[s_pk[p]];
+        __syncthreads();
+        if (s0 < oend) {
+            // the last run starting at or before s0 is non-empty and holds it
+            uint32_t p = last_le(s_pslot, R, s0);
+            uint32_t within = s0 - s_pslot[p];
+            for (int i = 0; i < EMIT_ITEMS_P; ++i) {
+                const uint32_t o = s0 + (uint32_t)i;
+                if (o >= oend || within >= s_pn[p]) break;
+                s_tk[o - o0] = (uint32_t)s_pty[p] * (uint32_t)gx + s_pc0[p] + within;
+                s_tg[o - o0] = s_id[s_pk[p]];
+                if (++within < s_pn[p]) continue;
+                within = 0;
+                do {
+                    ++p;
+                } while (p < R && s_pn[p] == 0);
+                if (p >= R) break;
             }
-            // current Gaussian k: rectangle, ellipse, row ty and its run [c0, c1]
-            PGauss q = k < NSTAGED ? s_pg[k] : pg[s_id[k]];
-            RectDec d = dec_rect(s_rect[k]);
-            int ty = d.ty0, c0 = 0, c1 = -1;
-            uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
-            while (l >= n && ty < d.ty0 + d.h - 1) {  // row holding local slot l
-                l -= n;
+        }
+    } else if (s0 < oend) {
+        // per-thread walk along the rows
+        uint32_t k = last_le(s_off, m, s0);
+        uint32_t l = s0 - s_off[k];
+        PGauss q = pg[s_id[k]];
+        RectDec d = dec_rect(s_rect[k]);
+        int ty = d.ty0, c0 = 0, c1 = -1;
+        uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+        while (l >= n && ty < d.ty0 + d.h - 1) {  // row holding local slot l
+            l -= n;
+            ++ty;
+            n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+        }
+        for (int i = 0; i < EMIT_ITEMS_P; ++i) {
+            const uint32_t o = s0 + (uint32_t)i;
+            if (o >= oend || l >= n) break;  // (l >= n only if the counts disagree)
+            s_tk[o - o0] = (uint32_t)ty * (uint32_t)gx + (uint32_t)(c0 + (int)l);
+            s_tg[o - o0] = s_id[k];
+            if (++l < n) continue;
+            l = 0;
+            n = 0;
+            while (n == 0 && ty < d.ty0 + d.h - 1) {  // next row with tiles
                 ++ty;
                 n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
             }
-            for (int i = 0; i < EMIT_ITEMS; ++i) {
-                uint32_t o = s0 + (uint32_t)i;
-                if (o >= oend || l >= n) break;  // (l >= n only if the counts disagree)
-                s_tk[o - o0] = (uint32_t)ty * (uint32_t)gx + (uint32_t)(c0 + (int)l);
-                s_tg[o - o0] = s_id[k];
-                if (++l < n) continue;
-                l = 0;
-                n = 0;
-                while (n == 0 && ty < d.ty0 + d.h - 1) {  // next row with tiles
-                    ++ty;
-                    n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
-                }
-                if (n > 0) continue;
-                // next Gaussian: the owner of slot o + 1 is the last one whose
-                // offset is <= o + 1
-                ++k;
-                while (k + 1 < m && s_off[k + 1] <= o + 1) ++k;
-                if (k >= m) break;
-                q = k < NSTAGED ? s_pg[k] : pg[s_id[k]];
-                d = dec_rect(s_rect[k]);
-                ty = d.ty0;
+            if (n > 0) continue;
+            ++k;  // next Gaussian (each one in the window has a slot)
+            if (k >= m) break;
+            q = pg[s_id[k]];
+            d = dec_rect(s_rect[k]);
+            ty = d.ty0;
+            n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+            while (n == 0 && ty < d.ty0 + d.h - 1) {
+                ++ty;
                 n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
-                while (n == 0 && ty < d.ty0 + d.h - 1) {
-                    ++ty;
-                    n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
-                }
             }
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < oend - o0; i += NT) {
+    for (uint32_t i = threadIdx.x; i < oend - o0; i += SORT_THREADS) {
         tkey[o0 + i] = s_tk[i];
         tid[o0 + i] = s_tg[i];
     }
@@ -798,8 +964,11 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
                        (uint32_t)P, part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, sblocks, d_num_splats);
     const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
+    static_assert((EMIT_TILE & (EMIT_TILE - 1)) == 0 && (EMIT_TILE_P & (EMIT_TILE_P - 1)) == 0,
+                  "windows are powers of two");
     hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
-                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin, win, d_num_splats);
+                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin, ceil_log2(win),
+                       d_num_splats);
     int tbits = ceil_log2((uint32_t)ntiles);
     if (tbits == 0) tbits = 1;
     int npass = (tbits + RADIX_BITS - 1) / RADIX_BITS;
@@ -811,15 +980,14 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
     uint32_t eblocks = (capacity + win - 1) / win;
     if (eblocks > 0) {
         if (precise)
-            hipLaunchKernelGGL((k_emit<true, EMIT_THREADS_P>), dim3(eblocks), dim3(EMIT_THREADS_P), 0, s, P, order,
+            hipLaunchKernelGGL(k_emit_precise, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
                                U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
                                U(L.tkey0), emit_ids);
         else
-            hipLaunchKernelGGL((k_emit<false, SORT_THREADS>), dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
-                               U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
-                               U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
-                               U(L.tkey0), emit_ids);
+            hipLaunchKernelGGL(k_emit, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order, U(L.offs),
+                               (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, gx,
+                               d_num_splats, capacity, U(L.tkey0), emit_ids);
     }
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
