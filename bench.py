@@ -230,6 +230,27 @@ def multiview(args):
     eager = float(np.median(autotune.time_ms(mv.frame, reps=5, warmup=1)))
     assert not any(mv.overflowed())
     lat = np.array(lat)
+    # pipelined frame: the raster of view v (second stream) overlaps the
+    # bin/sort of the later views
+    gpl = mv.capture(pipelined=True)
+    for _ in range(3):
+        gpl.replay()
+    torch.cuda.synchronize()
+    latpl = []
+    for _ in range(5):
+        gpl.replay()
+        torch.cuda.synchronize()
+        latpl.extend(mv.latencies_ms())
+    e0.record()
+    for _ in range(K):
+        gpl.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    mspl = e0.elapsed_time(e1) / K
+    pipelined = {"graph_ms_per_frame": mspl, "views_per_s": mv.V * 1e3 / mspl,
+                 "latency_ms_p50": float(np.percentile(latpl, 50)),
+                 "latency_ms_p99": float(np.percentile(latpl, 99))}
+    del gpl
     # the same frame with precise Gaussian-tile intersection in every view's binning
     mvp = gs.MultiViewRenderer(scene, cams, precision=args.precision, precise=True)
     mvp.tune = mv.tune
@@ -271,7 +292,8 @@ def multiview(args):
                           "raster_batched": st[2]},
             "raster_one_launch_per_view_ms": per_view_raster,
             "preprocess_one_call_per_view_ms": single_pre,
-            "precise_binning": precise}
+            "precise_binning": precise,
+            "pipelined_two_streams": pipelined}
 
 
 def main():

@@ -496,21 +496,52 @@ class MultiViewRenderer:
               tuple(self.views[v].background))
 
     def frame(self, tune: gs_batch_tune | None = None):
+        """preprocess -> bin/sort of every view -> ONE batched raster launch."""
         _check("gs_clock_stamp", lib().gs_clock_stamp(_ptr(self.clock), _stream()))
         self.preprocess()
         self.bin_sort()
         self.raster(tune)
 
-    def capture(self, tune: gs_batch_tune | None = None) -> "torch.cuda.CUDAGraph":
-        """A hipGraph of one whole frame (replay with ``g.replay()``)."""
+    def frame_pipelined(self):
+        """The same images with the rasterisation of view v (one launch per
+        view, on a second stream) overlapping the bin/sort of the views after
+        it: bin/sort is bound by memory traffic, the rasteriser by the vector
+        ALUs.  The second stream joins the current one at the end; each
+        view's clock stamp follows its raster on the second stream."""
+        cur = torch.cuda.current_stream()
+        if getattr(self, "_side", None) is None:
+            self._side = torch.cuda.Stream(device=self.device)
+            self._events = [torch.cuda.Event() for _ in range(self.V)]
+        L = lib()
+        _check("gs_clock_stamp", L.gs_clock_stamp(_ptr(self.clock), _stream()))
+        self.preprocess()
+        side = self._side
+        side.wait_stream(cur)
+        for v, (bs, r) in enumerate(zip(self.sorters, self.images)):
+            bs(*self._bin_inputs(v))
+            self._events[v].record(cur)
+            with torch.cuda.stream(side):
+                side.wait_event(self._events[v])
+                r(bs.ranges, bs.sorted_ids, self.pre["means2d"][v], self.pre["conics"][v],
+                  self.scene["opacities"], self.pre["rgb"][v], self.precision,
+                  tuple(self.views[v].background))
+                _check("gs_clock_stamp",
+                       L.gs_clock_stamp(c_void_p(self.clock.data_ptr() + 8 * (v + 1)), _stream()))
+        cur.wait_stream(side)
+
+    def capture(self, tune: gs_batch_tune | None = None, pipelined: bool = False) -> "torch.cuda.CUDAGraph":
+        """A hipGraph of one whole frame (replay with ``g.replay()``):
+        :meth:`frame`, or :meth:`frame_pipelined` (two streams, forked and
+        joined inside the graph)."""
+        run = self.frame_pipelined if pipelined else (lambda: self.frame(tune))
         s = torch.cuda.Stream(device=self.device)
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.frame(tune)  # warm-up outside the capture
+            run()  # warm-up outside the capture
         torch.cuda.current_stream().wait_stream(s)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.frame(tune)
+            run()
         return g
 
     # -- results ----------------------------------------------------------

@@ -139,6 +139,34 @@ def test_graph_replay_matches_eager():
         assert all(x > 0 for x in mv.latencies_ms())
 
 
+def test_pipelined_frame_and_graph():
+    """Two-stream pipelined frame (per-view raster overlapping the next
+    views' bin/sort): same images as the one-launch frame, eagerly and in a
+    replayed graph."""
+    sc, cams = small_case(n_views=5, P=20000, seed=1017)
+    mv = gs.MultiViewRenderer(scene_tensors(sc), [gs_cam(c) for c in cams])
+    mv.frame()
+    torch.cuda.synchronize()
+    ref = snapshot(mv)
+    for r in mv.images:
+        r.rgb.fill_(-1.0)
+    mv.frame_pipelined()
+    torch.cuda.synchronize()
+    assert_same(ref, snapshot(mv), "pipelined eager")
+    lat = mv.latencies_ms()
+    assert all(x > 0 for x in lat), lat
+    g = mv.capture(pipelined=True)
+    for rep in range(3):
+        for r in mv.images:
+            r.rgb.fill_(-1.0)
+            r.T.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"pipelined graph replay {rep}: latencies {[round(x, 3) for x in mv.latencies_ms()]}")
+        assert_same(ref, snapshot(mv), f"pipelined replay {rep}")
+
+
 def test_batched_rejects_bad_args():
     L = gs.lib()
     t = gs.make_tune(96, 5, 1)  # batch must be 64, 128 or 256
