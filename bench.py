@@ -157,6 +157,72 @@ def train_step(args):
             "raster_bwd_ms": bwd, "splats": probe.n_splats(), "precision": prec}
 
 
+def large_scene(args, poses=range(10), steps=3, warmup=1):
+    """6M Gaussians at 3840x2160, the 10 orbit poses: per pose and precision
+    (FP32 path, FP16 and BF16 hi/lo split) the frame time, the raster time,
+    the raster's roofline fraction (same algorithmic work as the headline)
+    and the PSNR against the FP32 path's image."""
+    import torch
+
+    import paper_2505_24796_amd as gs
+    import scenegen
+    cfg = scenegen.CONFIGS["fwd_4k_6M"]
+    W, H = cfg["width"], cfg["height"]
+    log(f"[bench] large scene: generating P={cfg['P']}")
+    sc = scenegen.make_scene(cfg)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    means, scales, quats, sh, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), dev(sc.opacities)
+    P = sc.P
+    del sc
+    rows = []
+    rz = gs.Rasterizer(W, H)
+    for pose in poses:
+        c = scenegen.make_camera(cfg, pose)
+        cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
+        pre = gs.preprocess(means, scales, quats, sh, cam)
+        probe = gs.BinSorter(P, 0, W, H)
+        probe(pre["means2d"], pre["radii"], pre["depths"])
+        N = probe.n_splats()
+        bs = gs.BinSorter(P, int(N * 1.1) + 1024, W, H)
+        bs(pre["means2d"], pre["radii"], pre["depths"])
+        rz(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac, pre["rgb"], "fp32", count=True)
+        torch.cuda.synchronize()
+        cnt = rz.counters.cpu().numpy()
+        pairs, surv = int(cnt[3]), int(cnt[0] + cnt[2])
+        ref = rz.rgb.clone()
+        row = {"pose": pose, "splats": N, "pairs": pairs}
+        for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split"):
+            def frame(ev):
+                ev[0].record()
+                p = gs.preprocess(means, scales, quats, sh, cam)
+                bs(p["means2d"], p["radii"], p["depths"])
+                ev[1].record()
+                rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], prec)
+                ev[2].record()
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(warmup + steps)]
+            for e in evs:
+                frame(e)
+            torch.cuda.synchronize()
+            fr = float(np.median([e[0].elapsed_time(e[2]) for e in evs[warmup:]]))
+            ra = float(np.median([e[1].elapsed_time(e[2]) for e in evs[warmup:]]))
+            m = float(torch.mean((rz.rgb - ref) ** 2))
+            row[prec] = {"ms_per_frame": fr, "raster_ms": ra,
+                         "roofline_frac": (FLOP_PER_PAIR * pairs + FLOP_PER_SURVIVOR * surv)
+                         / (ra / 1e3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                         "psnr_vs_fp32_db": 10 * np.log10(1.0 / m) if m > 0 else float("inf")}
+        row["speedup_frame_fp16_vs_fp32"] = row["fp32"]["ms_per_frame"] / row["fp16_g2l_split"]["ms_per_frame"]
+        rows.append(row)
+        log(f"[bench] 4K pose {pose}: N={N} fp32 {row['fp32']['ms_per_frame']:.2f} ms, "
+            f"fp16 {row['fp16_g2l_split']['ms_per_frame']:.2f} ms, bf16 {row['bf16_g2l_split']['ms_per_frame']:.2f} ms")
+        del bs, probe, pre
+    summ = {prec: {"ms_per_frame_mean": float(np.mean([r[prec]["ms_per_frame"] for r in rows])),
+                   "roofline_frac_mean": float(np.mean([r[prec]["roofline_frac"] for r in rows])),
+                   "psnr_vs_fp32_min_db": float(np.min([r[prec]["psnr_vs_fp32_db"] for r in rows]))}
+            for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split")}
+    return {"workload": "fwd_4k_6M", "gaussians": P, "width": W, "height": H, "poses": rows,
+            "summary": summ}
+
+
 def multiview(args):
     """Serving many cameras of one scene (2M Gaussians, 16 orbit cameras at
     640x480 / 1280x720 / 1920x1080 / 2560x1440): one multi-view preprocess,
@@ -296,6 +362,40 @@ def multiview(args):
             "pipelined_two_streams": pipelined}
 
 
+def binsort_only(args):
+    """Bin/sort of the 1080p/1M frame alone, 3-sigma rule and precise
+    intersection alternating, `steps` times each (for kernel traces)."""
+    import torch
+
+    import paper_2505_24796_amd as gs
+    import scenegen
+    cfg = scenegen.CONFIGS["fwd_1080p_1M"]
+    W, H = cfg["width"], cfg["height"]
+    sc = scenegen.make_scene(cfg)
+    c = scenegen.make_camera(cfg)
+    cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    opac = dev(sc.opacities)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    bp = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, conics=pre["conics"],
+                     opacities=opac, precise=True)
+    b3 = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tp, t3 = [], []
+    for _ in range(args.steps):
+        ev[0].record()
+        bp(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], opac)
+        ev[1].record()
+        b3(pre["means2d"], pre["radii"], pre["depths"])
+        ev[2].record()
+        torch.cuda.synchronize()
+        tp.append(ev[0].elapsed_time(ev[1]))
+        t3.append(ev[1].elapsed_time(ev[2]))
+    print(json.dumps({"workload": "fwd_1080p_1M", "bin_sort_precise_ms": float(np.median(tp)),
+                      "bin_sort_3sigma_ms": float(np.median(t3)), "splats_precise": bp.n_splats(),
+                      "splats_3sigma": b3.n_splats()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +408,9 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--no-precise", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--binsort-only", action="store_true",
+                    help="only time the 1080p/1M bin/sort (3-sigma and precise), for traces")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -323,6 +426,9 @@ def main():
     import scenegen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.binsort_only:
+        binsort_only(args)
+        return
     cfg = scenegen.CONFIGS[args.workload]
     assert cfg["kind"] == "3d"
     W, H = cfg["width"], cfg["height"]
@@ -507,6 +613,8 @@ def main():
     }
     if not args.no_train:
         out["train_step"] = train_step(args)
+    if not args.no_large:
+        out["large_4k_6M"] = large_scene(args)
     if not args.no_multiview:
         out["multiview"] = multiview(args)
         log(f"[bench] multiview {out['multiview']['graph_ms_per_frame']:.2f} ms/frame")
