@@ -211,14 +211,38 @@ def large_scene(args, poses=range(10), steps=3, warmup=1):
                          / (ra / 1e3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
                          "psnr_vs_fp32_db": 10 * np.log10(1.0 / m) if m > 0 else float("inf")}
         row["speedup_frame_fp16_vs_fp32"] = row["fp32"]["ms_per_frame"] / row["fp16_g2l_split"]["ms_per_frame"]
+        # the FP16 frame with precise Gaussian-tile intersection
+        probe_p = gs.BinSorter(P, 0, W, H, precise=True)
+        probe_p(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], opac)
+        Np = probe_p.n_splats()
+        bsp = gs.BinSorter(P, int(Np * 1.1) + 1024, W, H, precise=True)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(warmup + steps)]
+        for e in evs:
+            e[0].record()
+            p = gs.preprocess(means, scales, quats, sh, cam)
+            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], opac)
+            e[1].record()
+            rz(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], "fp16_g2l_split")
+            e[2].record()
+        torch.cuda.synchronize()
+        row["fp16_g2l_split_precise"] = {
+            "splats": Np, "ms_per_frame": float(np.median([e[0].elapsed_time(e[2]) for e in evs[warmup:]])),
+            "raster_ms": float(np.median([e[1].elapsed_time(e[2]) for e in evs[warmup:]]))}
+        row["speedup_frame_fp16_precise_vs_fp32"] = (row["fp32"]["ms_per_frame"]
+                                                     / row["fp16_g2l_split_precise"]["ms_per_frame"])
+        del bsp, probe_p
         rows.append(row)
         log(f"[bench] 4K pose {pose}: N={N} fp32 {row['fp32']['ms_per_frame']:.2f} ms, "
-            f"fp16 {row['fp16_g2l_split']['ms_per_frame']:.2f} ms, bf16 {row['bf16_g2l_split']['ms_per_frame']:.2f} ms")
+            f"fp16 {row['fp16_g2l_split']['ms_per_frame']:.2f} ms, bf16 {row['bf16_g2l_split']['ms_per_frame']:.2f} ms, "
+            f"fp16+precise {row['fp16_g2l_split_precise']['ms_per_frame']:.2f} ms (N={Np})")
         del bs, probe, pre
+    summ_precise = {"ms_per_frame_mean": float(np.mean([r["fp16_g2l_split_precise"]["ms_per_frame"]
+                                                        for r in rows]))}
     summ = {prec: {"ms_per_frame_mean": float(np.mean([r[prec]["ms_per_frame"] for r in rows])),
                    "roofline_frac_mean": float(np.mean([r[prec]["roofline_frac"] for r in rows])),
                    "psnr_vs_fp32_min_db": float(np.min([r[prec]["psnr_vs_fp32_db"] for r in rows]))}
             for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split")}
+    summ["fp16_g2l_split_precise"] = summ_precise
     return {"workload": "fwd_4k_6M", "gaussians": P, "width": W, "height": H, "poses": rows,
             "summary": summ}
 

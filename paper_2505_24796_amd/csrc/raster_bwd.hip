@@ -113,7 +113,9 @@ __device__ __forceinline__ void fragment_grad(PixState &ps, bool bl, float alpha
                                               float s22, float o, float fx, float fy,
                                               float *s_grad) {
     float g[NGRAD];
-    float Tk = ps.T / (1.0f - alpha);
+    // T before this fragment (1 - alpha >= 0.01: a reciprocal-based divide
+    // of ~1 ulp is ample for the gradient)
+    float Tk = __fdividef(ps.T, 1.0f - alpha);
     float da = ps.d0 * (col.x - ps.B0) + ps.d1 * (col.y - ps.B1) + ps.d2 * (col.z - ps.B2);
     da *= Tk;
     // lanes that do not blend this fragment contribute zero
