@@ -93,6 +93,46 @@ def test_invalid_arguments_rejected_on_host(gslib):
                                    v(0)) == 1
 
 
+def test_batched_and_precise_arguments_rejected_on_host(gslib):
+    """The multi-view, batched and precise-binning entry points validate
+    their arguments before any GPU call."""
+    import paper_2505_24796_amd as gs
+    v = ctypes.c_void_p
+    cam = gs.make_camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1], 100, 100, 50, 50, 100, 100)
+    cams = (gs.gs_camera * 2)(cam, cam)
+    # multi-camera preprocess: no cameras, too many, a bad camera
+    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), 3, 0, cams, v(16), v(16),
+                                         v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), 3, 65, cams, v(16), v(16),
+                                         v(16), v(16), v(16), v(16), v(0)) == 1
+    bad = (gs.gs_camera * 2)(cam, gs.make_camera([1] * 16, 100, 100, 50, 50, 0, 100))
+    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), 3, 2, bad, v(16), v(16),
+                                         v(16), v(16), v(16), v(16), v(0)) == 1
+    # batched raster: plan and workspace sizes, view count, alignment, precision, shape
+    assert gslib.gs_batch_plan_bytes(0) == 0 and gslib.gs_batch_plan_bytes(65) == 0
+    assert gslib.gs_batch_plan_bytes(16) > 0 and gslib.gs_batch_workspace_bytes(16) >= 4 * (16 + 16)
+    views = (gs.gs_view * 1)()
+    views[0].width, views[0].height = 64, 64  # null buffers
+    assert gslib.gs_batch_plan_write(1, views, v(256), 1 << 20) == 1
+    assert gslib.gs_batch_plan_write(1, views, v(260), 1 << 20) == 1  # misaligned plan
+    t = gs.make_tune(256, 5, 1)
+    assert gslib.gs_rasterize_fwd_batched(0, v(256), 4, t, v(256), 1024, v(0), v(0)) == 1
+    assert gslib.gs_rasterize_fwd_batched(1, v(256), 4, t, v(256), 4, v(0), v(0)) == 4
+    assert gslib.gs_rasterize_fwd_batched(1, v(256), 1, t, v(256), 1024, v(0), v(0)) == 2
+    assert gslib.gs_rasterize_fwd_batched(1, v(256), 4, gs.make_tune(96, 5, 1), v(256), 1024,
+                                          v(0), v(0)) == 1
+    assert gslib.gs_rasterize_fwd_batched(1, v(256), 4, gs.make_tune(64, 0, 1), v(256), 1024,
+                                          v(0), v(0)) == 1
+    assert gslib.gs_clock_stamp(v(0), v(0)) == 1
+    # precise binning: conics / opacities required, capacity check
+    assert gslib.gs_bin_sort_precise_workspace_bytes(10, 100, 64, 64) > \
+        gslib.gs_bin_sort_workspace_bytes(10, 100, 64, 64)
+    assert gslib.gs_bin_sort_precise(10, v(16), v(16), v(16), v(0), v(16), 64, 64, 100, v(256),
+                                     1 << 20, v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_bin_sort_precise(10, v(16), v(16), v(16), v(16), v(16), 64, 64, 100, v(256),
+                                     8, v(16), v(16), v(16), v(0)) == 4
+
+
 def test_zero_gaussians_is_noop(gslib):
     v = ctypes.c_void_p
     assert gslib.gs_preprocess_2d(0, v(0), v(0), 64, 64, v(0), v(0), v(0), v(0)) == 0

@@ -80,6 +80,30 @@ def test_preprocess_multiview_matches_single_and_oracle():
         np.testing.assert_allclose(host(mv["rgb"][v])[vis], o["rgb"][vis], atol=3e-5)
 
 
+def test_many_views():
+    """40 small views: the multi-camera preprocess runs in chunks of 16
+    cameras, the plan holds 40 views; everything bit-identical to one call /
+    one launch per view."""
+    res = ((64, 48), (96, 80), (48, 64), (130, 70), (16, 16))
+    sc = scenegen.scene_3d(8000, 1018)
+    cams = [scenegen.orbit_camera(k, 40, *res[k % len(res)]) for k in range(40)]
+    t = scene_tensors(sc)
+    mvp = gs.preprocess_multiview(t["means3d"], t["scales"], t["quats"], t["sh"],
+                                  [gs_cam(c) for c in cams])
+    for v in (0, 15, 16, 17, 39):
+        one = gs.preprocess(t["means3d"], t["scales"], t["quats"], t["sh"], gs_cam(cams[v]))
+        for k in ("radii", "means2d", "conics", "rgb", "depths"):
+            assert np.array_equal(host(mvp[k][v]), host(one[k])), (v, k)
+    mv = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams])
+    for tune in (gs.make_tune(64, 2, 1), gs.make_tune(128, 1, 0)):
+        mv.frame(tune)
+        torch.cuda.synchronize()
+        batched = snapshot(mv)
+        mv.raster_per_view()
+        assert_same(batched, snapshot(mv), f"40 views, shape {tune.as_tuple()}")
+    assert all(x > 0 for x in mv.latencies_ms())
+
+
 @pytest.mark.parametrize("prec", ["fp16_g2l_split", "bf16_g2l_split"])
 def test_batched_small_vs_single_and_oracle(prec):
     sc, cams = small_case()
