@@ -62,7 +62,7 @@ def read_traffic(precision: str):
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash(RASTER_SOURCES):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def cpu_baseline(scene, cam, pre_gpu, total_pairs: int, budget_s: float = 20.0):
@@ -519,13 +519,13 @@ def main():
         wall = (time.perf_counter() - t0) * 1e3 / args.steps
         st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
                         e[0].elapsed_time(e[3])] for e in evs])
-        return wall, np.median(st, axis=0), st.mean(axis=0)
+        return wall, np.median(st, axis=0), st.mean(axis=0), st
 
     log(f"[bench] timing {args.precision} ({args.warmup} warmup + {args.steps} steps)")
-    wall, med, mean = timed(args.precision)
+    wall, med, mean, st_all = timed(args.precision)
     img = rz.rgb.clone()
     log(f"[bench] timing fp32 baseline")
-    wall32, med32, mean32 = timed("fp32")
+    wall32, med32, mean32, _ = timed("fp32")
     torch.cuda.synchronize()
 
     # precision sweep (the paper's EarlyCull / precision ablations): raster
@@ -599,7 +599,35 @@ def main():
 
     raster_s = mean[2] / 1e3
     achieved = (FLOP_PER_PAIR * pairs + FLOP_PER_SURVIVOR * survivors) / raster_s / 1e12
-    traffic = read_traffic(args.precision)
+    counters = read_traffic(args.precision)
+    traffic = counters.get("bytes_per_launch") if counters else None
+    # other rooflines: matrix cores as executed (counters), the exp unit,
+    # and HBM for the bandwidth-bound stages (algorithmic bytes)
+    other = {}
+    if counters:
+        sq = counters["sq_counters_per_dispatch"]
+        t_cnt = sq["GRBM_GUI_ACTIVE"] / 8 / 2.4e9  # kernel time under counters (8 XCDs)
+        # v_mfma_f32_32x32x16_f16: 2 * 32 * 32 * 16 flop per wave instruction
+        mfma_exec = sq["SQ_INSTS_MFMA"] * 32768 / t_cnt / 1e12
+        exp_rate = sq["SQ_INSTS_VALU_TRANS_F32"] * 64 / t_cnt
+        other["raster_mfma_executed"] = {"achieved": mfma_exec, "peak": FP16_MFMA_PEAK_TFLOPS,
+                                         "unit": "TFLOP/s", "frac": mfma_exec / FP16_MFMA_PEAK_TFLOPS,
+                                         "source": "SQ_INSTS_MFMA x 32768 flop (counters)"}
+        # transcendental ops issue at a quarter of the 64-lane FP32 rate:
+        # 256 CUs x 4 SIMDs x 16 lanes / 4 x 2.4 GHz
+        exp_peak = 256 * 4 * 16 / 4 * 2.4e9
+        other["raster_exp"] = {"achieved": exp_rate, "peak": exp_peak, "unit": "exp/s",
+                               "frac": exp_rate / exp_peak,
+                               "source": "SQ_INSTS_VALU_TRANS_F32 x 64 lanes (counters)"}
+        other["raster_valu_issue_frac"] = counters.get("valu_issue_utilisation")
+    # preprocess: 236 B read + 44 B written per Gaussian; bin/sort: per
+    # Gaussian 4 x 16 B (depth passes) + 40 B, per splat 52 B
+    pre_bytes = 280.0 * P
+    bin_bytes = P * (4 * 16 + 40) + 52.0 * N
+    other["preprocess_hbm"] = {"achieved": pre_bytes / (mean[0] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": pre_bytes / (mean[0] / 1e3) / 1e9 / HBM_PEAK_GBS}
+    other["bin_sort_hbm"] = {"achieved": bin_bytes / (mean[1] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": bin_bytes / (mean[1] / 1e3) / 1e9 / HBM_PEAK_GBS}
     out = {
         "metric": METRIC,
         "value": pairs / (wall / 1e3),
@@ -623,6 +651,13 @@ def main():
                      "work": f"{FLOP_PER_PAIR} flop/pair + {FLOP_PER_SURVIVOR} flop/survivor "
                              "(Algorithm 1 in FP32)"},
         "mfma_util_algorithmic": 12.0 * pairs / raster_s / 1e12 / FP16_MFMA_PEAK_TFLOPS,
+        "rooflines_other": other,
+        "fragments": {"blended": int(cnt[0]), "culled": int(cnt[1]), "terminating": int(cnt[2]),
+                      "skipped": int(256 * N - pairs),
+                      "culled_frac_of_pairs": float(cnt[1]) / max(pairs, 1)},
+        "frame_ms_percentiles": {"p10": float(np.percentile(st_all[:, 3], 10)),
+                                 "p50": float(np.percentile(st_all[:, 3], 50)),
+                                 "p90": float(np.percentile(st_all[:, 3], 90))},
         "stages_ms": {"preprocess": mean[0], "bin_sort": mean[1], "raster": mean[2]},
         "fp32_path": {"ms_per_frame": wall32, "raster_ms": mean32[2],
                       "pairs_per_s": pairs / (wall32 / 1e3),

@@ -11,7 +11,9 @@
 //      ceil(log2 ntiles) bits), which keeps depth order within a tile, and
 //   4. finds each tile's [start, end).
 // Every splat moves 2 x (4 + 4) bytes per tile pass instead of 6 passes of
-// 24 bytes; all stages are HBM-bandwidth kernels.
+// 24 bytes.  A Gaussian covers the tiles of its 3-sigma pixel rectangle, or,
+// with the precise rule (gs_bin_sort_precise), only those of them where its
+// raw opacity can reach the culling threshold.
 #include "common.h"
 
 namespace {
