@@ -158,17 +158,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (8-bit digit) of u32 keys with u32 values:
-// per-block digit histograms -> per-digit scan over blocks -> scatter.
+// Stable LSD radix sort pass (BITS-bit digit, BITS <= 8) of u32 keys with u32
+// values: per-block digit histograms -> per-digit scan over blocks -> scatter.
 // ---------------------------------------------------------------------------
-template <int ITEMS>
+template <int ITEMS, int BITS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              Count cnt, int shift,
                                                              uint32_t *__restrict__ hist,
                                                              uint32_t nblocks) {
-    __shared__ uint32_t h[RADIX];
+    constexpr int NDIG = 1 << BITS;
+    __shared__ uint32_t h[NDIG];
     uint32_t n = cnt.get();
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < NDIG) h[threadIdx.x] = 0;
     __syncthreads();
     constexpr int TILE = SORT_THREADS * ITEMS;
     size_t base = (size_t)blockIdx.x * TILE;
@@ -176,11 +177,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (NDIG - 1)], 1u);
         }
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // One block per digit: exclusive scan of that digit's counts over blocks, in
@@ -202,14 +203,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-template <int ITEMS>
+template <int ITEMS, int BITS>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
     const uint32_t *__restrict__ totals, uint32_t nblocks) {
-    __shared__ uint32_t wcnt[WAVES][RADIX];
-    __shared__ uint32_t gbase[RADIX];   // global position of this block's first key of digit d
-    __shared__ uint32_t lstart[RADIX];  // local position of this block's first key of digit d
+    constexpr int NDIG = 1 << BITS;
+    __shared__ uint32_t wcnt[WAVES][NDIG];
+    __shared__ uint32_t gbase[NDIG];   // global position of this block's first key of digit d
+    __shared__ uint32_t lstart[NDIG];  // local position of this block's first key of digit d
     constexpr int TILE = SORT_THREADS * ITEMS;
     constexpr int W_ITEMS = TILE / WAVES, W_CHUNKS = W_ITEMS / 64;
     __shared__ uint32_t skey[TILE];
@@ -219,13 +221,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     size_t base = (size_t)blockIdx.x * TILE;
     if (base >= n) return;  // whole block idle: uniform exit
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < NDIG) {
 #pragma unroll
-    for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
+        for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
+    }
     {
         // exclusive scan of the global digit totals -> digit base
-        uint32_t t = totals[threadIdx.x], ex;
+        uint32_t t = threadIdx.x < NDIG ? totals[threadIdx.x] : 0u, ex;
         block_excl_scan<uint32_t>(t, ex, lds_scan);
-        gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
+        if (threadIdx.x < NDIG)
+            gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
     }
     __syncthreads();
 
@@ -251,10 +256,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n;
-        uint32_t d = (key[c] >> shift) & (RADIX - 1);
+        uint32_t d = (key[c] >> shift) & (NDIG - 1);
         uint64_t peers = __ballot(ok);
 #pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             bool bit = (d >> b) & 1u;
             uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -274,15 +279,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     {
         // per digit: prefix over waves, and the block's digit-major local start
         uint32_t d = threadIdx.x, off = 0;
+        if (d < NDIG) {
 #pragma unroll
-        for (int i = 0; i < WAVES; ++i) {
-            uint32_t t = wcnt[i][d];
-            wcnt[i][d] = off;
-            off += t;
+            for (int i = 0; i < WAVES; ++i) {
+                uint32_t t = wcnt[i][d];
+                wcnt[i][d] = off;
+                off += t;
+            }
         }
         uint32_t ex;
         block_excl_scan<uint32_t>(off, ex, lds_scan);
-        lstart[d] = ex;
+        if (d < NDIG) lstart[d] = ex;
     }
     __syncthreads();
     // stage in LDS in (digit, original order) order ...
@@ -290,7 +297,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n) {
-            uint32_t d = (key[c] >> shift) & (RADIX - 1);
+            uint32_t d = (key[c] >> shift) & (NDIG - 1);
             uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
             skey[lp] = key[c];
             sval[lp] = val[c];
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     uint32_t nloc = (uint32_t)min((size_t)TILE, (size_t)n - base);
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
-        uint32_t d = (k >> shift) & (RADIX - 1);
+        uint32_t d = (k >> shift) & (NDIG - 1);
         uint32_t dst = gbase[d] + (lp - lstart[d]);
         kout[dst] = k;
         vout[dst] = sval[lp];
@@ -312,7 +319,28 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
-// Sorts on bits [0, bits) with ceil(bits/8) passes of ITEMS keys per
+template <int ITEMS, int BITS>
+void radix_pass(SortBufs b, int cur, Count cnt, int shift, uint32_t nblocks, uint32_t *hist,
+                uint32_t *totals, hipStream_t s) {
+    hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS>), dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
+                       cnt, shift, hist, nblocks);
+    hipLaunchKernelGGL(k_hist_rows, dim3(1 << BITS), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS>), dim3(nblocks), dim3(SORT_THREADS), 0, s,
+                       b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals,
+                       nblocks);
+}
+
+// Digit widths of a sort on `bits` key bits: ceil(bits / 8) passes of
+// near-equal width (13 bits -> 7 + 6), each at least 4 bits (the keys are
+// zero above `bits`, so a wider digit sorts the same).
+inline int radix_passes(int bits) { return (bits + RADIX_BITS - 1) / RADIX_BITS; }
+inline int radix_width(int bits, int pass) {
+    int np = radix_passes(bits);
+    int w = bits / np + (pass < bits % np ? 1 : 0);
+    return w < 4 ? 4 : w;
+}
+
+// Sorts on bits [0, bits) with radix_passes(bits) passes of ITEMS keys per
 // thread; returns the index of the buffer pair holding the result.
 template <int ITEMS>
 int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
@@ -320,13 +348,17 @@ int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, 
     constexpr int TILE = SORT_THREADS * ITEMS;
     uint32_t nblocks = (max_n + TILE - 1) / TILE;
     if (nblocks == 0) nblocks = 1;
-    int cur = 0;
-    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
-                           cnt, shift, hist, nblocks);
-        hipLaunchKernelGGL(k_hist_rows, dim3(RADIX), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
-        hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
-                           b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals, nblocks);
+    int cur = 0, shift = 0;
+    for (int p = 0; p < radix_passes(bits); ++p) {
+        const int w = radix_width(bits, p);
+        switch (w) {
+        case 4: radix_pass<ITEMS, 4>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
+        case 5: radix_pass<ITEMS, 5>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
+        case 6: radix_pass<ITEMS, 6>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
+        case 7: radix_pass<ITEMS, 7>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
+        default: radix_pass<ITEMS, 8>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
+        }
+        shift += w;
         cur ^= 1;
     }
     return cur;
@@ -973,7 +1005,7 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
                        d_num_splats);
     int tbits = ceil_log2((uint32_t)ntiles);
     if (tbits == 0) tbits = 1;
-    int npass = (tbits + RADIX_BITS - 1) / RADIX_BITS;
+    int npass = radix_passes(tbits);
     // ids are emitted into the buffer that the last tile pass does NOT write,
     // so the sorted ids land in sorted_ids.
     uint32_t *emit_ids = (npass % 2 == 0) ? sorted_ids : U(L.tid);
