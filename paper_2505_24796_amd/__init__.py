@@ -408,7 +408,8 @@ def wall_clock_khz() -> int:
 
 class MultiViewRenderer:
     """Renders one scene to several cameras per frame: one multi-view
-    preprocess, one bin/sort per view (sharing a workspace), and ONE
+    preprocess, one bin/sort per view (``bin_streams`` views at a time, on
+    as many streams, each with its own workspace), and ONE
     persistent batched rasteriser launch over every (view, tile) pair.
     Buffers are sized once (splat capacity per view from a probe frame times
     ``slack``); a frame allocates nothing, so it can be captured in a
@@ -416,7 +417,7 @@ class MultiViewRenderer:
     device wall-clock stamps (frame start, last tile of each view)."""
 
     def __init__(self, scene: dict, cams, precision="fp16_g2l_split", slack=1.15,
-                 background=(0.0, 0.0, 0.0), sh_degree=3, precise=False):
+                 background=(0.0, 0.0, 0.0), sh_degree=3, precise=False, bin_streams=4):
         self.scene = {k: _dev(scene[k], torch.float32, k)
                       for k in ("means3d", "scales", "quats", "sh", "opacities")}
         self.cams = list(cams)
@@ -439,10 +440,15 @@ class MultiViewRenderer:
         wsb = (lib().gs_bin_sort_precise_workspace_bytes if self.precise
                else lib().gs_bin_sort_workspace_bytes)
         ws = max(wsb(self.P, cap, c.width, c.height) for cap, c in zip(self.capacity, self.cams))
-        self.bin_workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+        # views are sorted K at a time on K streams (view v on stream v % K),
+        # each stream with its own workspace: a view's bin/sort is a chain of
+        # small, latency-bound kernels that leaves most of the GPU idle
+        self.K = max(1, min(int(bin_streams), self.V))
+        self.bin_workspaces = [torch.empty(ws, dtype=torch.uint8, device=dev) for _ in range(self.K)]
         self.sorters = [BinSorter(self.P, cap, c.width, c.height, device=dev,
-                                  workspace=self.bin_workspace, precise=self.precise)
-                        for cap, c in zip(self.capacity, self.cams)]
+                                  workspace=self.bin_workspaces[v % self.K], precise=self.precise)
+                        for v, (cap, c) in enumerate(zip(self.capacity, self.cams))]
+        self._bin_streams = None
         self.images = [Rasterizer(c.width, c.height, device=dev) for c in self.cams]
         views = (gs_view * self.V)()
         for v, (c, bs, r) in enumerate(zip(self.cams, self.sorters, self.images)):
@@ -475,9 +481,21 @@ class MultiViewRenderer:
         return (self.pre["means2d"][v], self.pre["radii"][v], self.pre["depths"][v],
                 self.pre["conics"][v], self.scene["opacities"])
 
-    def bin_sort(self):
+    def bin_sort(self, concurrent: bool = True):
+        if self.K == 1 or not concurrent:
+            for v, bs in enumerate(self.sorters):
+                bs(*self._bin_inputs(v))
+            return
+        cur = torch.cuda.current_stream()
+        if self._bin_streams is None:
+            self._bin_streams = [torch.cuda.Stream(device=self.device) for _ in range(self.K)]
+        for st in self._bin_streams:
+            st.wait_stream(cur)
         for v, bs in enumerate(self.sorters):
-            bs(*self._bin_inputs(v))
+            with torch.cuda.stream(self._bin_streams[v % self.K]):
+                bs(*self._bin_inputs(v))
+        for st in self._bin_streams:
+            cur.wait_stream(st)
 
     def raster(self, tune: gs_batch_tune | None = None, stamp=True):
         t = self.tune if tune is None else tune
