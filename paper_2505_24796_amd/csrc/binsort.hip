@@ -161,7 +161,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 // Stable LSD radix sort pass (BITS-bit digit, BITS <= 8) of u32 keys with u32
 // values: per-block digit histograms -> per-digit scan over blocks -> scatter.
 // ---------------------------------------------------------------------------
-template <int ITEMS, int BITS>
+// With DROP, keys equal to DROP_KEY are left out (counted nowhere, written
+// nowhere): the pass also compacts.
+constexpr uint32_t DROP_KEY = 0xFFFFFFFFu;
+
+template <int ITEMS, int BITS, bool DROP>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              Count cnt, int shift,
                                                              uint32_t *__restrict__ hist,
@@ -177,7 +181,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (NDIG - 1)], 1u);
+            if (i < n) {
+                const uint32_t k = keys[i];
+                if (!DROP || k != DROP_KEY) atomicAdd(&h[(k >> shift) & (NDIG - 1)], 1u);
+            }
         }
     }
     __syncthreads();
@@ -203,11 +210,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-template <int ITEMS, int BITS>
+// With DROP, block 0 also writes the number of keys kept to *n_kept.
+template <int ITEMS, int BITS, bool DROP>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
-    const uint32_t *__restrict__ totals, uint32_t nblocks) {
+    const uint32_t *__restrict__ totals, uint32_t nblocks, uint32_t *__restrict__ n_kept) {
     constexpr int NDIG = 1 << BITS;
     __shared__ uint32_t wcnt[WAVES][NDIG];
     __shared__ uint32_t gbase[NDIG];   // global position of this block's first key of digit d
@@ -228,7 +236,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     {
         // exclusive scan of the global digit totals -> digit base
         uint32_t t = threadIdx.x < NDIG ? totals[threadIdx.x] : 0u, ex;
-        block_excl_scan<uint32_t>(t, ex, lds_scan);
+        const uint32_t kept = block_excl_scan<uint32_t>(t, ex, lds_scan);
+        if (DROP && blockIdx.x == 0 && threadIdx.x == 0) *n_kept = kept;
         if (threadIdx.x < NDIG)
             gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
     }
@@ -252,10 +261,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     // to back and still see the chunks in order; one wait, then each lane
     // takes its digit's base from that lowest lane.
     uint32_t lead[W_CHUNKS];
+    uint32_t nloc_kept;  // keys of this block that are written
 #pragma unroll
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
-        bool ok = i < n;
+        bool ok = i < n && (!DROP || key[c] != DROP_KEY);
         uint32_t d = (key[c] >> shift) & (NDIG - 1);
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -288,7 +298,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
             }
         }
         uint32_t ex;
-        block_excl_scan<uint32_t>(off, ex, lds_scan);
+        nloc_kept = block_excl_scan<uint32_t>(off, ex, lds_scan);
         if (d < NDIG) lstart[d] = ex;
     }
     __syncthreads();
@@ -296,7 +306,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 #pragma unroll
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
-        if (i < n) {
+        if (i < n && (!DROP || key[c] != DROP_KEY)) {
             uint32_t d = (key[c] >> shift) & (NDIG - 1);
             uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
             skey[lp] = key[c];
@@ -305,7 +315,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     // ... and write runs of equal digits to consecutive global addresses
-    uint32_t nloc = (uint32_t)min((size_t)TILE, (size_t)n - base);
+    const uint32_t nloc = nloc_kept;
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
         uint32_t d = (k >> shift) & (NDIG - 1);
@@ -319,15 +329,15 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
-template <int ITEMS, int BITS>
+template <int ITEMS, int BITS, bool DROP>
 void radix_pass(SortBufs b, int cur, Count cnt, int shift, uint32_t nblocks, uint32_t *hist,
-                uint32_t *totals, hipStream_t s) {
-    hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS>), dim3(nblocks), dim3(SORT_THREADS), 0, s, b.k[cur],
-                       cnt, shift, hist, nblocks);
+                uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
+    hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS, DROP>), dim3(nblocks), dim3(SORT_THREADS), 0, s,
+                       b.k[cur], cnt, shift, hist, nblocks);
     hipLaunchKernelGGL(k_hist_rows, dim3(1 << BITS), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS>), dim3(nblocks), dim3(SORT_THREADS), 0, s,
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS, DROP>), dim3(nblocks), dim3(SORT_THREADS), 0, s,
                        b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals,
-                       nblocks);
+                       nblocks, n_kept);
 }
 
 // Digit widths of a sort on `bits` key bits: ceil(bits / 8) passes of
@@ -341,22 +351,35 @@ inline int radix_width(int bits, int pass) {
 }
 
 // Sorts on bits [0, bits) with radix_passes(bits) passes of ITEMS keys per
-// thread; returns the index of the buffer pair holding the result.
+// thread; returns the index of the buffer pair holding the result.  With
+// n_kept, the first pass drops every DROP_KEY key and writes how many it
+// kept there; later passes sort that many.
 template <int ITEMS>
 int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
-               hipStream_t s) {
+               uint32_t *n_kept, hipStream_t s) {
     constexpr int TILE = SORT_THREADS * ITEMS;
     uint32_t nblocks = (max_n + TILE - 1) / TILE;
     if (nblocks == 0) nblocks = 1;
     int cur = 0, shift = 0;
     for (int p = 0; p < radix_passes(bits); ++p) {
         const int w = radix_width(bits, p);
-        switch (w) {
-        case 4: radix_pass<ITEMS, 4>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
-        case 5: radix_pass<ITEMS, 5>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
-        case 6: radix_pass<ITEMS, 6>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
-        case 7: radix_pass<ITEMS, 7>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
-        default: radix_pass<ITEMS, 8>(b, cur, cnt, shift, nblocks, hist, totals, s); break;
+        if (p == 0 && n_kept) {
+            switch (w) {
+            case 4: radix_pass<ITEMS, 4, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
+            case 5: radix_pass<ITEMS, 5, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
+            case 6: radix_pass<ITEMS, 6, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
+            case 7: radix_pass<ITEMS, 7, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
+            default: radix_pass<ITEMS, 8, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
+            }
+            cnt = Count{0u, n_kept, max_n};
+        } else {
+            switch (w) {
+            case 4: radix_pass<ITEMS, 4, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
+            case 5: radix_pass<ITEMS, 5, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
+            case 6: radix_pass<ITEMS, 6, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
+            case 7: radix_pass<ITEMS, 7, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
+            default: radix_pass<ITEMS, 8, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
+            }
         }
         shift += w;
         cur ^= 1;
@@ -571,15 +594,22 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
     cnt_g[i] = c;
 }
 
-// Rectangle and splat count of each Gaussian in depth order.
+// Rectangle and splat count of each Gaussian in depth order (zero past the
+// *n_vis Gaussians that have splats).
 template <bool PRECISE>
 __global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restrict__ order,
                                                 const uint2 *__restrict__ rects,
                                                 const uint32_t *__restrict__ cnt_g,
                                                 uint2 *__restrict__ rects_sorted,
-                                                uint32_t *__restrict__ cnt) {
+                                                uint32_t *__restrict__ cnt,
+                                                const uint32_t *__restrict__ n_vis) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= P) return;
+    if ((uint32_t)j >= *n_vis) {  // past the Gaussians that have splats
+        rects_sorted[j] = make_uint2(0u, 0u);
+        cnt[j] = 0u;
+        return;
+    }
     const uint32_t g = order[j];
     const uint2 r = rects[g];
     rects_sorted[j] = r;
@@ -865,7 +895,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
 struct Layout {
     size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt_g, cnt, offs, pg, tkey0, tkey1, tid,
         hist,
-        totals, part, win, total;
+        totals, nvis, part, win, total;
     uint32_t nwin;
 };
 
@@ -897,6 +927,7 @@ Layout layout(uint32_t P, uint32_t cap, bool precise) {
     L.tid = take(4ull * cap);
     L.hist = take(4ull * RADIX * nblocks);
     L.totals = take(4ull * RADIX);
+    L.nvis = take(4);
     L.part = take(8ull * ((P + SORT_TILE - 1) / SORT_TILE + 2));
     L.win = take(4ull * L.nwin);
     L.total = off;
@@ -980,19 +1011,22 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
                            U(L.did0), (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges,
                            2 * ntiles);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
+    // Gaussians without splats (key DROP_KEY) leave in the first pass: the
+    // depth order holds the *n_vis Gaussians that have splats
+    uint32_t *n_vis = U(L.nvis);
     int dcur = radix_sort<DEPTH_ITEMS>(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32,
-                                       U(L.hist), U(L.totals), s);
+                                       U(L.hist), U(L.totals), n_vis, s);
     const uint32_t *order = db.v[dcur];
     // 2. counts in depth order, scan (+ window owners), expansion
     int pblocks = (P + 255) / 256;
     if (precise)
         hipLaunchKernelGGL(k_counts<true>, dim3(pblocks), dim3(256), 0, s, P, order,
                            (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt));
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis);
     else
         hipLaunchKernelGGL(k_counts<false>, dim3(pblocks), dim3(256), 0, s, P, order,
                            (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt));
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis);
     uint32_t sblocks = (P + SORT_TILE - 1) / SORT_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt),
                        (uint32_t)P, part);
@@ -1026,7 +1060,7 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
     // 3. stable sort by tile
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     Count nc{0u, d_num_splats, capacity};
-    int tcur = radix_sort<TILE_ITEMS>(tb, nc, capacity, tbits, U(L.hist), U(L.totals), s);
+    int tcur = radix_sort<TILE_ITEMS>(tb, nc, capacity, tbits, U(L.hist), U(L.totals), nullptr, s);
     // 4. ranges
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
     hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
