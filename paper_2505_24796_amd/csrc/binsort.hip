@@ -84,50 +84,33 @@ template <typename T> __device__ __forceinline__ T block_excl_scan(T v, T &excl,
 
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of the per-Gaussian splat counts (u64 running
-// totals so that an overflowing count is detected instead of wrapping).  The
-// down-sweep also records, for every window of `win` output slots, the
-// Gaussian that owns the window's first slot.
+// totals so that an overflowing count is detected instead of wrapping): the
+// counts kernel leaves one partial sum per block of SORT_TILE counts; each
+// down-sweep block adds up the partials before it and the grand total N
+// itself (block 0 publishes N), scans its counts, and records, for every
+// window of `win` output slots, the Gaussian that owns the window's first
+// slot.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SORT_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
-                                                              uint32_t n,
-                                                              uint64_t *__restrict__ part) {
-    __shared__ uint64_t lds[WAVES];
-    size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
-    uint64_t s = 0;
-#pragma unroll
-    for (int k = 0; k < SORT_ITEMS; ++k)
-        if (base + k < n) s += in[base + k];
-    uint64_t ex;
-    uint64_t tot = block_excl_scan<uint64_t>(s, ex, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// Single block: exclusive scan of the block partials in place; writes the
-// grand total (saturated to u32) to *total.
-__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ part, uint32_t nparts,
-                                                        uint32_t *__restrict__ total) {
-    __shared__ uint64_t lds[16];
-    uint64_t carry = 0;
-    for (uint32_t base = 0; base < nparts; base += 1024) {
-        uint32_t i = base + threadIdx.x;
-        uint64_t v = i < nparts ? part[i] : 0;
-        uint64_t ex;
-        uint64_t tot = block_excl_scan<uint64_t>(v, ex, lds);
-        if (i < nparts) part[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *total = carry > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)carry;
-}
-
 __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__restrict__ cnt,
                                                             uint32_t *__restrict__ offs, uint32_t n,
                                                             const uint64_t *__restrict__ part,
+                                                            uint32_t nparts,
                                                             uint32_t *__restrict__ win_start,
                                                             uint32_t nwin, int wshift,
-                                                            const uint32_t *__restrict__ total) {
+                                                            uint32_t *__restrict__ d_total) {
     const uint64_t win = 1ull << wshift;  // window size (a power of two)
     __shared__ uint64_t lds[WAVES];
-    const uint64_t N = *total;
+    // the block partials before this block, and all of them
+    uint64_t before = 0, all = 0;
+    for (uint32_t i = threadIdx.x; i < nparts; i += SORT_THREADS) {
+        const uint64_t v = part[i];
+        all += v;
+        before += i < blockIdx.x ? v : 0ull;
+    }
+    uint64_t ex0;
+    const uint64_t pre = block_excl_scan<uint64_t>(before, ex0, lds);
+    const uint64_t N = block_excl_scan<uint64_t>(all, ex0, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *d_total = N > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)N;
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
     uint32_t v[SORT_ITEMS];
     uint64_t s = 0;
@@ -138,7 +121,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
     }
     uint64_t ex;
     block_excl_scan<uint64_t>(s, ex, lds);
-    uint64_t run = part[blockIdx.x] + ex;
+    uint64_t run = pre + ex;
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
         if (base + k < n) {
@@ -595,25 +578,38 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
 }
 
 // Rectangle and splat count of each Gaussian in depth order (zero past the
-// *n_vis Gaussians that have splats).
+// *n_vis Gaussians that have splats), and each block's sum of counts.
 template <bool PRECISE>
-__global__ __launch_bounds__(256) void k_counts(int P, const uint32_t *__restrict__ order,
-                                                const uint2 *__restrict__ rects,
-                                                const uint32_t *__restrict__ cnt_g,
-                                                uint2 *__restrict__ rects_sorted,
-                                                uint32_t *__restrict__ cnt,
-                                                const uint32_t *__restrict__ n_vis) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P) return;
-    if ((uint32_t)j >= *n_vis) {  // past the Gaussians that have splats
-        rects_sorted[j] = make_uint2(0u, 0u);
-        cnt[j] = 0u;
-        return;
+__global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *__restrict__ order,
+                                                         const uint2 *__restrict__ rects,
+                                                         const uint32_t *__restrict__ cnt_g,
+                                                         uint2 *__restrict__ rects_sorted,
+                                                         uint32_t *__restrict__ cnt,
+                                                         const uint32_t *__restrict__ n_vis,
+                                                         uint64_t *__restrict__ part) {
+    __shared__ uint64_t lds[WAVES];
+    const uint32_t nv = *n_vis;
+    const size_t base = (size_t)blockIdx.x * SORT_TILE;
+    uint64_t sum = 0;
+#pragma unroll 4
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        const size_t j = base + (size_t)k * SORT_THREADS + threadIdx.x;
+        if (j < (size_t)P) {
+            uint2 r = make_uint2(0u, 0u);  // past the Gaussians that have splats
+            uint32_t c = 0u;
+            if (j < nv) {
+                const uint32_t g = order[j];
+                r = rects[g];
+                c = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
+            }
+            rects_sorted[j] = r;
+            cnt[j] = c;
+            sum += c;
+        }
     }
-    const uint32_t g = order[j];
-    const uint2 r = rects[g];
-    rects_sorted[j] = r;
-    cnt[j] = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
+    uint64_t ex;
+    const uint64_t tot = block_excl_scan<uint64_t>(sum, ex, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 // Stages the Gaussians of output window `blk` (slots [blk * WIN, +WIN)):
@@ -1018,25 +1014,21 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
                                        U(L.hist), U(L.totals), n_vis, s);
     const uint32_t *order = db.v[dcur];
     // 2. counts in depth order, scan (+ window owners), expansion
-    int pblocks = (P + 255) / 256;
-    if (precise)
-        hipLaunchKernelGGL(k_counts<true>, dim3(pblocks), dim3(256), 0, s, P, order,
-                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis);
-    else
-        hipLaunchKernelGGL(k_counts<false>, dim3(pblocks), dim3(256), 0, s, P, order,
-                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis);
     uint32_t sblocks = (P + SORT_TILE - 1) / SORT_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt),
-                       (uint32_t)P, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, sblocks, d_num_splats);
+    if (precise)
+        hipLaunchKernelGGL(k_counts<true>, dim3(sblocks), dim3(SORT_THREADS), 0, s, P, order,
+                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part);
+    else
+        hipLaunchKernelGGL(k_counts<false>, dim3(sblocks), dim3(SORT_THREADS), 0, s, P, order,
+                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part);
     const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
     static_assert((EMIT_TILE & (EMIT_TILE - 1)) == 0 && (EMIT_TILE_P & (EMIT_TILE_P - 1)) == 0,
                   "windows are powers of two");
     hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
-                       (uint32_t)P, (const uint64_t *)part, U(L.win), L.nwin, ceil_log2(win),
-                       d_num_splats);
+                       (uint32_t)P, (const uint64_t *)part, sblocks, U(L.win), L.nwin,
+                       ceil_log2(win), d_num_splats);
     int tbits = ceil_log2((uint32_t)ntiles);
     if (tbits == 0) tbits = 1;
     int npass = radix_passes(tbits);
