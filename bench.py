@@ -439,6 +439,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--binsort-only", action="store_true",
                     help="only time the 1080p/1M bin/sort (3-sigma and precise), for traces")
+    ap.add_argument("--train-only", action="store_true",
+                    help="only time the 1600x1064/1M training step (forward + backward), for traces")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -456,6 +458,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.binsort_only:
         binsort_only(args)
+        return
+    if args.train_only:
+        print(json.dumps(train_step(args)), flush=True)
         return
     cfg = scenegen.CONFIGS[args.workload]
     assert cfg["kind"] == "3d"
