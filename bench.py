@@ -290,8 +290,11 @@ def multiview(args):
         return np.median(np.array(rows), axis=0)
 
     st = stage_times_of(mv)
-    seq_bin = float(np.median(autotune.time_ms(lambda: mv.bin_sort(concurrent=False), reps=5,
-                                               warmup=1)))
+    # the same lists with one gs_bin_sort call per view (four streams, then one)
+    pv_bin = float(np.median(autotune.time_ms(lambda: mv.bin_sort_per_view(concurrent=True),
+                                              reps=5, warmup=1)))
+    seq_bin = float(np.median(autotune.time_ms(lambda: mv.bin_sort_per_view(concurrent=False),
+                                               reps=5, warmup=1)))
     per_view_raster = float(np.median(autotune.time_ms(mv.raster_per_view, reps=5, warmup=1)))
     single_pre = float(np.median(autotune.time_ms(
         lambda: [gs.preprocess(scene["means3d"], scene["scales"], scene["quats"], scene["sh"], c)
@@ -382,8 +385,8 @@ def multiview(args):
             "eager_ms_per_frame": eager,
             "stages_ms": {"preprocess_multiview": st[0], "bin_sort_all_views": st[1],
                           "raster_batched": st[2]},
-            "bin_sort_streams": mv.K,
-            "bin_sort_all_views_one_stream_ms": seq_bin,
+            "bin_sort": "one gs_bin_sort_multiview call" if mv.joint else "per view",
+            "bin_sort_per_view_calls_ms": {f"{mv.K}_streams": pv_bin, "1_stream": seq_bin},
             "raster_one_launch_per_view_ms": per_view_raster,
             "preprocess_one_call_per_view_ms": single_pre,
             "precise_binning": precise,

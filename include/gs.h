@@ -171,6 +171,49 @@ gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const int32_t *ra
                               size_t workspace_bytes, uint32_t *sorted_ids, uint32_t *tile_ranges,
                               uint32_t *d_num_splats, void *stream);
 
+/* Views one gs_bin_sort_multiview call can serve. */
+#define GS_MAX_BIN_VIEWS 64
+
+/* Workspace bytes gs_bin_sort_multiview needs (0 for invalid sizes). */
+size_t gs_bin_sort_multiview_workspace_bytes(int32_t nviews, int32_t P, uint32_t capacity,
+                                             const int32_t *widths, const int32_t *heights,
+                                             int32_t precise);
+
+/*
+ * gs_bin_sort_multiview -- the per-tile lists of `nviews` views of one scene
+ * (Sec. 3.1 "Sorting" per view) in one call: every stage runs once over all
+ * (Gaussian, view) pairs instead of once per view.  The lists of each view
+ * are exactly those gs_bin_sort (precise = 0) or gs_bin_sort_precise
+ * (precise != 0) builds for that view alone; they are stored view after
+ * view in one id array.
+ *   nviews in [1, GS_MAX_BIN_VIEWS]; widths[v], heights[v] HOST arrays;
+ *   means2d [nviews][P][2], radii [nviews][P], depths [nviews][P] and, when
+ *   precise, conics [nviews][P][3] (as gs_preprocess_multiview writes them)
+ *   and opacities [P] (shared by the views);
+ *   sorted_ids [capacity]     Gaussian ids (0..P-1) of every view's lists
+ *   tile_ranges [T][2]         T = sum over views of ceil(w/16) ceil(h/16);
+ *                              view v's tiles come after those of views < v,
+ *                              each view's in row-major order; [start, end)
+ *                              index sorted_ids directly, so view v's
+ *                              tile_ranges slice and the whole sorted_ids
+ *                              array are what gs_rasterize_fwd (or a
+ *                              gs_view) takes for that view
+ *   d_num_splats [1]           total splat count N (device)
+ *   d_view_splats [nviews]     per-view splat counts (device; may be NULL)
+ * If N > capacity no list is built (every range empty); the counts are still
+ * written, so the caller can size the next call.  nviews * P must be below
+ * 2^31.  Errors: as gs_bin_sort, plus GS_ERR_INVALID_ARG for a bad view count
+ * or size and GS_ERR_CAPACITY if workspace_bytes is below
+ * gs_bin_sort_multiview_workspace_bytes(...).
+ */
+gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths,
+                                const int32_t *heights, const float *means2d,
+                                const int32_t *radii, const float *depths, const float *conics,
+                                const float *opacities, int32_t precise, uint32_t capacity,
+                                void *workspace, size_t workspace_bytes, uint32_t *sorted_ids,
+                                uint32_t *tile_ranges, uint32_t *d_num_splats,
+                                uint32_t *d_view_splats, void *stream);
+
 /*
  * gs_rasterize_fwd -- conditional alpha-blending (Algorithm 1) per 16x16
  * tile.  For each pixel, front to back over its tile's list:

@@ -22,12 +22,15 @@ import ctypes
 import os
 from ctypes import POINTER, c_float, c_int32, c_size_t, c_uint32, c_void_p
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgsmfma.so")
 
 TILE = 16
+
+GS_MAX_BIN_VIEWS = 64  # views one gs_bin_sort_multiview call serves
 
 PRECISIONS = {
     "fp32": 0,
@@ -111,6 +114,14 @@ def lib() -> ctypes.CDLL:
         L.gs_bin_sort_precise.restype = ctypes.c_int
         L.gs_bin_sort_precise.argtypes = [c_int32, vp, vp, vp, vp, vp, c_int32, c_int32, c_uint32,
                                           vp, c_size_t, vp, vp, vp, vp]
+        L.gs_bin_sort_multiview_workspace_bytes.restype = c_size_t
+        L.gs_bin_sort_multiview_workspace_bytes.argtypes = [c_int32, c_int32, c_uint32,
+                                                            POINTER(c_int32), POINTER(c_int32),
+                                                            c_int32]
+        L.gs_bin_sort_multiview.restype = ctypes.c_int
+        L.gs_bin_sort_multiview.argtypes = [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                            vp, vp, vp, vp, vp, c_int32, c_uint32, vp, c_size_t,
+                                            vp, vp, vp, vp, vp]
         L.gs_preprocess_multiview.restype = ctypes.c_int
         L.gs_preprocess_multiview.argtypes = [c_int32, vp, vp, vp, vp, c_int32, c_int32,
                                               POINTER(gs_camera), vp, vp, vp, vp, vp, vp, vp]
@@ -257,6 +268,64 @@ class BinSorter:
     def n_splats(self) -> int:
         """Host read of the device splat count (synchronises)."""
         return int(self.num_splats.item()) & 0xFFFFFFFF
+
+
+class MultiViewBinSorter:
+    """gs_bin_sort_multiview at a fixed (views, P, capacity): the lists of
+    every view in one call.  ``ranges(v)`` / ``sorted_ids`` are what a
+    one-view rasterisation of view v takes; ``view_splats`` holds the
+    per-view counts (device)."""
+
+    def __init__(self, P: int, capacity: int, sizes, device="cuda", precise: bool = False):
+        self.P, self.capacity, self.precise = P, int(capacity), bool(precise)
+        self.sizes = [(int(w), int(h)) for w, h in sizes]
+        self.V = len(self.sizes)
+        self._w = (c_int32 * self.V)(*[w for w, _ in self.sizes])
+        self._h = (c_int32 * self.V)(*[h for _, h in self.sizes])
+        nbytes = lib().gs_bin_sort_multiview_workspace_bytes(self.V, P, self.capacity, self._w,
+                                                             self._h, int(self.precise))
+        if nbytes == 0:
+            raise ValueError("invalid multi-view bin_sort sizes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        nt = [grid(w, h)[0] * grid(w, h)[1] for w, h in self.sizes]
+        self.tile_base = [0]
+        for n in nt:
+            self.tile_base.append(self.tile_base[-1] + n)
+        self.all_ranges = torch.empty(self.tile_base[-1], 2, dtype=torch.int32, device=device)
+        self.sorted_ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.num_splats = torch.zeros(1, dtype=torch.int32, device=device)
+        self.view_splats = torch.zeros(self.V, dtype=torch.int32, device=device)
+
+    def ranges(self, v: int) -> torch.Tensor:
+        return self.all_ranges[self.tile_base[v]:self.tile_base[v + 1]]
+
+    def __call__(self, means2d, radii, depths, conics=None, opacities=None):
+        """means2d [V, P, 2], radii [V, P], depths [V, P] (and, precise,
+        conics [V, P, 3] and opacities [P])."""
+        _dev(means2d, torch.float32, "means2d")
+        _dev(radii, torch.int32, "radii")
+        _dev(depths, torch.float32, "depths")
+        if self.precise:
+            if conics is None or opacities is None:
+                raise ValueError("precise binning needs conics and opacities")
+            _dev(conics, torch.float32, "conics")
+            _dev(opacities, torch.float32, "opacities")
+        st = lib().gs_bin_sort_multiview(self.V, self.P, self._w, self._h, _ptr(means2d),
+                                         _ptr(radii), _ptr(depths),
+                                         _ptr(conics) if self.precise else None,
+                                         _ptr(opacities) if self.precise else None,
+                                         int(self.precise), self.capacity, _ptr(self.workspace),
+                                         self.workspace.numel(), _ptr(self.sorted_ids),
+                                         _ptr(self.all_ranges), _ptr(self.num_splats),
+                                         _ptr(self.view_splats), _stream())
+        _check("gs_bin_sort_multiview", st)
+        return self.sorted_ids, self.all_ranges, self.num_splats
+
+    def n_splats(self) -> int:
+        return int(self.num_splats.item()) & 0xFFFFFFFF
+
+    def view_counts(self) -> list:
+        return [int(x) & 0xFFFFFFFF for x in self.view_splats.cpu().tolist()]
 
 
 def preprocess_multiview(means3d, scales, quats, sh, cams, sh_degree: int = 3, out: dict | None = None) -> dict:
@@ -408,16 +477,19 @@ def wall_clock_khz() -> int:
 
 class MultiViewRenderer:
     """Renders one scene to several cameras per frame: one multi-view
-    preprocess, one bin/sort per view (``bin_streams`` views at a time, on
-    as many streams, each with its own workspace), and ONE
-    persistent batched rasteriser launch over every (view, tile) pair.
+    preprocess, one bin/sort call for every view (gs_bin_sort_multiview;
+    with ``joint_bin=False``, or more than GS_MAX_BIN_VIEWS views, one
+    gs_bin_sort per view, ``bin_streams`` views at a time on as many
+    streams), and ONE persistent batched rasteriser launch over every
+    (view, tile) pair.
     Buffers are sized once (splat capacity per view from a probe frame times
     ``slack``); a frame allocates nothing, so it can be captured in a
     hipGraph (:meth:`capture`).  Per-view latency inside a frame comes from
     device wall-clock stamps (frame start, last tile of each view)."""
 
     def __init__(self, scene: dict, cams, precision="fp16_g2l_split", slack=1.15,
-                 background=(0.0, 0.0, 0.0), sh_degree=3, precise=False, bin_streams=4):
+                 background=(0.0, 0.0, 0.0), sh_degree=3, precise=False, bin_streams=4,
+                 joint_bin=True):
         self.scene = {k: _dev(scene[k], torch.float32, k)
                       for k in ("means3d", "scales", "quats", "sh", "opacities")}
         self.cams = list(cams)
@@ -429,32 +501,40 @@ class MultiViewRenderer:
         self.device = dev
         self.pre = preprocess_multiview(self.scene["means3d"], self.scene["scales"],
                                         self.scene["quats"], self.scene["sh"], self.cams, sh_degree)
-        # probe frame: splat count per view
-        counts = []
-        for v, c in enumerate(self.cams):
-            probe = BinSorter(self.P, 0, c.width, c.height, device=dev, precise=self.precise)
-            probe(*self._bin_inputs(v))
-            counts.append(probe.n_splats())
+        self.slack = slack
+        self.joint = bool(joint_bin)
+        self.K = max(1, min(int(bin_streams), self.V))
+        self.sorters = None
+        self._bin_streams = None
+        sizes = [(c.width, c.height) for c in self.cams]
+        if self.V > GS_MAX_BIN_VIEWS:
+            self.joint = False
+        # probe frame: splat count per view (capacity 0)
+        if self.joint:
+            probe = MultiViewBinSorter(self.P, 0, sizes, device=dev, precise=self.precise)
+            probe(*self._bin_inputs_all())
+            counts = probe.view_counts()
+            del probe
+        else:
+            counts = []
+            for v, c in enumerate(self.cams):
+                probe = BinSorter(self.P, 0, c.width, c.height, device=dev, precise=self.precise)
+                probe(*self._bin_inputs(v))
+                counts.append(probe.n_splats())
         self.probe_counts = counts
         self.capacity = [int(n * slack) + 1024 for n in counts]
-        wsb = (lib().gs_bin_sort_precise_workspace_bytes if self.precise
-               else lib().gs_bin_sort_workspace_bytes)
-        ws = max(wsb(self.P, cap, c.width, c.height) for cap, c in zip(self.capacity, self.cams))
-        # views are sorted K at a time on K streams (view v on stream v % K),
-        # each stream with its own workspace: a view's bin/sort is a chain of
-        # small, latency-bound kernels that leaves most of the GPU idle
-        self.K = max(1, min(int(bin_streams), self.V))
-        self.bin_workspaces = [torch.empty(ws, dtype=torch.uint8, device=dev) for _ in range(self.K)]
-        self.sorters = [BinSorter(self.P, cap, c.width, c.height, device=dev,
-                                  workspace=self.bin_workspaces[v % self.K], precise=self.precise)
-                        for v, (cap, c) in enumerate(zip(self.capacity, self.cams))]
-        self._bin_streams = None
+        if self.joint:
+            self.mvbin = MultiViewBinSorter(self.P, sum(self.capacity), sizes, device=dev,
+                                            precise=self.precise)
+        else:
+            self._per_view_sorters()
         self.images = [Rasterizer(c.width, c.height, device=dev) for c in self.cams]
         views = (gs_view * self.V)()
-        for v, (c, bs, r) in enumerate(zip(self.cams, self.sorters, self.images)):
+        for v, (c, r) in enumerate(zip(self.cams, self.images)):
             g = views[v]
             g.width, g.height = c.width, c.height
-            g.tile_ranges, g.sorted_ids = bs.ranges.data_ptr(), bs.sorted_ids.data_ptr()
+            rg, ids = self._lists(v)
+            g.tile_ranges, g.sorted_ids = rg.data_ptr(), ids.data_ptr()
             g.means2d = self.pre["means2d"][v].data_ptr()
             g.conics = self.pre["conics"][v].data_ptr()
             g.opacities = self.scene["opacities"].data_ptr()
@@ -481,7 +561,61 @@ class MultiViewRenderer:
         return (self.pre["means2d"][v], self.pre["radii"][v], self.pre["depths"][v],
                 self.pre["conics"][v], self.scene["opacities"])
 
+    def _bin_inputs_all(self):
+        return (self.pre["means2d"], self.pre["radii"], self.pre["depths"], self.pre["conics"],
+                self.scene["opacities"])
+
+    def _per_view_sorters(self):
+        """One BinSorter per view (views are sorted K at a time on K streams,
+        view v on stream v % K, each stream with its own workspace): the
+        pipelined frame and the per-view comparison use them."""
+        if self.sorters is None:
+            dev = self.device
+            wsb = (lib().gs_bin_sort_precise_workspace_bytes if self.precise
+                   else lib().gs_bin_sort_workspace_bytes)
+            ws = max(wsb(self.P, cap, c.width, c.height) for cap, c in zip(self.capacity, self.cams))
+            self.bin_workspaces = [torch.empty(ws, dtype=torch.uint8, device=dev)
+                                   for _ in range(self.K)]
+            self.sorters = [BinSorter(self.P, cap, c.width, c.height, device=dev,
+                                      workspace=self.bin_workspaces[v % self.K],
+                                      precise=self.precise)
+                            for v, (cap, c) in enumerate(zip(self.capacity, self.cams))]
+        return self.sorters
+
+    def _lists(self, v):
+        """(tile ranges, sorted ids) of view v for the frame's rasterisation."""
+        if self.joint:
+            return self.mvbin.ranges(v), self.mvbin.sorted_ids
+        return self.sorters[v].ranges, self.sorters[v].sorted_ids
+
+    def view_lists(self, v):
+        """Host copies of view v's lists as one-view binning gives them:
+        (ranges [ntiles, 2] counted from the view's first splat, empty tiles
+        [0, 0]; sorted ids [n])."""
+        rg, ids = self._lists(v)
+        rg = rg.cpu().numpy().astype(np.int64)
+        if self.joint:
+            base = sum(self.mvbin.view_counts()[:v])
+            n = self.mvbin.view_counts()[v]
+        else:
+            base, n = 0, self.sorters[v].n_splats()
+        full = rg[:, 1] > rg[:, 0]
+        out = np.zeros_like(rg)
+        out[full] = rg[full] - base
+        return out, ids[base:base + n].cpu().numpy()
+
     def bin_sort(self, concurrent: bool = True):
+        """Every view's lists: one gs_bin_sort_multiview call (joint), or one
+        gs_bin_sort per view."""
+        if self.joint:
+            self.mvbin(*self._bin_inputs_all())
+        else:
+            self.bin_sort_per_view(concurrent)
+
+    def bin_sort_per_view(self, concurrent: bool = True):
+        """One gs_bin_sort per view (K streams when ``concurrent``) into the
+        per-view sorters' own buffers."""
+        self._per_view_sorters()
         if self.K == 1 or not concurrent:
             for v, bs in enumerate(self.sorters):
                 bs(*self._bin_inputs(v))
@@ -508,8 +642,9 @@ class MultiViewRenderer:
 
     def raster_per_view(self):
         """The same images with one gs_rasterize_fwd launch per view."""
-        for v, (bs, r) in enumerate(zip(self.sorters, self.images)):
-            r(bs.ranges, bs.sorted_ids, self.pre["means2d"][v], self.pre["conics"][v],
+        for v, r in enumerate(self.images):
+            rg, ids = self._lists(v)
+            r(rg, ids, self.pre["means2d"][v], self.pre["conics"][v],
               self.scene["opacities"], self.pre["rgb"][v], self.precision,
               tuple(self.views[v].background))
 
@@ -531,6 +666,7 @@ class MultiViewRenderer:
             self._side = torch.cuda.Stream(device=self.device)
             self._events = [torch.cuda.Event() for _ in range(self.V)]
         L = lib()
+        self._per_view_sorters()
         _check("gs_clock_stamp", L.gs_clock_stamp(_ptr(self.clock), _stream()))
         self.preprocess()
         side = self._side
@@ -564,9 +700,14 @@ class MultiViewRenderer:
 
     # -- results ----------------------------------------------------------
     def n_splats(self):
+        if self.joint:
+            return self.mvbin.view_counts()
         return [bs.n_splats() for bs in self.sorters]
 
     def overflowed(self):
+        if self.joint:
+            over = self.mvbin.n_splats() > self.mvbin.capacity
+            return [over] * self.V
         return [n > cap for n, cap in zip(self.n_splats(), self.capacity)]
 
     def latencies_ms(self):

@@ -97,7 +97,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
                                                             uint32_t nparts,
                                                             uint32_t *__restrict__ win_start,
                                                             uint32_t nwin, int wshift,
-                                                            uint32_t *__restrict__ d_total) {
+                                                            uint32_t *__restrict__ d_total,
+                                                            uint32_t *__restrict__ seg_bounds,
+                                                            int nv, uint32_t Pv) {
     const uint64_t win = 1ull << wshift;  // window size (a power of two)
     __shared__ uint64_t lds[WAVES];
     // the block partials before this block, and all of them
@@ -110,7 +112,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
     uint64_t ex0;
     const uint64_t pre = block_excl_scan<uint64_t>(before, ex0, lds);
     const uint64_t N = block_excl_scan<uint64_t>(all, ex0, lds);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *d_total = N > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)N;
+    const uint32_t Nsat = N > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)N;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *d_total = Nsat;
+        seg_bounds[nv] = Nsat;
+    }
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
     uint32_t v[SORT_ITEMS];
     uint64_t s = 0;
@@ -122,10 +128,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
     uint64_t ex;
     block_excl_scan<uint64_t>(s, ex, lds);
     uint64_t run = pre + ex;
+    // view v's splats start at the offset of its first instance, v * Pv
+    uint32_t vnext = (uint32_t)((base + Pv - 1) / Pv);
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
         if (base + k < n) {
             offs[base + k] = (uint32_t)run;
+            if ((int)vnext < nv && base + k == (size_t)vnext * Pv) {
+                seg_bounds[vnext] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
+                ++vnext;
+            }
             // windows whose first slot falls inside [run, run + v)
             if (v[k] > 0) {
                 uint64_t w0 = (run + win - 1) >> wshift;
@@ -142,87 +154,153 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort pass (BITS-bit digit, BITS <= 8) of u32 keys with u32
-// values: per-block digit histograms -> per-digit scan over blocks -> scatter.
+// values over independent segments of the arrays (the views of a multi-view
+// frame; one segment for a single image): per-block digit histograms ->
+// per-(segment, digit) scan over the segment's blocks -> scatter.  Each
+// segment is split into blocks of ITEMS * SORT_THREADS keys; workgroup b of
+// a pass takes block b of the concatenation of the segments' blocks (idle
+// past the last one), so one launch serves every segment.
 // ---------------------------------------------------------------------------
 // With DROP, keys equal to DROP_KEY are left out (counted nowhere, written
 // nowhere): the pass also compacts.
 constexpr uint32_t DROP_KEY = 0xFFFFFFFFu;
+constexpr int MAX_SEGS = GS_MAX_BIN_VIEWS;
+
+// Segment s holds keys [base_s, base_s + n_s) of the arrays: base_s = s *
+// stride and n_s = n_dev[s] (or n_static), or base_s = bounds[s] and n_s =
+// bounds[s + 1] - bounds[s].  With `total`, every segment is empty when
+// *total > cap (an overflowing frame).  The digit of a key in segment s is
+// taken from key - kbase[s].
+struct SegTable {
+    int nseg;
+    uint32_t stride, n_static;
+    const uint32_t *n_dev;
+    const uint32_t *bounds;
+    const uint32_t *total;
+    uint32_t cap;
+    uint32_t kbase[MAX_SEGS];
+    __device__ __forceinline__ void get(int sg, uint32_t &base, uint32_t &n) const {
+        if (total && *total > cap) {
+            base = 0u;
+            n = 0u;
+        } else if (bounds) {
+            base = bounds[sg];
+            n = bounds[sg + 1] - base;
+        } else {
+            base = (uint32_t)sg * stride;
+            n = n_dev ? n_dev[sg] : n_static;
+        }
+    }
+};
+
+// Segment, block within it, and the segment's range for workgroup b; false
+// past the last block.  col0 = the segment's first workgroup.
+template <int TILE>
+__device__ __forceinline__ bool seg_block(const SegTable &st, uint32_t b, int &sg, uint32_t &lb,
+                                          uint32_t &base, uint32_t &n, uint32_t &col0) {
+    uint32_t acc = 0;
+    for (int q = 0; q < st.nseg; ++q) {
+        st.get(q, base, n);
+        const uint32_t nb = (n + TILE - 1) / TILE;
+        if (b < acc + nb) {
+            sg = q;
+            lb = b - acc;
+            col0 = acc;
+            return true;
+        }
+        acc += nb;
+    }
+    return false;
+}
 
 template <int ITEMS, int BITS, bool DROP>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
-                                                             Count cnt, int shift,
-                                                             uint32_t *__restrict__ hist,
-                                                             uint32_t nblocks) {
+                                                             SegTable st, int shift,
+                                                             uint32_t *__restrict__ hist) {
     constexpr int NDIG = 1 << BITS;
+    constexpr int TILE = SORT_THREADS * ITEMS;
     __shared__ uint32_t h[NDIG];
-    uint32_t n = cnt.get();
+    int sg;
+    uint32_t lb, base, n, col0;
+    if (!seg_block<TILE>(st, blockIdx.x, sg, lb, base, n, col0)) return;  // idle: uniform exit
     if (threadIdx.x < NDIG) h[threadIdx.x] = 0;
     __syncthreads();
-    constexpr int TILE = SORT_THREADS * ITEMS;
-    size_t base = (size_t)blockIdx.x * TILE;
-    if (base < n) {
+    const uint32_t kb = st.kbase[sg];
+    const size_t b0 = (size_t)lb * TILE;
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            size_t i = base + (size_t)k * SORT_THREADS + threadIdx.x;
-            if (i < n) {
-                const uint32_t k = keys[i];
-                if (!DROP || k != DROP_KEY) atomicAdd(&h[(k >> shift) & (NDIG - 1)], 1u);
-            }
+    for (int k = 0; k < ITEMS; ++k) {
+        const size_t i = b0 + (size_t)k * SORT_THREADS + threadIdx.x;
+        if (i < n) {
+            const uint32_t key = keys[base + i];
+            if (!DROP || key != DROP_KEY) atomicAdd(&h[((key - kb) >> shift) & (NDIG - 1)], 1u);
         }
     }
     __syncthreads();
-    if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// One block per digit: exclusive scan of that digit's counts over blocks, in
-// place; the digit total goes to totals[d].
+// Workgroup (d, s): exclusive scan of digit d's counts over the blocks of
+// segment s, in place; the total goes to totals[s][d].  ncols = workgroups
+// of the hist and scatter launches.
+template <int TILE>
 __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict__ hist,
-                                                            uint32_t nblocks,
+                                                            SegTable st, uint32_t ncols,
                                                             uint32_t *__restrict__ totals) {
     __shared__ uint32_t lds[WAVES];
-    uint32_t *row = hist + (size_t)blockIdx.x * nblocks;
+    const int sg = blockIdx.y;
+    uint32_t col0 = 0, base, n;
+    for (int q = 0; q < sg; ++q) {
+        st.get(q, base, n);
+        col0 += (n + TILE - 1) / TILE;
+    }
+    st.get(sg, base, n);
+    const uint32_t nb = (n + TILE - 1) / TILE;
+    uint32_t *row = hist + (size_t)blockIdx.x * ncols + col0;
     uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nblocks; b0 += SORT_THREADS) {
-        uint32_t i = b0 + threadIdx.x;
-        uint32_t v = i < nblocks ? row[i] : 0u;
+    for (uint32_t c0 = 0; c0 < nb; c0 += SORT_THREADS) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t v = i < nb ? row[i] : 0u;
         uint32_t ex;
-        uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
-        if (i < nblocks) row[i] = carry + ex;
+        const uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
+        if (i < nb) row[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) totals[sg * RADIX + blockIdx.x] = carry;
 }
 
-// With DROP, block 0 also writes the number of keys kept to *n_kept.
+// With DROP, the first block of each segment also writes the number of keys
+// the segment keeps to n_kept[s].
 template <int ITEMS, int BITS, bool DROP>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, Count cnt, int shift, const uint32_t *__restrict__ hist_scan,
-    const uint32_t *__restrict__ totals, uint32_t nblocks, uint32_t *__restrict__ n_kept) {
+    uint32_t *__restrict__ vout, SegTable st, int shift, const uint32_t *__restrict__ hist_scan,
+    const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept) {
     constexpr int NDIG = 1 << BITS;
     __shared__ uint32_t wcnt[WAVES][NDIG];
-    __shared__ uint32_t gbase[NDIG];   // global position of this block's first key of digit d
+    __shared__ uint32_t gbase[NDIG];   // segment position of this block's first key of digit d
     __shared__ uint32_t lstart[NDIG];  // local position of this block's first key of digit d
     constexpr int TILE = SORT_THREADS * ITEMS;
     constexpr int W_ITEMS = TILE / WAVES, W_CHUNKS = W_ITEMS / 64;
     __shared__ uint32_t skey[TILE];
     __shared__ uint32_t sval[TILE];
     __shared__ uint32_t lds_scan[WAVES];
-    uint32_t n = cnt.get();
-    size_t base = (size_t)blockIdx.x * TILE;
-    if (base >= n) return;  // whole block idle: uniform exit
+    int sg;
+    uint32_t lb, sbase, n, col0;
+    if (!seg_block<TILE>(st, blockIdx.x, sg, lb, sbase, n, col0)) return;  // idle: uniform exit
+    const uint32_t kb = st.kbase[sg];
+    const size_t base = (size_t)lb * TILE;  // within the segment
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < NDIG) {
 #pragma unroll
         for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
     }
     {
-        // exclusive scan of the global digit totals -> digit base
-        uint32_t t = threadIdx.x < NDIG ? totals[threadIdx.x] : 0u, ex;
+        // exclusive scan of the segment's digit totals -> digit base
+        uint32_t t = threadIdx.x < NDIG ? totals[sg * RADIX + threadIdx.x] : 0u, ex;
         const uint32_t kept = block_excl_scan<uint32_t>(t, ex, lds_scan);
-        if (DROP && blockIdx.x == 0 && threadIdx.x == 0) *n_kept = kept;
+        if (DROP && lb == 0 && threadIdx.x == 0) n_kept[sg] = kept;
         if (threadIdx.x < NDIG)
-            gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
+            gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
     }
     __syncthreads();
 
@@ -232,8 +310,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n;
-        key[c] = ok ? kin[i] : 0u;
-        val[c] = ok ? vin[i] : 0u;
+        key[c] = ok ? kin[sbase + i] : 0u;
+        val[c] = ok ? vin[sbase + i] : 0u;
     }
     // Rank of each key among the wave's keys of its digit, in input order:
     // within a chunk of 64 from the lanes below with the same digit (one
@@ -249,11 +327,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n && (!DROP || key[c] != DROP_KEY);
-        uint32_t d = (key[c] >> shift) & (NDIG - 1);
+        uint32_t d = ((key[c] - kb) >> shift) & (NDIG - 1);
         uint64_t peers = __ballot(ok);
 #pragma unroll
-        for (int b = 0; b < BITS; ++b) {
-            bool bit = (d >> b) & 1u;
+        for (int bb = 0; bb < BITS; ++bb) {
+            bool bit = (d >> bb) & 1u;
             uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
@@ -265,8 +343,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 #pragma unroll
     for (int c = 0; c < W_CHUNKS; ++c) {
         // the leader holds (count before | flag); the others their rank
-        const uint32_t b = (uint32_t)__shfl((int)pos[c], (int)lead[c], 64) & 0x7FFFFFFFu;
-        pos[c] = (pos[c] & 0x80000000u) ? b : b + pos[c];
+        const uint32_t ld = (uint32_t)__shfl((int)pos[c], (int)lead[c], 64) & 0x7FFFFFFFu;
+        pos[c] = (pos[c] & 0x80000000u) ? ld : ld + pos[c];
     }
     __syncthreads();
     {
@@ -290,7 +368,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     for (int c = 0; c < W_CHUNKS; ++c) {
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n && (!DROP || key[c] != DROP_KEY)) {
-            uint32_t d = (key[c] >> shift) & (NDIG - 1);
+            uint32_t d = ((key[c] - kb) >> shift) & (NDIG - 1);
             uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
             skey[lp] = key[c];
             sval[lp] = val[c];
@@ -301,8 +379,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t nloc = nloc_kept;
     for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
         uint32_t k = skey[lp];
-        uint32_t d = (k >> shift) & (NDIG - 1);
-        uint32_t dst = gbase[d] + (lp - lstart[d]);
+        uint32_t d = ((k - kb) >> shift) & (NDIG - 1);
+        uint32_t dst = sbase + gbase[d] + (lp - lstart[d]);
         kout[dst] = k;
         vout[dst] = sval[lp];
     }
@@ -313,14 +391,16 @@ struct SortBufs {
 };
 
 template <int ITEMS, int BITS, bool DROP>
-void radix_pass(SortBufs b, int cur, Count cnt, int shift, uint32_t nblocks, uint32_t *hist,
+void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols, uint32_t *hist,
                 uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
-    hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS, DROP>), dim3(nblocks), dim3(SORT_THREADS), 0, s,
-                       b.k[cur], cnt, shift, hist, nblocks);
-    hipLaunchKernelGGL(k_hist_rows, dim3(1 << BITS), dim3(SORT_THREADS), 0, s, hist, nblocks, totals);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS, DROP>), dim3(nblocks), dim3(SORT_THREADS), 0, s,
-                       b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], cnt, shift, hist, totals,
-                       nblocks, n_kept);
+    constexpr int TILE = SORT_THREADS * ITEMS;
+    hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS, DROP>), dim3(ncols), dim3(SORT_THREADS), 0, s,
+                       b.k[cur], st, shift, hist);
+    hipLaunchKernelGGL(k_hist_rows<TILE>, dim3(1 << BITS, st.nseg), dim3(SORT_THREADS), 0, s, hist,
+                       st, ncols, totals);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS, DROP>), dim3(ncols), dim3(SORT_THREADS), 0, s,
+                       b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], st, shift, hist, totals,
+                       n_kept);
 }
 
 // Digit widths of a sort on `bits` key bits: ceil(bits / 8) passes of
@@ -333,35 +413,34 @@ inline int radix_width(int bits, int pass) {
     return w < 4 ? 4 : w;
 }
 
-// Sorts on bits [0, bits) with radix_passes(bits) passes of ITEMS keys per
-// thread; returns the index of the buffer pair holding the result.  With
-// n_kept, the first pass drops every DROP_KEY key and writes how many it
-// kept there; later passes sort that many.
+// Sorts every segment of `st` on bits [0, bits) of (key - kbase) with
+// radix_passes(bits) passes of ITEMS keys per thread; `ncols` workgroups per
+// launch cover the segments' blocks.  Returns the index of the buffer pair
+// holding the result.  With n_kept, the first pass drops every DROP_KEY key
+// and writes how many each segment kept there; later passes sort that many.
 template <int ITEMS>
-int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, uint32_t *totals,
-               uint32_t *n_kept, hipStream_t s) {
-    constexpr int TILE = SORT_THREADS * ITEMS;
-    uint32_t nblocks = (max_n + TILE - 1) / TILE;
-    if (nblocks == 0) nblocks = 1;
+int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist,
+               uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
+    if (ncols == 0) ncols = 1;
     int cur = 0, shift = 0;
     for (int p = 0; p < radix_passes(bits); ++p) {
         const int w = radix_width(bits, p);
         if (p == 0 && n_kept) {
             switch (w) {
-            case 4: radix_pass<ITEMS, 4, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
-            case 5: radix_pass<ITEMS, 5, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
-            case 6: radix_pass<ITEMS, 6, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
-            case 7: radix_pass<ITEMS, 7, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
-            default: radix_pass<ITEMS, 8, true>(b, cur, cnt, shift, nblocks, hist, totals, n_kept, s); break;
+            case 4: radix_pass<ITEMS, 4, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
+            case 5: radix_pass<ITEMS, 5, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
+            case 6: radix_pass<ITEMS, 6, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
+            case 7: radix_pass<ITEMS, 7, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
+            default: radix_pass<ITEMS, 8, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
             }
-            cnt = Count{0u, n_kept, max_n};
+            st.n_dev = n_kept;
         } else {
             switch (w) {
-            case 4: radix_pass<ITEMS, 4, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
-            case 5: radix_pass<ITEMS, 5, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
-            case 6: radix_pass<ITEMS, 6, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
-            case 7: radix_pass<ITEMS, 7, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
-            default: radix_pass<ITEMS, 8, false>(b, cur, cnt, shift, nblocks, hist, totals, nullptr, s); break;
+            case 4: radix_pass<ITEMS, 4, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
+            case 5: radix_pass<ITEMS, 5, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
+            case 6: radix_pass<ITEMS, 6, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
+            case 7: radix_pass<ITEMS, 7, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
+            default: radix_pass<ITEMS, 8, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
             }
         }
         shift += w;
@@ -369,6 +448,18 @@ int radix_sort(SortBufs b, Count cnt, uint32_t max_n, int bits, uint32_t *hist, 
     }
     return cur;
 }
+
+// Views of one bin/sort call: instance i of its V * P (Gaussian, view)
+// pairs is Gaussian i % P seen from view i / P (the per-view arrays are
+// view-major).  View v's tiles are numbered tbase[v] + ty * gx[v] + tx in
+// the call's tile ranges.
+struct ViewTable {
+    int nv;
+    uint32_t P;
+    int W[MAX_SEGS], H[MAX_SEGS];
+    uint32_t gx[MAX_SEGS], tbase[MAX_SEGS];
+    __device__ __forceinline__ int view_of(uint32_t i) const { return nv == 1 ? 0 : (int)(i / P); }
+};
 
 // ---------------------------------------------------------------------------
 // Stage kernels
@@ -493,8 +584,8 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     const int *__restrict__ radii,
                                                     const float *__restrict__ depths,
                                                     const float *__restrict__ conics,
-                                                    const float *__restrict__ opac, int W, int H,
-                                                    int gx, uint32_t *__restrict__ keys,
+                                                    const float *__restrict__ opac, ViewTable vt,
+                                                    uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
                                                     uint2 *__restrict__ rects,
                                                     uint32_t *__restrict__ cnt_g,
@@ -506,13 +597,15 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
     // lanes past P stay, as Gaussians without tiles)
     if (!PRECISE && i >= P) return;
     const bool live = i < P;
+    const int view = live ? vt.view_of((uint32_t)i) : 0;
+    const int W = vt.W[view], H = vt.H[view];
     float d = live ? depths[i] : 0.0f;
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
     int n = 0;
     float2 m = make_float2(0.f, 0.f);
     if (live && isfinite(d)) {
         m = means2d[i];
-        n = gs::tile_rect(m.x, m.y, radii[i], W, H, gx, tx0, tx1, ty0, ty1);
+        n = gs::tile_rect(m.x, m.y, radii[i], W, H, (int)vt.gx[view], tx0, tx1, ty0, ty1);
     }
     uint32_t c = (uint32_t)n;
     if (PRECISE) {
@@ -521,7 +614,7 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
         // the wave wait for its tallest one); each pair adds its run length
         // to its Gaussian's count in LDS.
         __shared__ PGauss s_q[256];
-        __shared__ int s_rows[256][3];  // tx0, tx1, ty0 of the rectangle
+        __shared__ int s_rows[256][5];  // tx0, tx1, ty0 of the rectangle; W, H of the view
         __shared__ uint32_t s_start[256];
         __shared__ uint32_t s_cnt[256];
         const int lane = threadIdx.x & 63, wb = threadIdx.x & ~63;
@@ -529,7 +622,8 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
         uint32_t h = 0;
         if (n > 0) {
             bool any;
-            q = make_pgauss(m, conics[3 * i], conics[3 * i + 1], conics[3 * i + 2], opac[i], any);
+            q = make_pgauss(m, conics[3 * i], conics[3 * i + 1], conics[3 * i + 2],
+                            opac[i - view * (int)vt.P], any);
             if (any) h = (uint32_t)(ty1 - ty0 + 1);
         }
         if (live) pg[i] = q;
@@ -537,6 +631,8 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
         s_rows[threadIdx.x][0] = tx0;
         s_rows[threadIdx.x][1] = tx1;
         s_rows[threadIdx.x][2] = ty0;
+        s_rows[threadIdx.x][3] = W;
+        s_rows[threadIdx.x][4] = H;
         s_cnt[threadIdx.x] = 0u;
         // exclusive prefix of h over the wave
         uint32_t incl = h;
@@ -560,7 +656,8 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                 const int o = wb + (int)lo;
                 int c0, c1;
                 const uint32_t r = row_span(s_q[o], s_rows[o][2] + (int)(p - s_start[o]),
-                                            s_rows[o][0], s_rows[o][1], W, H, c0, c1);
+                                            s_rows[o][0], s_rows[o][1], s_rows[o][3],
+                                            s_rows[o][4], c0, c1);
                 if (r) atomicAdd(&s_cnt[o], r);
             }
         }
@@ -577,8 +674,9 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
     cnt_g[i] = c;
 }
 
-// Rectangle and splat count of each Gaussian in depth order (zero past the
-// *n_vis Gaussians that have splats), and each block's sum of counts.
+// Rectangle and splat count of each instance in depth order (view by view;
+// zero past the n_vis[v] instances of view v that have splats), and each
+// block's sum of counts.
 template <bool PRECISE>
 __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *__restrict__ order,
                                                          const uint2 *__restrict__ rects,
@@ -586,9 +684,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
                                                          uint2 *__restrict__ rects_sorted,
                                                          uint32_t *__restrict__ cnt,
                                                          const uint32_t *__restrict__ n_vis,
-                                                         uint64_t *__restrict__ part) {
+                                                         uint64_t *__restrict__ part, ViewTable vt) {
     __shared__ uint64_t lds[WAVES];
-    const uint32_t nv = *n_vis;
     const size_t base = (size_t)blockIdx.x * SORT_TILE;
     uint64_t sum = 0;
 #pragma unroll 4
@@ -597,7 +694,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
         if (j < (size_t)P) {
             uint2 r = make_uint2(0u, 0u);  // past the Gaussians that have splats
             uint32_t c = 0u;
-            if (j < nv) {
+            const int v = vt.view_of((uint32_t)j);
+            if (j - (size_t)v * vt.P < n_vis[v]) {
                 const uint32_t g = order[j];
                 r = rects[g];
                 c = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
@@ -613,29 +711,41 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
 }
 
 // Stages the Gaussians of output window `blk` (slots [blk * WIN, +WIN)):
-// j0 = owner of its first slot up to j1 = owner of the next window's first
-// slot (or of the last slot); every Gaussian in between owns at least one
-// slot of the window, so there are at most WIN + 1.  Returns m, or 0 when
-// the window is idle (overflow, past N).  All threads of the block call it.
+// those with splats among j0 = owner of its first slot up to j1 = owner of
+// the next window's first slot (or of the last slot).  Within one view
+// every instance in between owns at least one slot of the window; across a
+// view boundary the instances of view v without splats (positions
+// [v P + n_vis[v], (v + 1) P)) are skipped.  So at most WIN + 1 are staged.
+// Returns their number m, or 0 when the window is idle (overflow, past N).
+// All threads of the block call it.
 template <int WIN, int NT>
 __device__ __forceinline__ uint32_t stage_window(int P, const uint32_t *__restrict__ order,
                                                  const uint32_t *__restrict__ offs,
                                                  const uint2 *__restrict__ rects_sorted,
                                                  const uint32_t *__restrict__ win_start,
                                                  uint32_t nwin, uint32_t N, uint32_t cap,
+                                                 const ViewTable &vt,
+                                                 const uint32_t *__restrict__ n_vis,
                                                  uint32_t *s_off, uint2 *s_rect, uint32_t *s_id) {
     const uint32_t o0 = blockIdx.x * (uint32_t)WIN;
     if (N > cap || o0 >= N || blockIdx.x + 1 >= nwin) return 0u;
     const uint32_t j0 = win_start[blockIdx.x];
     const uint32_t j1 = win_start[blockIdx.x + 1];
-    if (j0 >= (uint32_t)P) return 0u;  // cannot happen when the scan ran; keeps reads in bounds
-    uint32_t m = (j1 >= j0 ? j1 - j0 : 0u) + 1u;
-    m = min(m, (uint32_t)WIN + 1u);
-    m = min(m, (uint32_t)P - j0);
-    for (uint32_t k = threadIdx.x; k < m; k += NT) {
-        s_off[k] = offs[j0 + k];
-        s_rect[k] = rects_sorted[j0 + k];
-        s_id[k] = order[j0 + k];
+    if (j0 >= (uint32_t)P || j1 >= (uint32_t)P || j1 < j0) return 0u;  // cannot happen when the scan ran
+    const int v0 = vt.view_of(j0), v1 = vt.view_of(j1);
+    uint32_t m = 0;
+    for (int v = v0; v <= v1 && m < (uint32_t)WIN + 1u; ++v) {
+        // view v's instances with splats that lie in [j0, j1]
+        const uint32_t vb = (uint32_t)v * vt.P;
+        const uint32_t lo = max(j0, vb), hi = min(j1 + 1u, vb + n_vis[v]);
+        if (hi <= lo) continue;
+        const uint32_t len = min(hi - lo, (uint32_t)WIN + 1u - m);
+        for (uint32_t k = threadIdx.x; k < len; k += NT) {
+            s_off[m + k] = offs[lo + k];
+            s_rect[m + k] = rects_sorted[lo + k];
+            s_id[m + k] = order[lo + k];
+        }
+        m += len;
     }
     return m;
 }
@@ -659,7 +769,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
                                                        const uint32_t *__restrict__ offs,
                                                        const uint2 *__restrict__ rects_sorted,
                                                        const uint32_t *__restrict__ win_start,
-                                                       uint32_t nwin, int gx,
+                                                       uint32_t nwin, ViewTable vt,
+                                                       const uint32_t *__restrict__ n_vis,
                                                        const uint32_t *__restrict__ n_splats,
                                                        uint32_t cap, uint32_t *__restrict__ tkey,
                                                        uint32_t *__restrict__ tid) {
@@ -670,7 +781,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
     __shared__ uint32_t s_tg[EMIT_TILE];
     const uint32_t N = *n_splats;
     const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS>(P, order, offs, rects_sorted, win_start,
-                                                             nwin, N, cap, s_off, s_rect, s_id);
+                                                             nwin, N, cap, vt, n_vis, s_off,
+                                                             s_rect, s_id);
     if (m == 0) return;  // block-uniform
     __syncthreads();
     const uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
@@ -682,12 +794,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
         uint2 r = s_rect[k];
         uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
         uint32_t row = l / w, col = l - row * w;
+        // the Gaussian's view: its tile numbering and its id within the view
+        int v = vt.view_of(s_id[k]);
+        uint32_t gid = s_id[k] - (uint32_t)v * vt.P;
         for (int i = 0; i < EMIT_ITEMS; ++i) {
             const uint32_t o = s0 + (uint32_t)i;
             if (o >= oend) break;
             const uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
-            s_tk[o - o0] = ty * (uint32_t)gx + tx;
-            s_tg[o - o0] = s_id[k];
+            s_tk[o - o0] = vt.tbase[v] + ty * vt.gx[v] + tx;
+            s_tg[o - o0] = gid;
             if (++col == w) {
                 col = 0;
                 if (++row == h && k + 1 < m) {
@@ -696,6 +811,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
                     r = s_rect[k];
                     w = max(r.y & 0xFFFFu, 1u);
                     h = max(r.y >> 16, 1u);
+                    v = vt.view_of(s_id[k]);
+                    gid = s_id[k] - (uint32_t)v * vt.P;
                 }
             }
         }
@@ -736,8 +853,9 @@ __device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t n, ui
 __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
     int P, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offs,
     const uint2 *__restrict__ rects_sorted, const PGauss *__restrict__ pg,
-    const uint32_t *__restrict__ win_start, uint32_t nwin, int gx, int W, int H,
-    const uint32_t *__restrict__ n_splats, uint32_t cap, uint32_t *__restrict__ tkey,
+    const uint32_t *__restrict__ win_start, uint32_t nwin, ViewTable vt,
+    const uint32_t *__restrict__ n_vis, const uint32_t *__restrict__ n_splats, uint32_t cap,
+    uint32_t *__restrict__ tkey,
     uint32_t *__restrict__ tid) {
     constexpr int WIN = EMIT_TILE_P;
     __shared__ uint32_t s_off[WIN + 1];
@@ -751,7 +869,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
     __shared__ uint32_t s_scan[WAVES];
     const uint32_t N = *n_splats;
     const uint32_t m = stage_window<WIN, SORT_THREADS>(P, order, offs, rects_sorted, win_start,
-                                                       nwin, N, cap, s_off, s_rect, s_id);
+                                                       nwin, N, cap, vt, n_vis, s_off, s_rect,
+                                                       s_id);
     if (m == 0) return;  // block-uniform
     __syncthreads();
     const uint32_t o0 = blockIdx.x * (uint32_t)WIN;
@@ -772,8 +891,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
             const RectDec d = dec_rect(s_rect[k]);
             const int ty = d.ty0 + (int)(p - s_hoff[k]);
             const PGauss q = pg[s_id[k]];
+            const int v = vt.view_of(s_id[k]);
             int c0 = 0, c1 = -1;
-            const uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
+            const uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, vt.W[v], vt.H[v], c0, c1);
             s_pk[p] = (uint16_t)k;
             s_pty[p] = (uint16_t)ty;
             s_pc0[p] = (uint16_t)c0;
@@ -795,8 +915,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
             for (int i = 0; i < EMIT_ITEMS_P; ++i) {
                 const uint32_t o = s0 + (uint32_t)i;
                 if (o >= oend || within >= s_pn[p]) break;
-                s_tk[o - o0] = (uint32_t)s_pty[p] * (uint32_t)gx + s_pc0[p] + within;
-                s_tg[o - o0] = s_id[s_pk[p]];
+                const uint32_t g = s_id[s_pk[p]];
+                const int v = vt.view_of(g);
+                s_tk[o - o0] = vt.tbase[v] + (uint32_t)s_pty[p] * vt.gx[v] + s_pc0[p] + within;
+                s_tg[o - o0] = g - (uint32_t)v * vt.P;
                 if (++within < s_pn[p]) continue;
                 within = 0;
                 do {
@@ -811,6 +933,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
         uint32_t l = s0 - s_off[k];
         PGauss q = pg[s_id[k]];
         RectDec d = dec_rect(s_rect[k]);
+        int v = vt.view_of(s_id[k]);
+        int W = vt.W[v], H = vt.H[v];
         int ty = d.ty0, c0 = 0, c1 = -1;
         uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
         while (l >= n && ty < d.ty0 + d.h - 1) {  // row holding local slot l
@@ -821,8 +945,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
         for (int i = 0; i < EMIT_ITEMS_P; ++i) {
             const uint32_t o = s0 + (uint32_t)i;
             if (o >= oend || l >= n) break;  // (l >= n only if the counts disagree)
-            s_tk[o - o0] = (uint32_t)ty * (uint32_t)gx + (uint32_t)(c0 + (int)l);
-            s_tg[o - o0] = s_id[k];
+            s_tk[o - o0] = vt.tbase[v] + (uint32_t)ty * vt.gx[v] + (uint32_t)(c0 + (int)l);
+            s_tg[o - o0] = s_id[k] - (uint32_t)v * vt.P;
             if (++l < n) continue;
             l = 0;
             n = 0;
@@ -835,6 +959,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
             if (k >= m) break;
             q = pg[s_id[k]];
             d = dec_rect(s_rect[k]);
+            v = vt.view_of(s_id[k]);
+            W = vt.W[v];
+            H = vt.H[v];
             ty = d.ty0;
             n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
             while (n == 0 && ty < d.ty0 + d.h - 1) {
@@ -887,15 +1014,15 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
     }
 }
 
-// Workspace carve-up (every region 256-byte aligned).
+// Workspace carve-up (every region 256-byte aligned) for n = V * P
+// instances and room for `cap` splats.
 struct Layout {
     size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt_g, cnt, offs, pg, tkey0, tkey1, tid,
-        hist,
-        totals, nvis, part, win, total;
-    uint32_t nwin;
+        hist, totals, nvis, bounds, part, win, total;
+    uint32_t nwin, ncols_depth, ncols_tile;
 };
 
-Layout layout(uint32_t P, uint32_t cap, bool precise) {
+Layout layout(uint32_t nv, uint32_t P, uint32_t cap, bool precise) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -903,28 +1030,30 @@ Layout layout(uint32_t P, uint32_t cap, bool precise) {
         off = align_up(off + (bytes ? bytes : 4), 256);
         return o;
     };
-    uint32_t maxn = P > cap ? P : cap;
-    const uint32_t min_tile = SORT_THREADS * (DEPTH_ITEMS < TILE_ITEMS ? DEPTH_ITEMS : TILE_ITEMS);
-    uint32_t nblocks = (maxn + min_tile - 1) / min_tile + 1;
+    const size_t n = (size_t)nv * P;
+    L.ncols_depth = nv * ((P + SORT_THREADS * DEPTH_ITEMS - 1) / (SORT_THREADS * DEPTH_ITEMS));
+    L.ncols_tile = (cap + SORT_THREADS * TILE_ITEMS - 1) / (SORT_THREADS * TILE_ITEMS) + nv;
+    const uint32_t ncols = L.ncols_depth > L.ncols_tile ? L.ncols_depth : L.ncols_tile;
     const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
     L.nwin = (cap + win - 1) / win + 2;
-    L.dkey0 = take(4ull * P);
-    L.dkey1 = take(4ull * P);
-    L.did0 = take(4ull * P);
-    L.did1 = take(4ull * P);
-    L.rects = take(8ull * P);
-    L.rects_sorted = take(8ull * P);
-    L.cnt = take(4ull * P);
-    L.offs = take(4ull * P);
-    L.cnt_g = take(4ull * P);
-    L.pg = take(precise ? sizeof(PGauss) * (size_t)P : 0);
+    L.dkey0 = take(4 * n);
+    L.dkey1 = take(4 * n);
+    L.did0 = take(4 * n);
+    L.did1 = take(4 * n);
+    L.rects = take(8 * n);
+    L.rects_sorted = take(8 * n);
+    L.cnt = take(4 * n);
+    L.offs = take(4 * n);
+    L.cnt_g = take(4 * n);
+    L.pg = take(precise ? sizeof(PGauss) * n : 0);
     L.tkey0 = take(4ull * cap);
     L.tkey1 = take(4ull * cap);
     L.tid = take(4ull * cap);
-    L.hist = take(4ull * RADIX * nblocks);
-    L.totals = take(4ull * RADIX);
-    L.nvis = take(4);
-    L.part = take(8ull * ((P + SORT_TILE - 1) / SORT_TILE + 2));
+    L.hist = take(4ull * RADIX * ncols);
+    L.totals = take(4ull * RADIX * nv);
+    L.nvis = take(4ull * nv);
+    L.bounds = take(4ull * (nv + 1));
+    L.part = take(8 * ((n + SORT_TILE - 1) / SORT_TILE + 2));
     L.win = take(4ull * L.nwin);
     L.total = off;
     return L;
@@ -936,34 +1065,86 @@ int ceil_log2(uint32_t x) {
     return b;
 }
 
+// Per-view image sizes -> the view table, the total tile count and the
+// widest per-view tile index (bits); false for invalid sizes.
+bool make_views(int nv, uint32_t P, const int32_t *widths, const int32_t *heights, ViewTable &vt,
+                uint32_t &ntiles, int &tbits) {
+    if (nv < 1 || nv > GS_MAX_BIN_VIEWS || !widths || !heights) return false;
+    vt = ViewTable{};
+    vt.nv = nv;
+    vt.P = P;
+    uint64_t acc = 0;
+    tbits = 1;
+    for (int v = 0; v < nv; ++v) {
+        const int w = widths[v], h = heights[v];
+        if (w <= 0 || h <= 0 || w > GS_MAX_DIM || h > GS_MAX_DIM) return false;
+        const uint32_t gx = (uint32_t)gs::grid_x(w), nt = gx * (uint32_t)gs::grid_y(h);
+        vt.W[v] = w;
+        vt.H[v] = h;
+        vt.gx[v] = gx;
+        vt.tbase[v] = (uint32_t)acc;
+        acc += nt;
+        const int b = ceil_log2(nt);
+        if (b > tbits) tbits = b;
+    }
+    if (acc >= 0x40000000ull) return false;
+    ntiles = (uint32_t)acc;
+    return true;
+}
+
+// Splats of each view (bounds[v + 1] - bounds[v]).
+__global__ void k_view_splats(const uint32_t *__restrict__ bounds, int nv,
+                              uint32_t *__restrict__ out) {
+    const int v = threadIdx.x;
+    if (v < nv) out[v] = bounds ? bounds[v + 1] - bounds[v] : 0u;
+}
+
 }  // namespace
 
 extern "C" size_t gs_bin_sort_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
                                               int32_t height) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
     if (capacity >= 0x80000000u) return 0;
-    return layout((uint32_t)P, capacity, false).total;
+    return layout(1, (uint32_t)P, capacity, false).total;
 }
 
 extern "C" size_t gs_bin_sort_precise_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,
                                                       int32_t height) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM) return 0;
     if (capacity >= 0x80000000u) return 0;
-    return layout((uint32_t)P, capacity, true).total;
+    return layout(1, (uint32_t)P, capacity, true).total;
+}
+
+extern "C" size_t gs_bin_sort_multiview_workspace_bytes(int32_t nviews, int32_t P,
+                                                        uint32_t capacity, const int32_t *widths,
+                                                        const int32_t *heights, int32_t precise) {
+    ViewTable vt;
+    uint32_t ntiles;
+    int tbits;
+    if (P < 0 || capacity >= 0x80000000u) return 0;
+    if (!make_views(nviews, (uint32_t)P, widths, heights, vt, ntiles, tbits)) return 0;
+    if ((uint64_t)nviews * (uint64_t)P >= 0x80000000ull) return 0;
+    return layout((uint32_t)nviews, (uint32_t)P, capacity, precise != 0).total;
 }
 
 namespace {
 
-gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const float *depths,
-                   const float *conics, const float *opacities, bool precise, int32_t width,
-                   int32_t height, uint32_t capacity, void *workspace, size_t workspace_bytes,
-                   uint32_t *sorted_ids, uint32_t *tile_ranges, uint32_t *d_num_splats,
-                   void *stream) {
-    if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM)
+gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t *heights,
+                         const float *means2d, const int32_t *radii, const float *depths,
+                         const float *conics, const float *opacities, bool precise,
+                         uint32_t capacity, void *workspace, size_t workspace_bytes,
+                         uint32_t *sorted_ids, uint32_t *tile_ranges, uint32_t *d_num_splats,
+                         uint32_t *d_view_splats, void *stream) {
+    ViewTable vt;
+    uint32_t ntiles_u;
+    int tbits;
+    if (P < 0 || !make_views(nv, (uint32_t)P, widths, heights, vt, ntiles_u, tbits))
         return GS_ERR_INVALID_ARG;
+    if ((uint64_t)nv * (uint64_t)P >= 0x80000000ull) return GS_ERR_INVALID_ARG;
     if (!tile_ranges || !d_num_splats || !workspace || !gs::aligned(workspace, 256) ||
         !gs::aligned(tile_ranges, 4) || !gs::aligned(d_num_splats, 4))
         return GS_ERR_INVALID_ARG;
+    if (d_view_splats && !gs::aligned(d_view_splats, 4)) return GS_ERR_INVALID_ARG;
     if (P > 0 && (!means2d || !radii || !depths || !gs::aligned(means2d, 8) ||
                   !gs::aligned(radii, 4) || !gs::aligned(depths, 4)))
         return GS_ERR_INVALID_ARG;
@@ -972,65 +1153,74 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
         return GS_ERR_INVALID_ARG;
     if (capacity >= 0x80000000u) return GS_ERR_INVALID_ARG;
     if (capacity > 0 && (!sorted_ids || !gs::aligned(sorted_ids, 4))) return GS_ERR_INVALID_ARG;
-    Layout L = layout((uint32_t)P, capacity, precise);
+    Layout L = layout((uint32_t)nv, (uint32_t)P, capacity, precise);
     if (workspace_bytes < L.total) return GS_ERR_CAPACITY;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     auto U = [&](size_t o) { return (uint32_t *)(ws + o); };
     uint64_t *part = (uint64_t *)(ws + L.part);
     PGauss *pg = (PGauss *)(ws + L.pg);
-    int gx = gs::grid_x(width), gy = gs::grid_y(height);
-    int ntiles = gx * gy;
+    const int ntiles = (int)ntiles_u;
+    const int n = nv * P;  // instances
 
     if (P == 0) {
         hipLaunchKernelGGL(k_depth_keys<false>, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s,
                            0, (const float2 *)nullptr, (const int *)nullptr,
                            (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
-                           width, height, gx, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                           (uint2 *)nullptr, (uint32_t *)nullptr, (PGauss *)nullptr, tile_ranges,
-                           2 * ntiles);
+                           vt, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint2 *)nullptr,
+                           (uint32_t *)nullptr, (PGauss *)nullptr, tile_ranges, 2 * ntiles);
         // a kernel rather than a memset node, so the call can be graph-captured
         hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, s, d_num_splats, 0u);
+        if (d_view_splats)
+            hipLaunchKernelGGL(k_view_splats, dim3(1), dim3(GS_MAX_BIN_VIEWS), 0, s,
+                               (const uint32_t *)nullptr, nv, d_view_splats);
         return gs::launch_status();
     }
     const float2 *m2 = (const float2 *)means2d;
-    int nthr = P > 2 * ntiles ? P : 2 * ntiles;
-    // 1. depth keys, rectangles, cleared ranges; depth order of the Gaussians
+    int nthr = n > 2 * ntiles ? n : 2 * ntiles;
+    // 1. depth keys, rectangles, cleared ranges; depth order of each view's
+    // Gaussians
     if (precise)
-        hipLaunchKernelGGL(k_depth_keys<true>, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2,
-                           radii, depths, conics, opacities, width, height, gx, U(L.dkey0),
-                           U(L.did0), (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges,
-                           2 * ntiles);
+        hipLaunchKernelGGL(k_depth_keys<true>, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2,
+                           radii, depths, conics, opacities, vt, U(L.dkey0), U(L.did0),
+                           (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges, 2 * ntiles);
     else
-        hipLaunchKernelGGL(k_depth_keys<false>, dim3((nthr + 255) / 256), dim3(256), 0, s, P, m2,
-                           radii, depths, conics, opacities, width, height, gx, U(L.dkey0),
-                           U(L.did0), (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges,
-                           2 * ntiles);
+        hipLaunchKernelGGL(k_depth_keys<false>, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2,
+                           radii, depths, conics, opacities, vt, U(L.dkey0), U(L.did0),
+                           (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges, 2 * ntiles);
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
-    // Gaussians without splats (key DROP_KEY) leave in the first pass: the
-    // depth order holds the *n_vis Gaussians that have splats
+    // one segment of P per view; Gaussians without splats (key DROP_KEY)
+    // leave in the first pass: view v's depth order holds the n_vis[v]
+    // Gaussians that have splats
     uint32_t *n_vis = U(L.nvis);
-    int dcur = radix_sort<DEPTH_ITEMS>(db, Count{(uint32_t)P, nullptr, 0}, (uint32_t)P, 32,
-                                       U(L.hist), U(L.totals), n_vis, s);
+    SegTable sd{};
+    sd.nseg = nv;
+    sd.stride = (uint32_t)P;
+    sd.n_static = (uint32_t)P;
+    int dcur = radix_sort<DEPTH_ITEMS>(db, sd, L.ncols_depth, 32, U(L.hist), U(L.totals), n_vis, s);
     const uint32_t *order = db.v[dcur];
-    // 2. counts in depth order, scan (+ window owners), expansion
-    uint32_t sblocks = (P + SORT_TILE - 1) / SORT_TILE;
+    // 2. counts in depth order, scan (+ window owners, view bounds), expansion
+    uint32_t sblocks = (n + SORT_TILE - 1) / SORT_TILE;
     if (precise)
-        hipLaunchKernelGGL(k_counts<true>, dim3(sblocks), dim3(SORT_THREADS), 0, s, P, order,
+        hipLaunchKernelGGL(k_counts<true>, dim3(sblocks), dim3(SORT_THREADS), 0, s, n, order,
                            (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part);
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part,
+                           vt);
     else
-        hipLaunchKernelGGL(k_counts<false>, dim3(sblocks), dim3(SORT_THREADS), 0, s, P, order,
+        hipLaunchKernelGGL(k_counts<false>, dim3(sblocks), dim3(SORT_THREADS), 0, s, n, order,
                            (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part);
+                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part,
+                           vt);
     const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
     static_assert((EMIT_TILE & (EMIT_TILE - 1)) == 0 && (EMIT_TILE_P & (EMIT_TILE_P - 1)) == 0,
                   "windows are powers of two");
+    uint32_t *bounds = U(L.bounds);
     hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
-                       (uint32_t)P, (const uint64_t *)part, sblocks, U(L.win), L.nwin,
-                       ceil_log2(win), d_num_splats);
-    int tbits = ceil_log2((uint32_t)ntiles);
-    if (tbits == 0) tbits = 1;
+                       (uint32_t)n, (const uint64_t *)part, sblocks, U(L.win), L.nwin,
+                       ceil_log2(win), d_num_splats, bounds, nv, (uint32_t)P);
+    if (d_view_splats)
+        hipLaunchKernelGGL(k_view_splats, dim3(1), dim3(GS_MAX_BIN_VIEWS), 0, s,
+                           (const uint32_t *)bounds, nv, d_view_splats);
     int npass = radix_passes(tbits);
     // ids are emitted into the buffer that the last tile pass does NOT write,
     // so the sorted ids land in sorted_ids.
@@ -1040,20 +1230,29 @@ gs_status bin_sort(int32_t P, const float *means2d, const int32_t *radii, const 
     uint32_t eblocks = (capacity + win - 1) / win;
     if (eblocks > 0) {
         if (precise)
-            hipLaunchKernelGGL(k_emit_precise, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order,
+            hipLaunchKernelGGL(k_emit_precise, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
-                               U(L.win), L.nwin, gx, width, height, d_num_splats, capacity,
-                               U(L.tkey0), emit_ids);
+                               U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
+                               capacity, U(L.tkey0), emit_ids);
         else
-            hipLaunchKernelGGL(k_emit, dim3(eblocks), dim3(SORT_THREADS), 0, s, P, order, U(L.offs),
-                               (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, gx,
-                               d_num_splats, capacity, U(L.tkey0), emit_ids);
+            hipLaunchKernelGGL(k_emit, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
+                               (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
+                               (const uint32_t *)n_vis, d_num_splats, capacity, U(L.tkey0),
+                               emit_ids);
     }
-    // 3. stable sort by tile
+    // 3. stable sort of each view's splats by tile (digits of the tile index
+    // within the view)
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
+    SegTable st{};
+    st.nseg = nv;
+    st.bounds = bounds;
+    st.total = d_num_splats;
+    st.cap = capacity;
+    for (int v = 0; v < nv; ++v) st.kbase[v] = vt.tbase[v];
+    int tcur = radix_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, U(L.hist), U(L.totals), nullptr,
+                                      s);
+    // 4. ranges (tile indices are unique across views)
     Count nc{0u, d_num_splats, capacity};
-    int tcur = radix_sort<TILE_ITEMS>(tb, nc, capacity, tbits, U(L.hist), U(L.totals), nullptr, s);
-    // 4. ranges
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
     hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
                        tile_ranges);
@@ -1067,8 +1266,9 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
                                  uint32_t capacity, void *workspace, size_t workspace_bytes,
                                  uint32_t *sorted_ids, uint32_t *tile_ranges,
                                  uint32_t *d_num_splats, void *stream) {
-    return bin_sort(P, means2d, radii, depths, nullptr, nullptr, false, width, height, capacity,
-                    workspace, workspace_bytes, sorted_ids, tile_ranges, d_num_splats, stream);
+    return bin_sort_views(1, P, &width, &height, means2d, radii, depths, nullptr, nullptr, false,
+                          capacity, workspace, workspace_bytes, sorted_ids, tile_ranges,
+                          d_num_splats, nullptr, stream);
 }
 
 extern "C" gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const int32_t *radii,
@@ -1078,6 +1278,20 @@ extern "C" gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const 
                                          size_t workspace_bytes, uint32_t *sorted_ids,
                                          uint32_t *tile_ranges, uint32_t *d_num_splats,
                                          void *stream) {
-    return bin_sort(P, means2d, radii, depths, conics, opacities, true, width, height, capacity,
-                    workspace, workspace_bytes, sorted_ids, tile_ranges, d_num_splats, stream);
+    return bin_sort_views(1, P, &width, &height, means2d, radii, depths, conics, opacities, true,
+                          capacity, workspace, workspace_bytes, sorted_ids, tile_ranges,
+                          d_num_splats, nullptr, stream);
+}
+
+extern "C" gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths,
+                                           const int32_t *heights, const float *means2d,
+                                           const int32_t *radii, const float *depths,
+                                           const float *conics, const float *opacities,
+                                           int32_t precise, uint32_t capacity, void *workspace,
+                                           size_t workspace_bytes, uint32_t *sorted_ids,
+                                           uint32_t *tile_ranges, uint32_t *d_num_splats,
+                                           uint32_t *d_view_splats, void *stream) {
+    return bin_sort_views(nviews, P, widths, heights, means2d, radii, depths, conics, opacities,
+                          precise != 0, capacity, workspace, workspace_bytes, sorted_ids,
+                          tile_ranges, d_num_splats, d_view_splats, stream);
 }

@@ -133,6 +133,39 @@ def test_batched_and_precise_arguments_rejected_on_host(gslib):
                                      8, v(16), v(16), v(16), v(0)) == 4
 
 
+def test_multiview_bin_sort_arguments_rejected_on_host(gslib):
+    """gs_bin_sort_multiview checks views, sizes, pointers and workspace
+    before any GPU call."""
+    v = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    W = (i32 * 3)(64, 100, 32)
+    H = (i32 * 3)(48, 60, 32)
+    q = gslib.gs_bin_sort_multiview_workspace_bytes
+    assert q(3, 10, 100, W, H, 0) > 0
+    assert q(3, 10, 100, W, H, 1) > q(3, 10, 100, W, H, 0)   # ellipse records
+    assert q(0, 10, 100, W, H, 0) == 0 and q(65, 10, 100, W, H, 0) == 0
+    assert q(3, 10, 100, None, H, 0) == 0
+    assert q(3, -1, 100, W, H, 0) == 0 and q(3, 10, 0x80000000, W, H, 0) == 0
+    Wbad = (i32 * 3)(64, 0, 32)
+    assert q(3, 10, 100, Wbad, H, 0) == 0
+    f = gslib.gs_bin_sort_multiview
+    ok = (v(16), v(16), v(16), v(16), v(16))  # means2d radii depths conics opacities
+    assert f(0, 10, W, H, *ok, 0, 100, v(256), 1 << 20, v(16), v(16), v(16), v(16), v(0)) == 1
+    assert f(65, 10, W, H, *ok, 0, 100, v(256), 1 << 20, v(16), v(16), v(16), v(16), v(0)) == 1
+    assert f(3, 10, None, H, *ok, 0, 100, v(256), 1 << 20, v(16), v(16), v(16), v(16), v(0)) == 1
+    assert f(3, 10, Wbad, H, *ok, 0, 100, v(256), 1 << 20, v(16), v(16), v(16), v(16), v(0)) == 1
+    # null means, misaligned workspace, misaligned per-view counts
+    assert f(3, 10, W, H, v(0), v(16), v(16), v(16), v(16), 0, 100, v(256), 1 << 20, v(16), v(16),
+             v(16), v(16), v(0)) == 1
+    assert f(3, 10, W, H, *ok, 0, 100, v(260), 1 << 20, v(16), v(16), v(16), v(16), v(0)) == 1
+    assert f(3, 10, W, H, *ok, 0, 100, v(256), 1 << 20, v(16), v(16), v(16), v(18), v(0)) == 1
+    # precise needs conics and opacities
+    assert f(3, 10, W, H, v(16), v(16), v(16), v(0), v(16), 1, 100, v(256), 1 << 20, v(16), v(16),
+             v(16), v(16), v(0)) == 1
+    # workspace too small
+    assert f(3, 10, W, H, *ok, 0, 100, v(256), 8, v(16), v(16), v(16), v(16), v(0)) == 4
+
+
 def test_zero_gaussians_is_noop(gslib):
     v = ctypes.c_void_p
     assert gslib.gs_preprocess_2d(0, v(0), v(0), 64, 64, v(0), v(0), v(0), v(0)) == 0

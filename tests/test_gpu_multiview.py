@@ -59,6 +59,76 @@ def assert_same(a, b, what):
             assert np.array_equal(p, q), f"{what}: view {v} output {k} differs"
 
 
+@pytest.mark.parametrize("precise", [False, True])
+def test_bin_sort_multiview_matches_per_view_and_oracle(precise):
+    """One gs_bin_sort_multiview call builds, view after view, exactly the
+    lists gs_bin_sort(_precise) builds for each view alone (ids, ranges,
+    counts); the 3-sigma lists of two views equal the oracle's binning."""
+    say(f"multi-view bin/sort, precise={precise}")
+    sc, cams = small_case()
+    gcams = [gs_cam(c) for c in cams]
+    pre = gs.preprocess_multiview(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), gcams)
+    opac = dev(sc.opacities)
+    V, P = len(cams), sc.P
+    kw = lambda v: dict(conics=pre["conics"][v], opacities=opac, precise=True) if precise else {}
+    per = [gs.bin_sort(pre["means2d"][v], pre["radii"][v], pre["depths"][v], c.width, c.height,
+                       **kw(v)) for v, c in enumerate(cams)]
+    ns = [b.n_splats() for b in per]
+    mb = gs.MultiViewBinSorter(P, sum(ns) + 100, [(c.width, c.height) for c in cams],
+                               precise=precise)
+    mb(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], opac)
+    assert mb.n_splats() == sum(ns) and mb.view_counts() == ns
+    ids = host(mb.sorted_ids)
+    start = 0
+    for v in range(V):
+        r1 = host(per[v].ranges).astype(np.int64)
+        r2 = host(mb.ranges(v)).astype(np.int64)
+        full = r1[:, 1] > r1[:, 0]
+        assert np.array_equal(r1[full], r2[full] - start), f"view {v}: ranges differ"
+        assert np.all(r2[~full, 0] == r2[~full, 1]), f"view {v}: extra tiles"
+        assert np.array_equal(host(per[v].sorted_ids)[:ns[v]], ids[start:start + ns[v]]), v
+        start += ns[v]
+    if not precise:
+        for v in (0, V - 1):
+            W, H = cams[v].width, cams[v].height
+            r_o, i_o = oracle.bin_splats(host(pre["means2d"][v]), host(pre["radii"][v]),
+                                         host(pre["depths"][v]), W, H)
+            r2 = host(mb.ranges(v)).astype(np.int64)
+            base = sum(ns[:v])
+            full = r_o[:, 1] > r_o[:, 0]
+            assert np.array_equal(r_o[full].astype(np.int64), r2[full] - base), v
+            assert np.array_equal(i_o, ids[base:base + ns[v]].astype(np.uint32)), v
+    # overflow: nothing is built, the counts are still reported
+    small = gs.MultiViewBinSorter(P, sum(ns) - 1, [(c.width, c.height) for c in cams],
+                                  precise=precise)
+    small(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], opac)
+    assert small.n_splats() == sum(ns) and small.view_counts() == ns
+    rg = host(small.all_ranges)
+    assert np.all(rg[:, 0] == rg[:, 1])
+
+
+def test_bin_sort_multiview_no_gaussians():
+    sizes = [(64, 48), (100, 60)]
+    mb = gs.MultiViewBinSorter(0, 16, sizes)
+    z2 = torch.zeros(2, 0, 2, dtype=torch.float32, device="cuda")
+    mb(z2, torch.zeros(2, 0, dtype=torch.int32, device="cuda"),
+       torch.zeros(2, 0, dtype=torch.float32, device="cuda"))
+    assert mb.n_splats() == 0 and mb.view_counts() == [0, 0]
+    assert int(host(mb.all_ranges).max()) == 0
+
+
+def test_joint_and_per_view_binning_render_the_same():
+    sc, cams = small_case()
+    t = scene_tensors(sc)
+    a = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams], joint_bin=True)
+    b = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams], joint_bin=False)
+    a.frame()
+    b.frame()
+    torch.cuda.synchronize()
+    assert a.n_splats() == b.n_splats()
+    assert_same(snapshot(a), snapshot(b), "joint vs per-view binning")
+
+
 def test_preprocess_multiview_matches_single_and_oracle():
     sc, cams = small_case(n_views=5, P=20000)
     t = scene_tensors(sc)
@@ -121,11 +191,11 @@ def test_batched_small_vs_single_and_oracle(prec):
         m2 = host(mv.pre["means2d"][v])
         rad, dep = host(mv.pre["radii"][v]), host(mv.pre["depths"][v])
         r_o, i_o = oracle.bin_splats(m2, rad, dep, W, H)
-        bs = mv.sorters[v]
-        n = bs.n_splats()
-        assert n == len(i_o)
-        assert np.array_equal(host(bs.ranges).astype(np.int64), r_o.astype(np.int64))
-        assert np.array_equal(host(bs.sorted_ids)[:n].astype(np.uint32), i_o)
+        rg, ids = mv.view_lists(v)
+        n = len(ids)
+        assert n == len(i_o) == mv.n_splats()[v]
+        assert np.array_equal(rg, r_o.astype(np.int64))
+        assert np.array_equal(ids.astype(np.uint32), i_o)
         ref = oracle.render(W, H, r_o, i_o, m2, host(mv.pre["conics"][v]).astype(np.float64),
                             sc.opacities, host(mv.pre["rgb"][v]))
         q = quality(batched[v][0], ref["rgb"])
@@ -239,9 +309,7 @@ def test_multiview_fullsize_sampled():
         assert np.mean(same) > 0.999
         vis = same & (o["radii"] > 0)
         np.testing.assert_allclose(m2[sel][vis], o["means2d"][vis], rtol=1e-5, atol=2e-3)
-        bs = mv.sorters[v]
-        ranges_g = host(bs.ranges).astype(np.int64)
-        ids_g = host(bs.sorted_ids)
+        ranges_g, ids_g = mv.view_lists(v)
         tiles = sample_tiles(ranges_g, gx, gy, n_random=5, n_heavy=2, seed=v)
         r_o, i_o = oracle.bin_tiles(m2, rad, dep, W, H, tiles)
         for j, t in enumerate(tiles):
