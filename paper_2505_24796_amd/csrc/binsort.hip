@@ -118,13 +118,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
         seg_bounds[nv] = Nsat;
     }
     size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
+    static_assert(SORT_ITEMS % 4 == 0, "16-byte loads");
     uint32_t v[SORT_ITEMS];
     uint64_t s = 0;
+    if (base + SORT_ITEMS <= n) {  // (cnt is 256-byte aligned, base a multiple of 16)
 #pragma unroll
-    for (int k = 0; k < SORT_ITEMS; ++k) {
-        v[k] = base + k < n ? cnt[base + k] : 0u;
-        s += v[k];
+        for (int k = 0; k < SORT_ITEMS; k += 4) {
+            const uint4 q = *(const uint4 *)(cnt + base + k);
+            v[k] = q.x;
+            v[k + 1] = q.y;
+            v[k + 2] = q.z;
+            v[k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS; ++k) v[k] = base + k < n ? cnt[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) s += v[k];
     uint64_t ex;
     block_excl_scan<uint64_t>(s, ex, lds);
     uint64_t run = pre + ex;
@@ -170,7 +181,12 @@ constexpr int MAX_SEGS = GS_MAX_BIN_VIEWS;
 // stride and n_s = n_dev[s] (or n_static), or base_s = bounds[s] and n_s =
 // bounds[s + 1] - bounds[s].  With `total`, every segment is empty when
 // *total > cap (an overflowing frame).  The digit of a key in segment s is
-// taken from key - kbase[s].
+// taken from key - kv[s].tbase (key itself without kv).
+struct ViewDims {
+    int W, H;
+    uint32_t gx, tbase;
+};
+
 struct SegTable {
     int nseg;
     uint32_t stride, n_static;
@@ -178,17 +194,22 @@ struct SegTable {
     const uint32_t *bounds;
     const uint32_t *total;
     uint32_t cap;
-    uint32_t kbase[MAX_SEGS];
+    const ViewDims *kv;
+    __device__ __forceinline__ uint32_t key_base(int sg) const { return kv ? kv[sg].tbase : 0u; }
     __device__ __forceinline__ void get(int sg, uint32_t &base, uint32_t &n) const {
-        if (total && *total > cap) {
+        // independent loads (the pointers are uniform), then the selection
+        uint32_t b0 = 0u, b1 = 0u, nd = n_static, tot = 0u;
+        if (bounds) {
+            b0 = bounds[sg];
+            b1 = bounds[sg + 1];
+        }
+        if (n_dev) nd = n_dev[sg];
+        if (total) tot = *total;
+        base = bounds ? b0 : (uint32_t)sg * stride;
+        n = bounds ? b1 - b0 : nd;
+        if (total && tot > cap) {
             base = 0u;
             n = 0u;
-        } else if (bounds) {
-            base = bounds[sg];
-            n = bounds[sg + 1] - base;
-        } else {
-            base = (uint32_t)sg * stride;
-            n = n_dev ? n_dev[sg] : n_static;
         }
     }
 };
@@ -225,7 +246,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     if (!seg_block<TILE>(st, blockIdx.x, sg, lb, base, n, col0)) return;  // idle: uniform exit
     if (threadIdx.x < NDIG) h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t kb = st.kbase[sg];
+    const uint32_t kb = st.key_base(sg);
     const size_t b0 = (size_t)lb * TILE;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -287,7 +308,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     int sg;
     uint32_t lb, sbase, n, col0;
     if (!seg_block<TILE>(st, blockIdx.x, sg, lb, sbase, n, col0)) return;  // idle: uniform exit
-    const uint32_t kb = st.kbase[sg];
+    const uint32_t kb = st.key_base(sg);
     const size_t base = (size_t)lb * TILE;  // within the segment
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < NDIG) {
@@ -452,14 +473,36 @@ int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist
 // Views of one bin/sort call: instance i of its V * P (Gaussian, view)
 // pairs is Gaussian i % P seen from view i / P (the per-view arrays are
 // view-major).  View v's tiles are numbered tbase[v] + ty * gx[v] + tx in
-// the call's tile ranges.
+// the call's tile ranges.  ViewTable is the host-side description; kernels
+// take a ViewRef, which holds view 0 inline (a one-view call reads nothing)
+// and otherwise points at a ViewDims table the call writes to its workspace
+// (small kernel arguments keep the launches of the chain cheap).
 struct ViewTable {
     int nv;
     uint32_t P;
     int W[MAX_SEGS], H[MAX_SEGS];
     uint32_t gx[MAX_SEGS], tbase[MAX_SEGS];
-    __device__ __forceinline__ int view_of(uint32_t i) const { return nv == 1 ? 0 : (int)(i / P); }
 };
+
+struct ViewRef {
+    int nv;
+    uint32_t P;
+    int W0, H0;
+    uint32_t gx0;
+    const ViewDims *vd;
+    // M: a multi-view call (kernels are instantiated for both, so a
+    // one-view call does no division and reads no table)
+    template <bool M> __device__ __forceinline__ int view_of(uint32_t i) const { return M ? (int)(i / P) : 0; }
+    template <bool M> __device__ __forceinline__ int W(int v) const { return M ? vd[v].W : W0; }
+    template <bool M> __device__ __forceinline__ int H(int v) const { return M ? vd[v].H : H0; }
+    template <bool M> __device__ __forceinline__ uint32_t gx(int v) const { return M ? vd[v].gx : gx0; }
+    template <bool M> __device__ __forceinline__ uint32_t tbase(int v) const { return M ? vd[v].tbase : 0u; }
+};
+
+__global__ void k_put_views(ViewTable vt, ViewDims *__restrict__ out) {
+    const int v = threadIdx.x;
+    if (v < vt.nv) out[v] = ViewDims{vt.W[v], vt.H[v], vt.gx[v], vt.tbase[v]};
+}
 
 // ---------------------------------------------------------------------------
 // Stage kernels
@@ -579,12 +622,12 @@ __device__ __forceinline__ RectDec dec_rect(uint2 r) {
 // and the ellipse parameters are kept for the emission); also clears the
 // tile ranges.  A Gaussian without splats gets the largest key, so it sorts
 // after every Gaussian that has splats.
-template <bool PRECISE>
+template <bool PRECISE, bool MULTI>
 __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restrict__ means2d,
                                                     const int *__restrict__ radii,
                                                     const float *__restrict__ depths,
                                                     const float *__restrict__ conics,
-                                                    const float *__restrict__ opac, ViewTable vt,
+                                                    const float *__restrict__ opac, ViewRef vt,
                                                     uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
                                                     uint2 *__restrict__ rects,
@@ -597,15 +640,15 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
     // lanes past P stay, as Gaussians without tiles)
     if (!PRECISE && i >= P) return;
     const bool live = i < P;
-    const int view = live ? vt.view_of((uint32_t)i) : 0;
-    const int W = vt.W[view], H = vt.H[view];
+    const int view = live ? vt.view_of<MULTI>((uint32_t)i) : 0;
+    const int W = vt.W<MULTI>(view), H = vt.H<MULTI>(view);
     float d = live ? depths[i] : 0.0f;
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
     int n = 0;
     float2 m = make_float2(0.f, 0.f);
     if (live && isfinite(d)) {
         m = means2d[i];
-        n = gs::tile_rect(m.x, m.y, radii[i], W, H, (int)vt.gx[view], tx0, tx1, ty0, ty1);
+        n = gs::tile_rect(m.x, m.y, radii[i], W, H, (int)vt.gx<MULTI>(view), tx0, tx1, ty0, ty1);
     }
     uint32_t c = (uint32_t)n;
     if (PRECISE) {
@@ -677,25 +720,26 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
 // Rectangle and splat count of each instance in depth order (view by view;
 // zero past the n_vis[v] instances of view v that have splats), and each
 // block's sum of counts.
-template <bool PRECISE>
+template <bool PRECISE, bool MULTI>
 __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *__restrict__ order,
                                                          const uint2 *__restrict__ rects,
                                                          const uint32_t *__restrict__ cnt_g,
                                                          uint2 *__restrict__ rects_sorted,
                                                          uint32_t *__restrict__ cnt,
                                                          const uint32_t *__restrict__ n_vis,
-                                                         uint64_t *__restrict__ part, ViewTable vt) {
+                                                         uint64_t *__restrict__ part, ViewRef vt) {
     __shared__ uint64_t lds[WAVES];
     const size_t base = (size_t)blockIdx.x * SORT_TILE;
     uint64_t sum = 0;
+    const uint32_t nvis0 = n_vis[0];
 #pragma unroll 4
     for (int k = 0; k < SORT_ITEMS; ++k) {
         const size_t j = base + (size_t)k * SORT_THREADS + threadIdx.x;
         if (j < (size_t)P) {
             uint2 r = make_uint2(0u, 0u);  // past the Gaussians that have splats
             uint32_t c = 0u;
-            const int v = vt.view_of((uint32_t)j);
-            if (j - (size_t)v * vt.P < n_vis[v]) {
+            const int v = vt.view_of<MULTI>((uint32_t)j);
+            if (j - (size_t)v * vt.P < (MULTI ? n_vis[v] : nvis0)) {
                 const uint32_t g = order[j];
                 r = rects[g];
                 c = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
@@ -718,13 +762,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
 // [v P + n_vis[v], (v + 1) P)) are skipped.  So at most WIN + 1 are staged.
 // Returns their number m, or 0 when the window is idle (overflow, past N).
 // All threads of the block call it.
-template <int WIN, int NT>
+template <int WIN, int NT, bool MULTI>
 __device__ __forceinline__ uint32_t stage_window(int P, const uint32_t *__restrict__ order,
                                                  const uint32_t *__restrict__ offs,
                                                  const uint2 *__restrict__ rects_sorted,
                                                  const uint32_t *__restrict__ win_start,
                                                  uint32_t nwin, uint32_t N, uint32_t cap,
-                                                 const ViewTable &vt,
+                                                 const ViewRef &vt,
                                                  const uint32_t *__restrict__ n_vis,
                                                  uint32_t *s_off, uint2 *s_rect, uint32_t *s_id) {
     const uint32_t o0 = blockIdx.x * (uint32_t)WIN;
@@ -732,7 +776,16 @@ __device__ __forceinline__ uint32_t stage_window(int P, const uint32_t *__restri
     const uint32_t j0 = win_start[blockIdx.x];
     const uint32_t j1 = win_start[blockIdx.x + 1];
     if (j0 >= (uint32_t)P || j1 >= (uint32_t)P || j1 < j0) return 0u;  // cannot happen when the scan ran
-    const int v0 = vt.view_of(j0), v1 = vt.view_of(j1);
+    if (!MULTI) {  // one view: every instance in [j0, j1] owns a slot
+        const uint32_t m = min(j1 - j0 + 1u, (uint32_t)WIN + 1u);
+        for (uint32_t k = threadIdx.x; k < m; k += NT) {
+            s_off[k] = offs[j0 + k];
+            s_rect[k] = rects_sorted[j0 + k];
+            s_id[k] = order[j0 + k];
+        }
+        return m;
+    }
+    const int v0 = vt.view_of<MULTI>(j0), v1 = vt.view_of<MULTI>(j1);
     uint32_t m = 0;
     for (int v = v0; v <= v1 && m < (uint32_t)WIN + 1u; ++v) {
         // view v's instances with splats that lie in [j0, j1]
@@ -763,24 +816,25 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t *a, uint32_t n, uint3
 
 // Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
 // slots) under the 3-sigma rule: each thread locates the owner of its first
-// of EMIT_ITEMS consecutive slots by binary search and walks the rectangles
-// in row-major order; results are staged in LDS and written out coalesced.
+// of EMIT_ITEMS consecutive slots by binary search, walks the rectangles in
+// row-major order and writes its slots with two 16-byte stores per array
+// (consecutive threads, consecutive 32-byte pieces).
+template <bool MULTI>
 __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ offs,
                                                        const uint2 *__restrict__ rects_sorted,
                                                        const uint32_t *__restrict__ win_start,
-                                                       uint32_t nwin, ViewTable vt,
+                                                       uint32_t nwin, ViewRef vt,
                                                        const uint32_t *__restrict__ n_vis,
                                                        const uint32_t *__restrict__ n_splats,
                                                        uint32_t cap, uint32_t *__restrict__ tkey,
                                                        uint32_t *__restrict__ tid) {
+    static_assert(EMIT_ITEMS == 8, "two 16-byte stores per thread and array");
     __shared__ uint32_t s_off[EMIT_TILE + 1];
     __shared__ uint2 s_rect[EMIT_TILE + 1];
     __shared__ uint32_t s_id[EMIT_TILE + 1];
-    __shared__ uint32_t s_tk[EMIT_TILE];
-    __shared__ uint32_t s_tg[EMIT_TILE];
     const uint32_t N = *n_splats;
-    const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS>(P, order, offs, rects_sorted, win_start,
+    const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
                                                              nwin, N, cap, vt, n_vis, s_off,
                                                              s_rect, s_id);
     if (m == 0) return;  // block-uniform
@@ -788,21 +842,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
     const uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
     const uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
     const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
-    if (s0 < oend) {
+    if (s0 >= oend) return;
+    // this thread's EMIT_ITEMS consecutive slots, written from registers
+    uint32_t tk[EMIT_ITEMS], tg[EMIT_ITEMS];
+    {
         uint32_t k = last_le(s_off, m, s0);
         const uint32_t l = s0 - s_off[k];
         uint2 r = s_rect[k];
         uint32_t w = max(r.y & 0xFFFFu, 1u), h = max(r.y >> 16, 1u);
         uint32_t row = l / w, col = l - row * w;
         // the Gaussian's view: its tile numbering and its id within the view
-        int v = vt.view_of(s_id[k]);
+        int v = vt.view_of<MULTI>(s_id[k]);
         uint32_t gid = s_id[k] - (uint32_t)v * vt.P;
+#pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) {
-            const uint32_t o = s0 + (uint32_t)i;
-            if (o >= oend) break;
             const uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
-            s_tk[o - o0] = vt.tbase[v] + ty * vt.gx[v] + tx;
-            s_tg[o - o0] = gid;
+            tk[i] = vt.tbase<MULTI>(v) + ty * vt.gx<MULTI>(v) + tx;
+            tg[i] = gid;
             if (++col == w) {
                 col = 0;
                 if (++row == h && k + 1 < m) {
@@ -811,16 +867,27 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
                     r = s_rect[k];
                     w = max(r.y & 0xFFFFu, 1u);
                     h = max(r.y >> 16, 1u);
-                    v = vt.view_of(s_id[k]);
+                    v = vt.view_of<MULTI>(s_id[k]);
                     gid = s_id[k] - (uint32_t)v * vt.P;
                 }
             }
         }
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < oend - o0; i += SORT_THREADS) {
-        tkey[o0 + i] = s_tk[i];
-        tid[o0 + i] = s_tg[i];
+    const bool vec = s0 + EMIT_ITEMS <= oend && gs::aligned(tkey + s0, 16) && gs::aligned(tid + s0, 16);
+    if (vec) {
+        uint4 *dk = (uint4 *)(tkey + s0), *di = (uint4 *)(tid + s0);
+        dk[0] = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+        dk[1] = make_uint4(tk[4], tk[5], tk[6], tk[7]);
+        di[0] = make_uint4(tg[0], tg[1], tg[2], tg[3]);
+        di[1] = make_uint4(tg[4], tg[5], tg[6], tg[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i) {
+            if (s0 + (uint32_t)i < oend) {
+                tkey[s0 + i] = tk[i];
+                tid[s0 + i] = tg[i];
+            }
+        }
     }
 }
 
@@ -850,10 +917,11 @@ __device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t n, ui
 // thread then finds the run holding its first slot by binary search and
 // writes its EMIT_ITEMS_P tiles directly.  A window with more than RCAP
 // pairs (several very tall Gaussians) walks the rows per thread instead.
+template <bool MULTI>
 __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
     int P, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offs,
     const uint2 *__restrict__ rects_sorted, const PGauss *__restrict__ pg,
-    const uint32_t *__restrict__ win_start, uint32_t nwin, ViewTable vt,
+    const uint32_t *__restrict__ win_start, uint32_t nwin, ViewRef vt,
     const uint32_t *__restrict__ n_vis, const uint32_t *__restrict__ n_splats, uint32_t cap,
     uint32_t *__restrict__ tkey,
     uint32_t *__restrict__ tid) {
@@ -868,7 +936,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
     __shared__ uint32_t s_tg[WIN];
     __shared__ uint32_t s_scan[WAVES];
     const uint32_t N = *n_splats;
-    const uint32_t m = stage_window<WIN, SORT_THREADS>(P, order, offs, rects_sorted, win_start,
+    const uint32_t m = stage_window<WIN, SORT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
                                                        nwin, N, cap, vt, n_vis, s_off, s_rect,
                                                        s_id);
     if (m == 0) return;  // block-uniform
@@ -891,9 +959,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
             const RectDec d = dec_rect(s_rect[k]);
             const int ty = d.ty0 + (int)(p - s_hoff[k]);
             const PGauss q = pg[s_id[k]];
-            const int v = vt.view_of(s_id[k]);
+            const int v = vt.view_of<MULTI>(s_id[k]);
             int c0 = 0, c1 = -1;
-            const uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, vt.W[v], vt.H[v], c0, c1);
+            const uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, vt.W<MULTI>(v), vt.H<MULTI>(v), c0, c1);
             s_pk[p] = (uint16_t)k;
             s_pty[p] = (uint16_t)ty;
             s_pc0[p] = (uint16_t)c0;
@@ -916,8 +984,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
                 const uint32_t o = s0 + (uint32_t)i;
                 if (o >= oend || within >= s_pn[p]) break;
                 const uint32_t g = s_id[s_pk[p]];
-                const int v = vt.view_of(g);
-                s_tk[o - o0] = vt.tbase[v] + (uint32_t)s_pty[p] * vt.gx[v] + s_pc0[p] + within;
+                const int v = vt.view_of<MULTI>(g);
+                s_tk[o - o0] = vt.tbase<MULTI>(v) + (uint32_t)s_pty[p] * vt.gx<MULTI>(v) + s_pc0[p] + within;
                 s_tg[o - o0] = g - (uint32_t)v * vt.P;
                 if (++within < s_pn[p]) continue;
                 within = 0;
@@ -933,8 +1001,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
         uint32_t l = s0 - s_off[k];
         PGauss q = pg[s_id[k]];
         RectDec d = dec_rect(s_rect[k]);
-        int v = vt.view_of(s_id[k]);
-        int W = vt.W[v], H = vt.H[v];
+        int v = vt.view_of<MULTI>(s_id[k]);
+        int W = vt.W<MULTI>(v), H = vt.H<MULTI>(v);
         int ty = d.ty0, c0 = 0, c1 = -1;
         uint32_t n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
         while (l >= n && ty < d.ty0 + d.h - 1) {  // row holding local slot l
@@ -945,7 +1013,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
         for (int i = 0; i < EMIT_ITEMS_P; ++i) {
             const uint32_t o = s0 + (uint32_t)i;
             if (o >= oend || l >= n) break;  // (l >= n only if the counts disagree)
-            s_tk[o - o0] = vt.tbase[v] + (uint32_t)ty * vt.gx[v] + (uint32_t)(c0 + (int)l);
+            s_tk[o - o0] = vt.tbase<MULTI>(v) + (uint32_t)ty * vt.gx<MULTI>(v) + (uint32_t)(c0 + (int)l);
             s_tg[o - o0] = s_id[k] - (uint32_t)v * vt.P;
             if (++l < n) continue;
             l = 0;
@@ -959,9 +1027,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
             if (k >= m) break;
             q = pg[s_id[k]];
             d = dec_rect(s_rect[k]);
-            v = vt.view_of(s_id[k]);
-            W = vt.W[v];
-            H = vt.H[v];
+            v = vt.view_of<MULTI>(s_id[k]);
+            W = vt.W<MULTI>(v);
+            H = vt.H<MULTI>(v);
             ty = d.ty0;
             n = row_span(q, ty, d.tx0, d.tx0 + d.w - 1, W, H, c0, c1);
             while (n == 0 && ty < d.ty0 + d.h - 1) {
@@ -1018,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
 // instances and room for `cap` splats.
 struct Layout {
     size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt_g, cnt, offs, pg, tkey0, tkey1, tid,
-        hist, totals, nvis, bounds, part, win, total;
+        hist, totals, nvis, bounds, vdims, part, win, total;
     uint32_t nwin, ncols_depth, ncols_tile;
 };
 
@@ -1053,6 +1121,7 @@ Layout layout(uint32_t nv, uint32_t P, uint32_t cap, bool precise) {
     L.totals = take(4ull * RADIX * nv);
     L.nvis = take(4ull * nv);
     L.bounds = take(4ull * (nv + 1));
+    L.vdims = take(sizeof(ViewDims) * nv);
     L.part = take(8 * ((n + SORT_TILE - 1) / SORT_TILE + 2));
     L.win = take(4ull * L.nwin);
     L.total = off;
@@ -1135,10 +1204,10 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
                          uint32_t capacity, void *workspace, size_t workspace_bytes,
                          uint32_t *sorted_ids, uint32_t *tile_ranges, uint32_t *d_num_splats,
                          uint32_t *d_view_splats, void *stream) {
-    ViewTable vt;
+    ViewTable vtab;
     uint32_t ntiles_u;
     int tbits;
-    if (P < 0 || !make_views(nv, (uint32_t)P, widths, heights, vt, ntiles_u, tbits))
+    if (P < 0 || !make_views(nv, (uint32_t)P, widths, heights, vtab, ntiles_u, tbits))
         return GS_ERR_INVALID_ARG;
     if ((uint64_t)nv * (uint64_t)P >= 0x80000000ull) return GS_ERR_INVALID_ARG;
     if (!tile_ranges || !d_num_splats || !workspace || !gs::aligned(workspace, 256) ||
@@ -1162,9 +1231,12 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     PGauss *pg = (PGauss *)(ws + L.pg);
     const int ntiles = (int)ntiles_u;
     const int n = nv * P;  // instances
+    ViewDims *vdims = (ViewDims *)(ws + L.vdims);
+    const ViewRef vt{nv, (uint32_t)P, vtab.W[0], vtab.H[0], vtab.gx[0], vdims};
+    if (nv > 1) hipLaunchKernelGGL(k_put_views, dim3(1), dim3(GS_MAX_BIN_VIEWS), 0, s, vtab, vdims);
 
     if (P == 0) {
-        hipLaunchKernelGGL(k_depth_keys<false>, dim3((2 * ntiles + 255) / 256), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_depth_keys<false, false>), dim3((2 * ntiles + 255) / 256), dim3(256), 0, s,
                            0, (const float2 *)nullptr, (const int *)nullptr,
                            (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
                            vt, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint2 *)nullptr,
@@ -1180,14 +1252,13 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     int nthr = n > 2 * ntiles ? n : 2 * ntiles;
     // 1. depth keys, rectangles, cleared ranges; depth order of each view's
     // Gaussians
-    if (precise)
-        hipLaunchKernelGGL(k_depth_keys<true>, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2,
-                           radii, depths, conics, opacities, vt, U(L.dkey0), U(L.did0),
-                           (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges, 2 * ntiles);
-    else
-        hipLaunchKernelGGL(k_depth_keys<false>, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2,
-                           radii, depths, conics, opacities, vt, U(L.dkey0), U(L.did0),
-                           (uint2 *)(ws + L.rects), U(L.cnt_g), pg, tile_ranges, 2 * ntiles);
+    {
+        auto kk = precise ? (nv > 1 ? k_depth_keys<true, true> : k_depth_keys<true, false>)
+                          : (nv > 1 ? k_depth_keys<false, true> : k_depth_keys<false, false>);
+        hipLaunchKernelGGL(kk, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2, radii, depths,
+                           conics, opacities, vt, U(L.dkey0), U(L.did0), (uint2 *)(ws + L.rects),
+                           U(L.cnt_g), pg, tile_ranges, 2 * ntiles);
+    }
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
     // one segment of P per view; Gaussians without splats (key DROP_KEY)
     // leave in the first pass: view v's depth order holds the n_vis[v]
@@ -1201,16 +1272,14 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     const uint32_t *order = db.v[dcur];
     // 2. counts in depth order, scan (+ window owners, view bounds), expansion
     uint32_t sblocks = (n + SORT_TILE - 1) / SORT_TILE;
-    if (precise)
-        hipLaunchKernelGGL(k_counts<true>, dim3(sblocks), dim3(SORT_THREADS), 0, s, n, order,
+    {
+        auto kc = precise ? (nv > 1 ? k_counts<true, true> : k_counts<true, false>)
+                          : (nv > 1 ? k_counts<false, true> : k_counts<false, false>);
+        hipLaunchKernelGGL(kc, dim3(sblocks), dim3(SORT_THREADS), 0, s, n, order,
                            (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
                            (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part,
                            vt);
-    else
-        hipLaunchKernelGGL(k_counts<false>, dim3(sblocks), dim3(SORT_THREADS), 0, s, n, order,
-                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
-                           (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part,
-                           vt);
+    }
     const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
     static_assert((EMIT_TILE & (EMIT_TILE - 1)) == 0 && (EMIT_TILE_P & (EMIT_TILE_P - 1)) == 0,
                   "windows are powers of two");
@@ -1230,12 +1299,12 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     uint32_t eblocks = (capacity + win - 1) / win;
     if (eblocks > 0) {
         if (precise)
-            hipLaunchKernelGGL(k_emit_precise, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order,
+            hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
                                U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
                                capacity, U(L.tkey0), emit_ids);
         else
-            hipLaunchKernelGGL(k_emit, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
+            hipLaunchKernelGGL(nv > 1 ? k_emit<true> : k_emit<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
                                (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
                                (const uint32_t *)n_vis, d_num_splats, capacity, U(L.tkey0),
                                emit_ids);
@@ -1248,7 +1317,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     st.bounds = bounds;
     st.total = d_num_splats;
     st.cap = capacity;
-    for (int v = 0; v < nv; ++v) st.kbase[v] = vt.tbase[v];
+    st.kv = nv > 1 ? vdims : nullptr;
     int tcur = radix_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, U(L.hist), U(L.totals), nullptr,
                                       s);
     // 4. ranges (tile indices are unique across views)

@@ -15,7 +15,7 @@
 
 namespace gs {
 
-inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+__host__ __device__ inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 inline int grid_x(int W) { return (W + GS_TILE - 1) / GS_TILE; }
 inline int grid_y(int H) { return (H + GS_TILE - 1) / GS_TILE; }
