@@ -290,7 +290,12 @@ def multiview(args):
         return np.median(np.array(rows), axis=0)
 
     st = stage_times_of(mv)
-    # the same lists with one gs_bin_sort call per view (four streams, then one)
+    # the same lists with one gs_bin_sort_multiview call for all views
+    mvj = gs.MultiViewRenderer(scene, cams, precision=args.precision, joint_bin=True)
+    mvj.preprocess()
+    joint_bin = float(np.median(autotune.time_ms(mvj.bin_sort, reps=5, warmup=1)))
+    del mvj
+    # the per-view calls on four streams, then on one
     pv_bin = float(np.median(autotune.time_ms(lambda: mv.bin_sort_per_view(concurrent=True),
                                               reps=5, warmup=1)))
     seq_bin = float(np.median(autotune.time_ms(lambda: mv.bin_sort_per_view(concurrent=False),
@@ -385,8 +390,9 @@ def multiview(args):
             "eager_ms_per_frame": eager,
             "stages_ms": {"preprocess_multiview": st[0], "bin_sort_all_views": st[1],
                           "raster_batched": st[2]},
-            "bin_sort": "one gs_bin_sort_multiview call" if mv.joint else "per view",
+            "bin_sort": f"one gs_bin_sort per view on {mv.K} streams",
             "bin_sort_per_view_calls_ms": {f"{mv.K}_streams": pv_bin, "1_stream": seq_bin},
+            "bin_sort_joint_call_ms": joint_bin,
             "raster_one_launch_per_view_ms": per_view_raster,
             "preprocess_one_call_per_view_ms": single_pre,
             "precise_binning": precise,

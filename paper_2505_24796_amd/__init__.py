@@ -477,11 +477,11 @@ def wall_clock_khz() -> int:
 
 class MultiViewRenderer:
     """Renders one scene to several cameras per frame: one multi-view
-    preprocess, one bin/sort call for every view (gs_bin_sort_multiview;
-    with ``joint_bin=False``, or more than GS_MAX_BIN_VIEWS views, one
-    gs_bin_sort per view, ``bin_streams`` views at a time on as many
-    streams), and ONE persistent batched rasteriser launch over every
-    (view, tile) pair.
+    preprocess, the views' bin/sort (one gs_bin_sort per view,
+    ``bin_streams`` views at a time on as many streams; or, with
+    ``joint_bin``, gs_bin_sort_multiview over ``bin_groups`` groups of
+    views, one stream each), and ONE persistent batched rasteriser launch
+    over every (view, tile) pair.
     Buffers are sized once (splat capacity per view from a probe frame times
     ``slack``); a frame allocates nothing, so it can be captured in a
     hipGraph (:meth:`capture`).  Per-view latency inside a frame comes from
@@ -489,7 +489,7 @@ class MultiViewRenderer:
 
     def __init__(self, scene: dict, cams, precision="fp16_g2l_split", slack=1.15,
                  background=(0.0, 0.0, 0.0), sh_degree=3, precise=False, bin_streams=4,
-                 joint_bin=True):
+                 joint_bin=False, bin_groups=1):
         self.scene = {k: _dev(scene[k], torch.float32, k)
                       for k in ("means3d", "scales", "quats", "sh", "opacities")}
         self.cams = list(cams)
@@ -524,8 +524,14 @@ class MultiViewRenderer:
         self.probe_counts = counts
         self.capacity = [int(n * slack) + 1024 for n in counts]
         if self.joint:
-            self.mvbin = MultiViewBinSorter(self.P, sum(self.capacity), sizes, device=dev,
-                                            precise=self.precise)
+            # G groups of consecutive views, one joint call each (on G streams)
+            G = max(1, min(int(bin_groups), self.V))
+            cuts = [round(g * self.V / G) for g in range(G + 1)]
+            self.groups = [(cuts[g], cuts[g + 1]) for g in range(G)]
+            self.mvbins = [MultiViewBinSorter(self.P, sum(self.capacity[a:b]), sizes[a:b],
+                                              device=dev, precise=self.precise)
+                           for a, b in self.groups]
+            self.mvbin = self.mvbins[0]
         else:
             self._per_view_sorters()
         self.images = [Rasterizer(c.width, c.height, device=dev) for c in self.cams]
@@ -582,10 +588,17 @@ class MultiViewRenderer:
                             for v, (cap, c) in enumerate(zip(self.capacity, self.cams))]
         return self.sorters
 
+    def _group_of(self, v):
+        for g, (a, b) in enumerate(self.groups):
+            if a <= v < b:
+                return g, v - a
+        raise IndexError(v)
+
     def _lists(self, v):
         """(tile ranges, sorted ids) of view v for the frame's rasterisation."""
         if self.joint:
-            return self.mvbin.ranges(v), self.mvbin.sorted_ids
+            g, w = self._group_of(v)
+            return self.mvbins[g].ranges(w), self.mvbins[g].sorted_ids
         return self.sorters[v].ranges, self.sorters[v].sorted_ids
 
     def view_lists(self, v):
@@ -595,8 +608,9 @@ class MultiViewRenderer:
         rg, ids = self._lists(v)
         rg = rg.cpu().numpy().astype(np.int64)
         if self.joint:
-            base = sum(self.mvbin.view_counts()[:v])
-            n = self.mvbin.view_counts()[v]
+            g, w = self._group_of(v)
+            counts = self.mvbins[g].view_counts()
+            base, n = sum(counts[:w]), counts[w]
         else:
             base, n = 0, self.sorters[v].n_splats()
         full = rg[:, 1] > rg[:, 0]
@@ -607,10 +621,24 @@ class MultiViewRenderer:
     def bin_sort(self, concurrent: bool = True):
         """Every view's lists: one gs_bin_sort_multiview call (joint), or one
         gs_bin_sort per view."""
-        if self.joint:
-            self.mvbin(*self._bin_inputs_all())
-        else:
+        if not self.joint:
             self.bin_sort_per_view(concurrent)
+            return
+        m2, rad, dep, con, opac = self._bin_inputs_all()
+        if len(self.groups) == 1:
+            self.mvbin(m2, rad, dep, con, opac)
+            return
+        cur = torch.cuda.current_stream()
+        if self._bin_streams is None or len(self._bin_streams) < len(self.groups):
+            self._bin_streams = [torch.cuda.Stream(device=self.device)
+                                 for _ in range(max(len(self.groups), self.K))]
+        for st in self._bin_streams[:len(self.groups)]:
+            st.wait_stream(cur)
+        for (a, b), mb, st in zip(self.groups, self.mvbins, self._bin_streams):
+            with torch.cuda.stream(st):
+                mb(m2[a:b], rad[a:b], dep[a:b], con[a:b], opac)
+        for st in self._bin_streams[:len(self.groups)]:
+            cur.wait_stream(st)
 
     def bin_sort_per_view(self, concurrent: bool = True):
         """One gs_bin_sort per view (K streams when ``concurrent``) into the
@@ -701,13 +729,13 @@ class MultiViewRenderer:
     # -- results ----------------------------------------------------------
     def n_splats(self):
         if self.joint:
-            return self.mvbin.view_counts()
+            return [c for mb in self.mvbins for c in mb.view_counts()]
         return [bs.n_splats() for bs in self.sorters]
 
     def overflowed(self):
         if self.joint:
-            over = self.mvbin.n_splats() > self.mvbin.capacity
-            return [over] * self.V
+            return [mb.n_splats() > mb.capacity for (a, b), mb in zip(self.groups, self.mvbins)
+                    for _ in range(b - a)]
         return [n > cap for n, cap in zip(self.n_splats(), self.capacity)]
 
     def latencies_ms(self):

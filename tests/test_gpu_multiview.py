@@ -122,11 +122,18 @@ def test_joint_and_per_view_binning_render_the_same():
     t = scene_tensors(sc)
     a = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams], joint_bin=True)
     b = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams], joint_bin=False)
+    c4 = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams], joint_bin=True, bin_groups=4)
     a.frame()
     b.frame()
+    c4.frame()
     torch.cuda.synchronize()
-    assert a.n_splats() == b.n_splats()
+    assert a.n_splats() == b.n_splats() == c4.n_splats()
     assert_same(snapshot(a), snapshot(b), "joint vs per-view binning")
+    assert_same(snapshot(c4), snapshot(b), "four joint groups vs per-view binning")
+    g = c4.capture()
+    g.replay()
+    torch.cuda.synchronize()
+    assert_same(snapshot(c4), snapshot(b), "graph of four joint groups")
 
 
 def test_preprocess_multiview_matches_single_and_oracle():
@@ -174,11 +181,13 @@ def test_many_views():
     assert all(x > 0 for x in mv.latencies_ms())
 
 
-@pytest.mark.parametrize("prec", ["fp16_g2l_split", "bf16_g2l_split"])
-def test_batched_small_vs_single_and_oracle(prec):
+@pytest.mark.parametrize("prec,joint", [("fp16_g2l_split", False), ("bf16_g2l_split", False),
+                                        ("fp16_g2l_split", True)])
+def test_batched_small_vs_single_and_oracle(prec, joint):
     sc, cams = small_case()
-    say(f"batched {prec}: {len(cams)} views, P={sc.P}")
-    mv = gs.MultiViewRenderer(scene_tensors(sc), [gs_cam(c) for c in cams], precision=prec)
+    say(f"batched {prec}: {len(cams)} views, P={sc.P}, joint binning {joint}")
+    mv = gs.MultiViewRenderer(scene_tensors(sc), [gs_cam(c) for c in cams], precision=prec,
+                              joint_bin=joint, bin_groups=2 if joint else 1)
     mv.frame()
     assert not any(mv.overflowed())
     batched = snapshot(mv)
