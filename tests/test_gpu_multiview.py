@@ -107,6 +107,43 @@ def test_bin_sort_multiview_matches_per_view_and_oracle(precise):
     assert np.all(rg[:, 0] == rg[:, 1])
 
 
+def test_bin_sort_multiview_empty_and_tiny_views():
+    """Views that keep nothing (a camera turned away from the scene), a
+    one-tile view and the most views one call takes: every view's lists are
+    still exactly its one-view lists."""
+    import dataclasses
+    sc = scenegen.scene_3d(20000, 1016)
+    base = [scenegen.orbit_camera(k, 8, *SMALL_RES[k % len(SMALL_RES)]) for k in range(8)]
+    away = dataclasses.replace(base[1], viewmat=(np.diag([-1.0, 1.0, -1.0, 1.0]) @ base[1].viewmat)
+                               .astype(np.float32))
+    tiny = scenegen.orbit_camera(3, 8, 16, 16)
+    cams = [base[0], away, tiny, base[2], away, base[5]]
+    cams = cams + [base[k % 8] if k % 5 else away for k in range(gs.GS_MAX_BIN_VIEWS - len(cams))]
+    assert len(cams) == gs.GS_MAX_BIN_VIEWS
+    gcams = [gs_cam(c) for c in cams]
+    pre = gs.preprocess_multiview(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), gcams)
+    ns = []
+    per = []
+    for v, c in enumerate(cams):
+        b = gs.bin_sort(pre["means2d"][v], pre["radii"][v], pre["depths"][v], c.width, c.height)
+        per.append(b)
+        ns.append(b.n_splats())
+    assert ns[1] == 0 and ns[4] == 0 and ns[0] > 0
+    mb = gs.MultiViewBinSorter(sc.P, sum(ns) + 1, [(c.width, c.height) for c in cams])
+    mb(pre["means2d"], pre["radii"], pre["depths"])
+    assert mb.view_counts() == ns
+    ids = host(mb.sorted_ids)
+    start = 0
+    for v in range(len(cams)):
+        r1 = host(per[v].ranges).astype(np.int64)
+        r2 = host(mb.ranges(v)).astype(np.int64)
+        full = r1[:, 1] > r1[:, 0]
+        assert np.array_equal(r1[full], r2[full] - start), v
+        assert np.all(r2[~full, 0] == r2[~full, 1]), v
+        assert np.array_equal(host(per[v].sorted_ids)[:ns[v]], ids[start:start + ns[v]]), v
+        start += ns[v]
+
+
 def test_bin_sort_multiview_no_gaussians():
     sizes = [(64, 48), (100, 60)]
     mb = gs.MultiViewBinSorter(0, 16, sizes)
