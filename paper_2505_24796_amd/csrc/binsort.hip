@@ -3,17 +3,21 @@
 //
 // Instead of one radix sort of N 64-bit (tile | depth) keys, the stage
 //   1. sorts the P Gaussians by depth (stable LSD radix, 4 x 8-bit passes on
-//      an order-preserving image of the float bits; ties keep id order),
+//      an order-preserving image of the float bits; ties keep id order; the
+//      first pass drops the Gaussians without splats),
 //   2. scans the per-Gaussian tile counts in that order and expands the
 //      splats (tile, id) in depth order, load-balanced over fixed windows of
 //      output slots,
 //   3. sorts the N splats by tile only (stable LSD radix over
-//      ceil(log2 ntiles) bits), which keeps depth order within a tile, and
+//      ceil(log2 ntiles) bits in passes of near-equal width), which keeps
+//      depth order within a tile, and
 //   4. finds each tile's [start, end).
 // Every splat moves 2 x (4 + 4) bytes per tile pass instead of 6 passes of
 // 24 bytes.  A Gaussian covers the tiles of its 3-sigma pixel rectangle, or,
 // with the precise rule (gs_bin_sort_precise), only those of them where its
-// raw opacity can reach the culling threshold.
+// raw opacity can reach the culling threshold.  One call can serve several
+// views of a scene (gs_bin_sort_multiview): every stage then runs over all
+// (Gaussian, view) pairs, and the two sorts over per-view segments.
 #include "common.h"
 
 namespace {
