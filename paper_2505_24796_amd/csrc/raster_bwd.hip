@@ -248,9 +248,11 @@ __global__ __launch_bounds__(256) void k_raster_bwd_fp32(BwdArgs a) {
 // ---------------------------------------------------------------------------
 // Matrix-core paths: the same staging (per-tile cull, compaction, V rows) and
 // the same products as k_raster_mfma, walked in reverse.
+// At least 5 waves per SIMD (86 VGPRs for the FP16 split; 4 waves at the
+// 120 the compiler otherwise takes were 3 % slower).
 // ---------------------------------------------------------------------------
 template <int VAR>
-__global__ __launch_bounds__(256) void k_raster_bwd_mfma(BwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_bwd_mfma(BwdArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR>::BYTES];
     __shared__ float4 s_p0[BATCH];   // mu'x, mu'y, s11, s12
     __shared__ float4 s_p1[BATCH];   // s22, o, id, -
