@@ -38,9 +38,10 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
             uint32_t id = a.ids[k];
             s_mu[threadIdx.x] = a.means2d[id];
             float o = a.opac[id];
-            s_co[threadIdx.x] = make_float4(a.conics[3 * id], a.conics[3 * id + 1],
-                                            a.conics[3 * id + 2], EARLY ? __logf(o) : o);
-            s_rgb[threadIdx.x] = make_float4(a.rgb[3 * id], a.rgb[3 * id + 1], a.rgb[3 * id + 2], 0.f);
+            const Float3 c3 = *(const Float3 *)(a.conics + 3 * (size_t)id);
+            const Float3 k3 = *(const Float3 *)(a.rgb + 3 * (size_t)id);
+            s_co[threadIdx.x] = make_float4(c3.x, c3.y, c3.z, EARLY ? __logf(o) : o);
+            s_rgb[threadIdx.x] = make_float4(k3.x, k3.y, k3.z, 0.f);
         }
         __syncthreads();
         int cnt = (int)min((uint32_t)BATCH, end - b0);

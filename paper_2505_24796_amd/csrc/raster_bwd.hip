@@ -208,9 +208,10 @@ __global__ __launch_bounds__(256) void k_raster_bwd_fp32(BwdArgs a) {
             uint32_t id = a.f.ids[start + j0 + threadIdx.x];
             s_mu[threadIdx.x] = a.f.means2d[id];
             float o = a.f.opac[id];
-            s_co[threadIdx.x] = make_float4(a.f.conics[3 * id], a.f.conics[3 * id + 1],
-                                            a.f.conics[3 * id + 2], EARLY ? __logf(o) : o);
-            s_rgb[threadIdx.x] = make_float4(a.f.rgb[3 * id], a.f.rgb[3 * id + 1], a.f.rgb[3 * id + 2], o);
+            const Float3 c3 = *(const Float3 *)(a.f.conics + 3 * (size_t)id);
+            const Float3 k3 = *(const Float3 *)(a.f.rgb + 3 * (size_t)id);
+            s_co[threadIdx.x] = make_float4(c3.x, c3.y, c3.z, EARLY ? __logf(o) : o);
+            s_rgb[threadIdx.x] = make_float4(k3.x, k3.y, k3.z, o);
             s_id[threadIdx.x] = id;
         }
 #pragma unroll

@@ -235,18 +235,28 @@ struct SplatRegs {
     bool valid;
 };
 
+// Three consecutive floats read with one 12-byte load (the arrays are only
+// 4-byte aligned per Gaussian; gfx950 loads dword-aligned dwordx3).
+struct __attribute__((aligned(4))) Float3 {
+    float x, y, z;
+};
+
+// One splat's parameters: four loads (mean, conic, opacity, colour) rather
+// than one per float, so a wave's gather touches each array's lines once.
 __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bool valid) {
     SplatRegs s;
     s.valid = valid;
     if (valid) {
         s.mu = a.means2d[id];
-        s.s11 = a.conics[3 * id];
-        s.s12 = a.conics[3 * id + 1];
-        s.s22 = a.conics[3 * id + 2];
+        const Float3 c = *(const Float3 *)(a.conics + 3 * (size_t)id);
+        s.s11 = c.x;
+        s.s12 = c.y;
+        s.s22 = c.z;
         s.o = a.opac[id];
-        s.r = a.rgb[3 * id];
-        s.g = a.rgb[3 * id + 1];
-        s.b = a.rgb[3 * id + 2];
+        const Float3 k = *(const Float3 *)(a.rgb + 3 * (size_t)id);
+        s.r = k.x;
+        s.g = k.y;
+        s.b = k.z;
     } else {
         s.mu = make_float2(0.f, 0.f);
         s.s11 = s.s12 = s.s22 = 0.f;
