@@ -415,6 +415,16 @@ struct SortBufs {
     uint32_t *k[2], *v[2];
 };
 
+// The scatter of a pass from buffer pair cur into cur ^ 1 (hist and totals
+// already scanned).
+template <int ITEMS, int BITS, bool DROP>
+void scatter_launch(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols,
+                    uint32_t *hist, uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS, DROP>), dim3(ncols), dim3(SORT_THREADS), 0, s,
+                       b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], st, shift, hist, totals,
+                       n_kept);
+}
+
 template <int ITEMS, int BITS, bool DROP>
 void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols, uint32_t *hist,
                 uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
@@ -423,9 +433,7 @@ void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t nco
                        b.k[cur], st, shift, hist);
     hipLaunchKernelGGL(k_hist_rows<TILE>, dim3(1 << BITS, st.nseg), dim3(SORT_THREADS), 0, s, hist,
                        st, ncols, totals);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS, DROP>), dim3(ncols), dim3(SORT_THREADS), 0, s,
-                       b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], st, shift, hist, totals,
-                       n_kept);
+    scatter_launch<ITEMS, BITS, DROP>(b, cur, st, shift, ncols, hist, totals, n_kept, s);
 }
 
 // Digit widths of a sort on `bits` key bits: ceil(bits / 8) passes of
@@ -443,12 +451,15 @@ inline int radix_width(int bits, int pass) {
 // launch cover the segments' blocks.  Returns the index of the buffer pair
 // holding the result.  With n_kept, the first pass drops every DROP_KEY key
 // and writes how many each segment kept there; later passes sort that many.
+// With p0 > 0 the first p0 passes have been done elsewhere and their result
+// is in buffer pair p0 % 2.
 template <int ITEMS>
 int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist,
-               uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
+               uint32_t *totals, uint32_t *n_kept, hipStream_t s, int p0 = 0) {
     if (ncols == 0) ncols = 1;
-    int cur = 0, shift = 0;
-    for (int p = 0; p < radix_passes(bits); ++p) {
+    int cur = p0 & 1, shift = 0;
+    for (int p = 0; p < p0; ++p) shift += radix_width(bits, p);
+    for (int p = p0; p < radix_passes(bits); ++p) {
         const int w = radix_width(bits, p);
         if (p == 0 && n_kept) {
             switch (w) {
@@ -818,36 +829,17 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t *a, uint32_t n, uint3
     return lo;
 }
 
-// Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
-// slots) under the 3-sigma rule: each thread locates the owner of its first
-// of EMIT_ITEMS consecutive slots by binary search, walks the rectangles in
-// row-major order and writes its slots with two 16-byte stores per array
-// (consecutive threads, consecutive 32-byte pieces).
-template <bool MULTI>
-__global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
-                                                       const uint32_t *__restrict__ offs,
-                                                       const uint2 *__restrict__ rects_sorted,
-                                                       const uint32_t *__restrict__ win_start,
-                                                       uint32_t nwin, ViewRef vt,
-                                                       const uint32_t *__restrict__ n_vis,
-                                                       const uint32_t *__restrict__ n_splats,
-                                                       uint32_t cap, uint32_t *__restrict__ tkey,
-                                                       uint32_t *__restrict__ tid) {
-    static_assert(EMIT_ITEMS == 8, "two 16-byte stores per thread and array");
-    __shared__ uint32_t s_off[EMIT_TILE + 1];
-    __shared__ uint2 s_rect[EMIT_TILE + 1];
-    __shared__ uint32_t s_id[EMIT_TILE + 1];
-    const uint32_t N = *n_splats;
-    const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
-                                                             nwin, N, cap, vt, n_vis, s_off,
-                                                             s_rect, s_id);
-    if (m == 0) return;  // block-uniform
-    __syncthreads();
-    const uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
-    const uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
-    const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
-    if (s0 >= oend) return;
-    // this thread's EMIT_ITEMS consecutive slots, written from registers
+// The EMIT_ITEMS consecutive slots from s0 (< oend) of a staged window under
+// the 3-sigma rule: the owner of s0 by binary search, then the rectangles
+// walked in row-major order; written from registers with two 16-byte stores
+// per array (consecutive threads, consecutive 32-byte pieces).  With HIST,
+// each key's lowest digit (key & dmask) is also counted in hcount (LDS).
+template <bool MULTI, bool HIST>
+__device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uint32_t *s_off,
+                                           const uint2 *s_rect, const uint32_t *s_id, uint32_t m,
+                                           const ViewRef &vt, uint32_t *__restrict__ tkey,
+                                           uint32_t *__restrict__ tid, uint32_t dmask,
+                                           uint32_t *hcount) {
     uint32_t tk[EMIT_ITEMS], tg[EMIT_ITEMS];
     {
         uint32_t k = last_le(s_off, m, s0);
@@ -893,6 +885,88 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
             }
         }
     }
+    if (HIST) {
+#pragma unroll
+        for (int i = 0; i < EMIT_ITEMS; ++i)
+            if (s0 + (uint32_t)i < oend) atomicAdd(&hcount[tk[i] & dmask], 1u);
+    }
+}
+
+// Expands the splats of output window blockIdx.x (EMIT_TILE consecutive
+// slots) under the 3-sigma rule, EMIT_ITEMS slots per thread.
+//
+// With HIST (one view), the window also counts its keys' lowest digit (key &
+// dmask, at most RADIX digits) for the first tile pass and writes the counts
+// to hist2[d * gridDim.x + window], so that pass needs no histogram kernel of
+// its own; windows past the splats write nothing.
+template <bool MULTI, bool HIST>
+__global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
+                                                       const uint32_t *__restrict__ offs,
+                                                       const uint2 *__restrict__ rects_sorted,
+                                                       const uint32_t *__restrict__ win_start,
+                                                       uint32_t nwin, ViewRef vt,
+                                                       const uint32_t *__restrict__ n_vis,
+                                                       const uint32_t *__restrict__ n_splats,
+                                                       uint32_t cap, uint32_t *__restrict__ tkey,
+                                                       uint32_t *__restrict__ tid, uint32_t dmask,
+                                                       uint32_t *__restrict__ hist2) {
+    static_assert(EMIT_ITEMS == 8, "two 16-byte stores per thread and array");
+    static_assert(!(MULTI && HIST), "the windows of a multi-view call cross views");
+    __shared__ uint32_t s_off[EMIT_TILE + 1];
+    __shared__ uint2 s_rect[EMIT_TILE + 1];
+    __shared__ uint32_t s_id[EMIT_TILE + 1];
+    __shared__ uint32_t hcount[HIST ? RADIX : 1];
+    const uint32_t N = *n_splats;
+    const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
+                                                             nwin, N, cap, vt, n_vis, s_off,
+                                                             s_rect, s_id);
+    if (m == 0) return;  // block-uniform
+    if (HIST && threadIdx.x <= dmask) hcount[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
+    const uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
+    const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
+    if (s0 < oend)
+        emit_slots<MULTI, HIST>(s0, oend, s_off, s_rect, s_id, m, vt, tkey, tid, dmask, hcount);
+    if (HIST) {
+        __syncthreads();
+        if (threadIdx.x <= dmask)
+            hist2[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = hcount[threadIdx.x];
+    }
+}
+
+// Workgroup d: digit d's counts of the first tile pass per block of
+// 2 * EMIT_TILE keys (the sum of two emission windows' counts, from hist2 as
+// k_emit<false, true> wrote it over nw_cols windows), scanned exclusively
+// over the blocks into hist[d * ncols + block]; the total goes to
+// totals[d].  One segment (one view).
+__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_pairs(const uint32_t *__restrict__ hist2,
+                                                                  uint32_t nw_cols, SegTable st,
+                                                                  uint32_t ncols,
+                                                                  uint32_t *__restrict__ hist,
+                                                                  uint32_t *__restrict__ totals) {
+    static_assert(TILE_ITEMS * SORT_THREADS == 2 * EMIT_TILE, "two windows per block");
+    __shared__ uint32_t lds[WAVES];
+    uint32_t base, n;
+    st.get(0, base, n);
+    const uint32_t nb = (n + 2u * EMIT_TILE - 1u) / (2u * EMIT_TILE);
+    const uint32_t nw = (n + EMIT_TILE - 1u) / EMIT_TILE;
+    const uint32_t *src = hist2 + (size_t)blockIdx.x * nw_cols;
+    uint32_t *row = hist + (size_t)blockIdx.x * ncols;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nb; c0 += SORT_THREADS) {
+        const uint32_t i = c0 + threadIdx.x;
+        uint32_t v = 0u;
+        if (i < nb) {
+            v = src[2u * i];
+            if (2u * i + 1u < nw) v += src[2u * i + 1u];
+        }
+        uint32_t ex;
+        const uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
+        if (i < nb) row[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 // Exclusive prefix sum of a[0, n) in place (n <= NT * 8); returns the total.
@@ -1301,20 +1375,6 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     uint32_t *other_ids = (npass % 2 == 0) ? U(L.tid) : sorted_ids;
     if (capacity == 0) emit_ids = other_ids = U(L.tid);  // nothing fits
     uint32_t eblocks = (capacity + win - 1) / win;
-    if (eblocks > 0) {
-        if (precise)
-            hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order,
-                               U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
-                               U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
-                               capacity, U(L.tkey0), emit_ids);
-        else
-            hipLaunchKernelGGL(nv > 1 ? k_emit<true> : k_emit<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
-                               (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
-                               (const uint32_t *)n_vis, d_num_splats, capacity, U(L.tkey0),
-                               emit_ids);
-    }
-    // 3. stable sort of each view's splats by tile (digits of the tile index
-    // within the view)
     SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     SegTable st{};
     st.nseg = nv;
@@ -1322,8 +1382,43 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     st.total = d_num_splats;
     st.cap = capacity;
     st.kv = nv > 1 ? vdims : nullptr;
+    // One view, 3-sigma rule: the expansion also counts the first tile pass's
+    // digits.  Its per-window counts go to the first pass's output key buffer
+    // (free until that pass scatters; RADIX counts per window must fit).
+    const bool emit_hist = nv == 1 && !precise && eblocks > 0 &&
+                           (uint64_t)RADIX * eblocks <= (uint64_t)capacity;
+    const int w0 = radix_width(tbits, 0);
+    if (eblocks > 0) {
+        if (precise)
+            hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order,
+                               U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
+                               U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
+                               capacity, U(L.tkey0), emit_ids);
+        else {
+            auto ke = emit_hist ? k_emit<false, true>
+                                : (nv > 1 ? k_emit<true, false> : k_emit<false, false>);
+            hipLaunchKernelGGL(ke, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
+                               (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
+                               (const uint32_t *)n_vis, d_num_splats, capacity, U(L.tkey0),
+                               emit_ids, (1u << w0) - 1u, U(L.tkey1));
+        }
+    }
+    // 3. stable sort of each view's splats by tile (digits of the tile index
+    // within the view)
+    if (emit_hist) {
+        hipLaunchKernelGGL(k_hist_rows_pairs, dim3(1 << w0), dim3(SORT_THREADS), 0, s,
+                           (const uint32_t *)U(L.tkey1), eblocks, st, L.ncols_tile, U(L.hist),
+                           U(L.totals));
+        switch (w0) {
+        case 4: scatter_launch<TILE_ITEMS, 4, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
+        case 5: scatter_launch<TILE_ITEMS, 5, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
+        case 6: scatter_launch<TILE_ITEMS, 6, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
+        case 7: scatter_launch<TILE_ITEMS, 7, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
+        default: scatter_launch<TILE_ITEMS, 8, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
+        }
+    }
     int tcur = radix_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, U(L.hist), U(L.totals), nullptr,
-                                      s);
+                                      s, emit_hist ? 1 : 0);
     // 4. ranges (tile indices are unique across views)
     Count nc{0u, d_num_splats, capacity};
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
