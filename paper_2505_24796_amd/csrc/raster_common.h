@@ -293,15 +293,20 @@ __device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y
     float fmin = 0.0f, fabs_terms = 0.0f;
     if (!(mx >= x0 && mx <= x1 && my >= y0 && my <= y1)) {
         fmin = __builtin_inff();
+        // Each edge's minimiser -b dx / c (or -b dy / a) through one hardware
+        // reciprocal per coefficient: it only picks the point where the form
+        // is evaluated, and at the minimum the form is flat, so its 1-ulp
+        // error moves f by far less than the margin below.
+        const float nb_c = -b * __builtin_amdgcn_rcpf(c), nb_a = -b * __builtin_amdgcn_rcpf(a);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             float dx, dy;
             if (e < 2) {
                 dx = (e == 0 ? x0 : x1) - mx;
-                dy = fminf(fmaxf(-b * dx / c, y0 - my), y1 - my);
+                dy = fminf(fmaxf(nb_c * dx, y0 - my), y1 - my);
             } else {
                 dy = (e == 2 ? y0 : y1) - my;
-                dx = fminf(fmaxf(-b * dy / a, x0 - mx), x1 - mx);
+                dx = fminf(fmaxf(nb_a * dy, x0 - mx), x1 - mx);
             }
             float t0 = a * dx * dx, t1 = 2.0f * b * dx * dy, t2 = c * dy * dy;
             float f = 0.5f * (t0 + t1 + t2);
