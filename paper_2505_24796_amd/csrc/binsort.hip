@@ -936,21 +936,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
 }
 
 // Workgroup d: digit d's counts of the first tile pass per block of
-// 2 * EMIT_TILE keys (the sum of two emission windows' counts, from hist2 as
-// k_emit<false, true> wrote it over nw_cols windows), scanned exclusively
-// over the blocks into hist[d * ncols + block]; the total goes to
-// totals[d].  One segment (one view).
-__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_pairs(const uint32_t *__restrict__ hist2,
-                                                                  uint32_t nw_cols, SegTable st,
-                                                                  uint32_t ncols,
-                                                                  uint32_t *__restrict__ hist,
-                                                                  uint32_t *__restrict__ totals) {
-    static_assert(TILE_ITEMS * SORT_THREADS == 2 * EMIT_TILE, "two windows per block");
+// TILE_ITEMS * SORT_THREADS keys (the sum of the counts of the block's G
+// emission windows of WIN slots, from hist2 as k_emit<false, true> wrote
+// it over nw_cols windows), scanned exclusively over the blocks into
+// hist[d * ncols + block]; the total goes to totals[d].  One segment (one
+// view).
+template <int WIN>
+__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32_t *__restrict__ hist2,
+                                                                    uint32_t nw_cols, SegTable st,
+                                                                    uint32_t ncols,
+                                                                    uint32_t *__restrict__ hist,
+                                                                    uint32_t *__restrict__ totals) {
+    constexpr uint32_t BLK = TILE_ITEMS * SORT_THREADS, G = BLK / WIN;
+    static_assert(BLK % WIN == 0, "whole windows per block");
     __shared__ uint32_t lds[WAVES];
     uint32_t base, n;
     st.get(0, base, n);
-    const uint32_t nb = (n + 2u * EMIT_TILE - 1u) / (2u * EMIT_TILE);
-    const uint32_t nw = (n + EMIT_TILE - 1u) / EMIT_TILE;
+    const uint32_t nb = (n + BLK - 1u) / BLK;
+    const uint32_t nw = (n + WIN - 1u) / WIN;
     const uint32_t *src = hist2 + (size_t)blockIdx.x * nw_cols;
     uint32_t *row = hist + (size_t)blockIdx.x * ncols;
     uint32_t carry = 0;
@@ -958,8 +961,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_pairs(const uint32_t
         const uint32_t i = c0 + threadIdx.x;
         uint32_t v = 0u;
         if (i < nb) {
-            v = src[2u * i];
-            if (2u * i + 1u < nw) v += src[2u * i + 1u];
+#pragma unroll
+            for (uint32_t g = 0; g < G; ++g)
+                if (G * i + g < nw) v += src[G * i + g];
         }
         uint32_t ex;
         const uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
@@ -1383,18 +1387,21 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     st.cap = capacity;
     st.kv = nv > 1 ? vdims : nullptr;
     // One view, 3-sigma rule: the expansion also counts the first tile pass's
-    // digits.  Its per-window counts go to the first pass's output key buffer
-    // (free until that pass scatters; RADIX counts per window must fit).
+    // digits (for precise lists, whose expansion already stages its window
+    // in LDS, this measured no faster).  The per-window counts go to the
+    // first pass's output key buffer (free until that pass scatters; RADIX
+    // counts per window must fit).
     const bool emit_hist = nv == 1 && !precise && eblocks > 0 &&
                            (uint64_t)RADIX * eblocks <= (uint64_t)capacity;
     const int w0 = radix_width(tbits, 0);
     if (eblocks > 0) {
-        if (precise)
-            hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order,
+        if (precise) {
+            hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks),
+                               dim3(SORT_THREADS), 0, s, n, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
                                U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
                                capacity, U(L.tkey0), emit_ids);
-        else {
+        } else {
             auto ke = emit_hist ? k_emit<false, true>
                                 : (nv > 1 ? k_emit<true, false> : k_emit<false, false>);
             hipLaunchKernelGGL(ke, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
@@ -1406,9 +1413,9 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     // 3. stable sort of each view's splats by tile (digits of the tile index
     // within the view)
     if (emit_hist) {
-        hipLaunchKernelGGL(k_hist_rows_pairs, dim3(1 << w0), dim3(SORT_THREADS), 0, s,
-                           (const uint32_t *)U(L.tkey1), eblocks, st, L.ncols_tile, U(L.hist),
-                           U(L.totals));
+        hipLaunchKernelGGL(k_hist_rows_windows<EMIT_TILE>,
+                           dim3(1 << w0), dim3(SORT_THREADS), 0, s, (const uint32_t *)U(L.tkey1),
+                           eblocks, st, L.ncols_tile, U(L.hist), U(L.totals));
         switch (w0) {
         case 4: scatter_launch<TILE_ITEMS, 4, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
         case 5: scatter_launch<TILE_ITEMS, 5, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
