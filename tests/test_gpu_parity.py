@@ -127,6 +127,25 @@ def test_bin_sort_overflow_and_empty():
     assert b2.n_splats() == 0 and int(host(b2.ranges).max()) == 0
 
 
+def test_bin_sort_first_pass_histogram_both_ways():
+    """A one-view call counts the first tile pass's digits during the
+    expansion when 256 counts per 2048-slot window fit in its capacity, and
+    runs a histogram kernel otherwise: both give the oracle's lists."""
+    W, H = 96, 64
+    sc, d = scene2d_inputs(W, H, 40, 12)  # ~190 splats
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    ranges_o, ids_o = oracle.bin_splats(sc.means2d, host(pre["radii"]), sc.depths, W, H)
+    N = len(ids_o)
+    say(f"bin_sort first-pass histogram, N={N}")
+    assert 0 < N < 256, N  # capacity N: the histogram kernel
+    for cap in (N, 256, 4096 + 7):
+        bs = gs.BinSorter(40, cap, W, H)
+        bs(d["means2d"], pre["radii"], d["depths"])
+        assert bs.n_splats() == N
+        assert np.array_equal(host(bs.ranges).astype(np.uint32), ranges_o), cap
+        assert np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids_o), cap
+
+
 # ---------------------------------------------------------------- raster FP32
 @pytest.mark.parametrize("prec", ["fp32", "fp32_earlycull"])
 @pytest.mark.parametrize("W,H,P,seed", [(256, 256, 2000, 1001), (250, 190, 3000, 7)])
