@@ -526,15 +526,22 @@ def main():
             ev[3].record()
 
     def timed(prec):
+        # K frames back to back between two synchronisations (the step time;
+        # no events inside the frames, each of which costs the GPU a few
+        # microseconds), then K more with HIP events between the stages on
+        # the frame's stream (stage times, the raster's duration)
         for _ in range(args.warmup):
             frame(prec)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            frame(prec, evs[k])
+            frame(prec)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        for k in range(args.steps):
+            frame(prec, evs[k])
+        torch.cuda.synchronize()
         st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
                         e[0].elapsed_time(e[3])] for e in evs])
         return wall, np.median(st, axis=0), st.mean(axis=0), st
@@ -594,13 +601,16 @@ def main():
 
         for _ in range(args.warmup):
             frame_p()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for _ in range(args.steps):
+            frame_p()
+        torch.cuda.synchronize()
+        wallp = (time.perf_counter() - t0) * 1e3 / args.steps
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         for e in evs:
             frame_p(e)
         torch.cuda.synchronize()
-        wallp = (time.perf_counter() - t0) * 1e3 / args.steps
         stp = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]),
                          e[2].elapsed_time(e[3])] for e in evs]).mean(axis=0)
         mp = float(torch.mean((rzp.rgb - ref_img) ** 2))
