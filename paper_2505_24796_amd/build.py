@@ -55,16 +55,18 @@ def _kernel_resources(src: str) -> list:
 
 def check_resources() -> list:
     """Every kernel must run from registers: no scratch (private segment) and
-    no register spills.  A regression here (e.g. a loop over the exponent
-    registers that is no longer fully unrolled) costs several times the run
-    time, so the build refuses it."""
+    no vector register spills.  A regression here (e.g. a loop over the
+    exponent registers that is no longer fully unrolled) costs several times
+    the run time, so the build refuses it.  Scalar registers spilled into
+    vector register lanes (no private segment) stay in registers and are
+    allowed."""
     bad, rows = [], []
     for src in SOURCES:
         for k in _kernel_resources(src):
             row = (k[".name"], k.get(".vgpr_count"), k.get(".private_segment_fixed_size", 0),
                    k.get(".vgpr_spill_count", 0), k.get(".sgpr_spill_count", 0))
             rows.append(row)
-            if row[2] or row[3] or row[4]:
+            if row[2] or row[3]:
                 bad.append(row)
     if bad:
         raise RuntimeError("kernels using scratch or spilling registers: " +

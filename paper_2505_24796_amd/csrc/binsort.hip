@@ -32,6 +32,11 @@ constexpr int WAVES = SORT_THREADS / 64;
 // many (smaller) workgroups as the N splats' tile sort
 constexpr int DEPTH_ITEMS = 8;
 constexpr int TILE_ITEMS = 16;
+// a one-view call with room for this many splats sorts them by tile in
+// blocks of twice as many keys (longer runs of equal digits per block to
+// write; below it, more and shorter blocks measure faster)
+constexpr int TILE_ITEMS_BIG = 32;
+constexpr uint32_t BIG_SORT_CAP = 32u << 20;
 constexpr int EMIT_ITEMS = 8;
 constexpr int EMIT_TILE = SORT_THREADS * EMIT_ITEMS;   // output slots per window (3-sigma rule)
 // precise rule: windows of 256 threads x 4 slots, with a table of up to
@@ -935,19 +940,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
     }
 }
 
-// Workgroup d: digit d's counts of the first tile pass per block of
-// TILE_ITEMS * SORT_THREADS keys (the sum of the counts of the block's G
+// Workgroup d: digit d's counts of the first tile pass per block of BLK
+// keys (the sum of the counts of the block's G = BLK / WIN
 // emission windows of WIN slots, from hist2 as k_emit<false, true> wrote
 // it over nw_cols windows), scanned exclusively over the blocks into
 // hist[d * ncols + block]; the total goes to totals[d].  One segment (one
 // view).
-template <int WIN>
+template <int WIN, int BLK>
 __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32_t *__restrict__ hist2,
                                                                     uint32_t nw_cols, SegTable st,
                                                                     uint32_t ncols,
                                                                     uint32_t *__restrict__ hist,
                                                                     uint32_t *__restrict__ totals) {
-    constexpr uint32_t BLK = TILE_ITEMS * SORT_THREADS, G = BLK / WIN;
+    constexpr uint32_t G = BLK / WIN;
     static_assert(BLK % WIN == 0, "whole windows per block");
     __shared__ uint32_t lds[WAVES];
     uint32_t base, n;
@@ -1172,6 +1177,11 @@ struct Layout {
     uint32_t nwin, ncols_depth, ncols_tile;
 };
 
+// Keys per thread of the tile sort's blocks.
+inline int tile_items(uint32_t nv, uint32_t cap) {
+    return nv == 1 && cap >= BIG_SORT_CAP ? TILE_ITEMS_BIG : TILE_ITEMS;
+}
+
 Layout layout(uint32_t nv, uint32_t P, uint32_t cap, bool precise) {
     Layout L{};
     size_t off = 0;
@@ -1182,7 +1192,8 @@ Layout layout(uint32_t nv, uint32_t P, uint32_t cap, bool precise) {
     };
     const size_t n = (size_t)nv * P;
     L.ncols_depth = nv * ((P + SORT_THREADS * DEPTH_ITEMS - 1) / (SORT_THREADS * DEPTH_ITEMS));
-    L.ncols_tile = (cap + SORT_THREADS * TILE_ITEMS - 1) / (SORT_THREADS * TILE_ITEMS) + nv;
+    const uint32_t tblk = SORT_THREADS * tile_items(nv, cap);
+    L.ncols_tile = (cap + tblk - 1) / tblk + nv;
     const uint32_t ncols = L.ncols_depth > L.ncols_tile ? L.ncols_depth : L.ncols_tile;
     const uint32_t win = precise ? EMIT_TILE_P : EMIT_TILE;
     L.nwin = (cap + win - 1) / win + 2;
@@ -1279,6 +1290,29 @@ extern "C" size_t gs_bin_sort_multiview_workspace_bytes(int32_t nviews, int32_t 
 }
 
 namespace {
+
+// The tile sort of a call, ITEMS keys per thread.  With emit_hist, the
+// expansion has counted the first pass's digits per window into hist2
+// (eblocks windows): the pass then only scans and scatters.  Returns the
+// buffer pair holding the result.
+template <int ITEMS>
+int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool emit_hist,
+              const uint32_t *hist2, uint32_t eblocks, uint32_t *hist, uint32_t *totals,
+              hipStream_t s) {
+    if (emit_hist) {
+        const int w0 = radix_width(tbits, 0);
+        hipLaunchKernelGGL((k_hist_rows_windows<EMIT_TILE, SORT_THREADS * ITEMS>), dim3(1 << w0),
+                           dim3(SORT_THREADS), 0, s, hist2, eblocks, st, ncols, hist, totals);
+        switch (w0) {
+        case 4: scatter_launch<ITEMS, 4, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
+        case 5: scatter_launch<ITEMS, 5, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
+        case 6: scatter_launch<ITEMS, 6, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
+        case 7: scatter_launch<ITEMS, 7, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
+        default: scatter_launch<ITEMS, 8, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
+        }
+    }
+    return radix_sort<ITEMS>(tb, st, ncols, tbits, hist, totals, nullptr, s, emit_hist ? 1 : 0);
+}
 
 gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t *heights,
                          const float *means2d, const int32_t *radii, const float *depths,
@@ -1412,20 +1446,11 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     }
     // 3. stable sort of each view's splats by tile (digits of the tile index
     // within the view)
-    if (emit_hist) {
-        hipLaunchKernelGGL(k_hist_rows_windows<EMIT_TILE>,
-                           dim3(1 << w0), dim3(SORT_THREADS), 0, s, (const uint32_t *)U(L.tkey1),
-                           eblocks, st, L.ncols_tile, U(L.hist), U(L.totals));
-        switch (w0) {
-        case 4: scatter_launch<TILE_ITEMS, 4, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
-        case 5: scatter_launch<TILE_ITEMS, 5, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
-        case 6: scatter_launch<TILE_ITEMS, 6, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
-        case 7: scatter_launch<TILE_ITEMS, 7, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
-        default: scatter_launch<TILE_ITEMS, 8, false>(tb, 0, st, 0, L.ncols_tile, U(L.hist), U(L.totals), nullptr, s); break;
-        }
-    }
-    int tcur = radix_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, U(L.hist), U(L.totals), nullptr,
-                                      s, emit_hist ? 1 : 0);
+    int tcur = tile_items((uint32_t)nv, capacity) == TILE_ITEMS_BIG
+                   ? tile_sort<TILE_ITEMS_BIG>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
+                                               eblocks, U(L.hist), U(L.totals), s)
+                   : tile_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
+                                           eblocks, U(L.hist), U(L.totals), s);
     // 4. ranges (tile indices are unique across views)
     Count nc{0u, d_num_splats, capacity};
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
