@@ -102,3 +102,26 @@ def test_fullsize_sampled(workload, poses, precs):
             assert q["psnr"] >= 50.0
             if prec != "fp16_g2l":  # the paper's K = 8 layout meets the PSNR bar only
                 assert q["frac_2_255"] >= 0.999
+
+
+def test_tile_sort_block_sizes_agree():
+    """A one-view call with room for 32M+ splats sorts by tile in 8192-key
+    blocks, smaller ones in 4096-key blocks: the 1080p/1M lists (3-sigma and
+    precise) are the same either way."""
+    cfg = scenegen.CONFIGS["fwd_1080p_1M"]
+    W, H = cfg["width"], cfg["height"]
+    sc = scenegen.make_scene(cfg)
+    c = scenegen.make_camera(cfg)
+    cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
+    opac = dev(sc.opacities)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    for precise in (False, True):
+        kw = dict(conics=pre["conics"], opacities=opac, precise=True) if precise else {}
+        small = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, **kw)
+        N = small.n_splats()
+        big = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, capacity=(32 << 20) + 5,
+                          **kw)
+        say(f"  precise={precise}: N={N}, capacities {N} and {(32 << 20) + 5}")
+        assert big.n_splats() == N
+        assert torch.equal(big.ranges, small.ranges)
+        assert torch.equal(big.sorted_ids[:N], small.sorted_ids[:N])
