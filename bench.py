@@ -400,13 +400,15 @@ def multiview(args):
 
 
 def binsort_only(args):
-    """Bin/sort of the 1080p/1M frame alone, 3-sigma rule and precise
-    intersection alternating, `steps` times each (for kernel traces)."""
+    """Bin/sort of one frame of `--workload` alone (1080p/1M by default),
+    3-sigma rule and precise intersection alternating, `steps` times each
+    (for kernel traces)."""
     import torch
 
     import paper_2505_24796_amd as gs
     import scenegen
-    cfg = scenegen.CONFIGS["fwd_1080p_1M"]
+    cfg = scenegen.CONFIGS[args.workload]
+    assert cfg["kind"] == "3d"
     W, H = cfg["width"], cfg["height"]
     sc = scenegen.make_scene(cfg)
     c = scenegen.make_camera(cfg)
@@ -428,7 +430,7 @@ def binsort_only(args):
         torch.cuda.synchronize()
         tp.append(ev[0].elapsed_time(ev[1]))
         t3.append(ev[1].elapsed_time(ev[2]))
-    print(json.dumps({"workload": "fwd_1080p_1M", "bin_sort_precise_ms": float(np.median(tp)),
+    print(json.dumps({"workload": args.workload, "bin_sort_precise_ms": float(np.median(tp)),
                       "bin_sort_3sigma_ms": float(np.median(t3)), "splats_precise": bp.n_splats(),
                       "splats_3sigma": b3.n_splats()}), flush=True)
 
