@@ -148,12 +148,26 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
     uint64_t ex;
     block_excl_scan<uint64_t>(s, ex, lds);
     uint64_t run = pre + ex;
+    // the thread's offsets: four 16-byte stores when all its items exist
+    const bool full = base + SORT_ITEMS <= n;
+    if (full) {
+        uint32_t o[SORT_ITEMS];
+        uint64_t r = run;
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS; ++k) {
+            o[k] = (uint32_t)r;
+            r += v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS; k += 4)
+            *(uint4 *)(offs + base + k) = make_uint4(o[k], o[k + 1], o[k + 2], o[k + 3]);
+    }
     // view v's splats start at the offset of its first instance, v * Pv
     uint32_t vnext = (uint32_t)((base + Pv - 1) / Pv);
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
         if (base + k < n) {
-            offs[base + k] = (uint32_t)run;
+            if (!full) offs[base + k] = (uint32_t)run;
             if ((int)vnext < nv && base + k == (size_t)vnext * Pv) {
                 seg_bounds[vnext] = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
                 ++vnext;
@@ -253,17 +267,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     int sg;
     uint32_t lb, base, n, col0;
     if (!seg_block<TILE>(st, blockIdx.x, sg, lb, base, n, col0)) return;  // idle: uniform exit
-    if (threadIdx.x < NDIG) h[threadIdx.x] = 0;
-    __syncthreads();
     const uint32_t kb = st.key_base(sg);
     const size_t b0 = (size_t)lb * TILE;
+    // every load issued before the first count (a block that is not idle has
+    // n >= 1, so the index is clamped into the segment), then the counts
+    uint32_t kv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const size_t i = b0 + (size_t)k * SORT_THREADS + threadIdx.x;
-        if (i < n) {
-            const uint32_t key = keys[base + i];
-            if (!DROP || key != DROP_KEY) atomicAdd(&h[((key - kb) >> shift) & (NDIG - 1)], 1u);
-        }
+        kv[k] = keys[base + (i < n ? i : (size_t)n - 1)];
+    }
+    if (threadIdx.x < NDIG) h[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const size_t i = b0 + (size_t)k * SORT_THREADS + threadIdx.x;
+        if (i < n && (!DROP || kv[k] != DROP_KEY))
+            atomicAdd(&h[((kv[k] - kb) >> shift) & (NDIG - 1)], 1u);
     }
     __syncthreads();
     if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -752,19 +772,36 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
     const size_t base = (size_t)blockIdx.x * SORT_TILE;
     uint64_t sum = 0;
     const uint32_t nvis0 = n_vis[0];
-#pragma unroll 4
+    // two rounds of loads for all the thread's items (the order entries,
+    // then the rectangles they name) rather than two dependent loads per
+    // item.  Slots past a view's Gaussians with splats (and past the end:
+    // the index is clamped, P >= 1 here) hold no valid id and read
+    // Gaussian 0 instead; their outputs are zero.
+    uint32_t g[SORT_ITEMS];
+    bool has[SORT_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        const size_t j = base + (size_t)k * SORT_THREADS + threadIdx.x;
+        const size_t jc = j < (size_t)P ? j : (size_t)P - 1;
+        const int v = vt.view_of<MULTI>((uint32_t)jc);
+        has[k] = j < (size_t)P && jc - (size_t)v * vt.P < (MULTI ? n_vis[v] : nvis0);
+        const uint32_t o = order[jc];
+        g[k] = has[k] ? o : 0u;
+    }
+    uint2 r[SORT_ITEMS];
+    uint32_t cg[SORT_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        r[k] = rects[g[k]];
+        cg[k] = PRECISE ? cnt_g[g[k]] : 0u;
+    }
+#pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
         const size_t j = base + (size_t)k * SORT_THREADS + threadIdx.x;
         if (j < (size_t)P) {
-            uint2 r = make_uint2(0u, 0u);  // past the Gaussians that have splats
-            uint32_t c = 0u;
-            const int v = vt.view_of<MULTI>((uint32_t)j);
-            if (j - (size_t)v * vt.P < (MULTI ? n_vis[v] : nvis0)) {
-                const uint32_t g = order[j];
-                r = rects[g];
-                c = PRECISE ? cnt_g[g] : (r.y & 0xFFFFu) * (r.y >> 16);
-            }
-            rects_sorted[j] = r;
+            const uint2 rr = has[k] ? r[k] : make_uint2(0u, 0u);
+            const uint32_t c = !has[k] ? 0u : PRECISE ? cg[k] : (rr.y & 0xFFFFu) * (rr.y >> 16);
+            rects_sorted[j] = rr;
             cnt[j] = c;
             sum += c;
         }
