@@ -289,6 +289,40 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan over columns [0, nb) of get(i) into out[i], ROW_RPT
+// consecutive columns per thread per round (a row of a few thousand blocks
+// takes a few rounds, not one block scan per 256 columns); returns the
+// total.  get(i) is called with i < nb only, and every column of a round
+// is read before any is written, so out may be the row that get reads.
+// All threads of the block call it.
+constexpr int ROW_RPT = 8;
+template <typename Get>
+__device__ __forceinline__ uint32_t scan_columns(Get get, uint32_t *out, uint32_t nb,
+                                                 uint32_t *lds) {
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nb; c0 += SORT_THREADS * ROW_RPT) {
+        const uint32_t i0 = c0 + threadIdx.x * ROW_RPT;
+        uint32_t v[ROW_RPT], sum = 0;
+#pragma unroll
+        for (int r = 0; r < ROW_RPT; ++r) {
+            const uint32_t i = i0 + r;
+            const uint32_t x = get(i < nb ? i : nb - 1u);
+            v[r] = i < nb ? x : 0u;
+            sum += v[r];
+        }
+        uint32_t ex;
+        const uint32_t tot = block_excl_scan<uint32_t>(sum, ex, lds);
+        uint32_t run = carry + ex;
+#pragma unroll
+        for (int r = 0; r < ROW_RPT; ++r) {
+            if (i0 + (uint32_t)r < nb) out[i0 + r] = run;
+            run += v[r];
+        }
+        carry += tot;
+    }
+    return carry;
+}
+
 // Workgroup (d, s): exclusive scan of digit d's counts over the blocks of
 // segment s, in place; the total goes to totals[s][d].  ncols = workgroups
 // of the hist and scatter launches.
@@ -306,15 +340,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
     st.get(sg, base, n);
     const uint32_t nb = (n + TILE - 1) / TILE;
     uint32_t *row = hist + (size_t)blockIdx.x * ncols + col0;
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < nb; c0 += SORT_THREADS) {
-        const uint32_t i = c0 + threadIdx.x;
-        const uint32_t v = i < nb ? row[i] : 0u;
-        uint32_t ex;
-        const uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
-        if (i < nb) row[i] = carry + ex;
-        carry += tot;
-    }
+    const uint32_t carry = scan_columns([&](uint32_t i) { return row[i]; }, row, nb, lds);
     if (threadIdx.x == 0) totals[sg * RADIX + blockIdx.x] = carry;
 }
 
@@ -998,20 +1024,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32
     const uint32_t nw = (n + WIN - 1u) / WIN;
     const uint32_t *src = hist2 + (size_t)blockIdx.x * nw_cols;
     uint32_t *row = hist + (size_t)blockIdx.x * ncols;
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < nb; c0 += SORT_THREADS) {
-        const uint32_t i = c0 + threadIdx.x;
+    // block i's count: its windows G i .. G i + G - 1 that hold splats
+    // (nw >= 1 whenever nb >= 1)
+    auto block_count = [&](uint32_t i) {
         uint32_t v = 0u;
-        if (i < nb) {
 #pragma unroll
-            for (uint32_t g = 0; g < G; ++g)
-                if (G * i + g < nw) v += src[G * i + g];
+        for (uint32_t g = 0; g < G; ++g) {
+            const uint32_t w = G * i + g;
+            const uint32_t x = src[w < nw ? w : nw - 1u];
+            v += w < nw ? x : 0u;
         }
-        uint32_t ex;
-        const uint32_t tot = block_excl_scan<uint32_t>(v, ex, lds);
-        if (i < nb) row[i] = carry + ex;
-        carry += tot;
-    }
+        return v;
+    };
+    const uint32_t carry = scan_columns(block_count, row, nb, lds);
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
