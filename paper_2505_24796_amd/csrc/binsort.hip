@@ -37,8 +37,12 @@ constexpr int TILE_ITEMS = 16;
 // write; below it, more and shorter blocks measure faster)
 constexpr int TILE_ITEMS_BIG = 32;
 constexpr uint32_t BIG_SORT_CAP = 32u << 20;
-constexpr int EMIT_ITEMS = 8;
-constexpr int EMIT_TILE = SORT_THREADS * EMIT_ITEMS;   // output slots per window (3-sigma rule)
+// 3-sigma expansion: windows of EMIT_TILE output slots, 512 threads of 4
+// slots each (the window's staged Gaussians fill 33 KB of LDS, so wider
+// workgroups are what keeps more waves per CU in flight)
+constexpr int EMIT_THREADS = 512;
+constexpr int EMIT_ITEMS = 4;
+constexpr int EMIT_TILE = EMIT_THREADS * EMIT_ITEMS;
 // precise rule: windows of 256 threads x 4 slots, with a table of up to
 // RCAP (Gaussian, tile row) runs per window
 constexpr int EMIT_ITEMS_P = 4;
@@ -899,8 +903,8 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t *a, uint32_t n, uint3
 
 // The EMIT_ITEMS consecutive slots from s0 (< oend) of a staged window under
 // the 3-sigma rule: the owner of s0 by binary search, then the rectangles
-// walked in row-major order; written from registers with two 16-byte stores
-// per array (consecutive threads, consecutive 32-byte pieces).  With HIST,
+// walked in row-major order; written from registers with one 16-byte store
+// per array (consecutive threads, consecutive 16-byte pieces).  With HIST,
 // each key's lowest digit (key & dmask) is also counted in hcount (LDS).
 template <bool MULTI, bool HIST>
 __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uint32_t *s_off,
@@ -939,11 +943,8 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
     }
     const bool vec = s0 + EMIT_ITEMS <= oend && gs::aligned(tkey + s0, 16) && gs::aligned(tid + s0, 16);
     if (vec) {
-        uint4 *dk = (uint4 *)(tkey + s0), *di = (uint4 *)(tid + s0);
-        dk[0] = make_uint4(tk[0], tk[1], tk[2], tk[3]);
-        dk[1] = make_uint4(tk[4], tk[5], tk[6], tk[7]);
-        di[0] = make_uint4(tg[0], tg[1], tg[2], tg[3]);
-        di[1] = make_uint4(tg[4], tg[5], tg[6], tg[7]);
+        *(uint4 *)(tkey + s0) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+        *(uint4 *)(tid + s0) = make_uint4(tg[0], tg[1], tg[2], tg[3]);
     } else {
 #pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) {
@@ -968,7 +969,7 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
 // to hist2[d * gridDim.x + window], so that pass needs no histogram kernel of
 // its own; windows past the splats write nothing.
 template <bool MULTI, bool HIST>
-__global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ offs,
                                                        const uint2 *__restrict__ rects_sorted,
                                                        const uint32_t *__restrict__ win_start,
@@ -978,14 +979,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit(int P, const uint32_t *__
                                                        uint32_t cap, uint32_t *__restrict__ tkey,
                                                        uint32_t *__restrict__ tid, uint32_t dmask,
                                                        uint32_t *__restrict__ hist2) {
-    static_assert(EMIT_ITEMS == 8, "two 16-byte stores per thread and array");
+    static_assert(EMIT_ITEMS == 4, "one 16-byte store per thread and array");
+    static_assert(EMIT_THREADS > RADIX, "one thread per digit count");
     static_assert(!(MULTI && HIST), "the windows of a multi-view call cross views");
     __shared__ uint32_t s_off[EMIT_TILE + 1];
     __shared__ uint2 s_rect[EMIT_TILE + 1];
     __shared__ uint32_t s_id[EMIT_TILE + 1];
     __shared__ uint32_t hcount[HIST ? RADIX : 1];
     const uint32_t N = *n_splats;
-    const uint32_t m = stage_window<EMIT_TILE, SORT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
+    const uint32_t m = stage_window<EMIT_TILE, EMIT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
                                                              nwin, N, cap, vt, n_vis, s_off,
                                                              s_rect, s_id);
     if (m == 0) return;  // block-uniform
@@ -1500,7 +1502,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
         } else {
             auto ke = emit_hist ? k_emit<false, true>
                                 : (nv > 1 ? k_emit<true, false> : k_emit<false, false>);
-            hipLaunchKernelGGL(ke, dim3(eblocks), dim3(SORT_THREADS), 0, s, n, order, U(L.offs),
+            hipLaunchKernelGGL(ke, dim3(eblocks), dim3(EMIT_THREADS), 0, s, n, order, U(L.offs),
                                (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
                                (const uint32_t *)n_vis, d_num_splats, capacity, U(L.tkey0),
                                emit_ids, (1u << w0) - 1u, U(L.tkey1));
