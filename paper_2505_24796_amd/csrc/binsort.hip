@@ -43,10 +43,11 @@ constexpr uint32_t BIG_SORT_CAP = 32u << 20;
 constexpr int EMIT_THREADS = 512;
 constexpr int EMIT_ITEMS = 4;
 constexpr int EMIT_TILE = EMIT_THREADS * EMIT_ITEMS;
-// precise rule: windows of 256 threads x 4 slots, with a table of up to
+// precise rule: windows of 512 threads x 2 slots, with a table of up to
 // RCAP (Gaussian, tile row) runs per window
-constexpr int EMIT_ITEMS_P = 4;
-constexpr int EMIT_TILE_P = SORT_THREADS * EMIT_ITEMS_P;
+constexpr int EMIT_THREADS_P = 512;
+constexpr int EMIT_ITEMS_P = 2;
+constexpr int EMIT_TILE_P = EMIT_THREADS_P * EMIT_ITEMS_P;
 constexpr int RCAP = 1280;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -1069,7 +1070,7 @@ __device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t n, ui
 // writes its EMIT_ITEMS_P tiles directly.  A window with more than RCAP
 // pairs (several very tall Gaussians) walks the rows per thread instead.
 template <bool MULTI>
-__global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
+__global__ __launch_bounds__(EMIT_THREADS_P) void k_emit_precise(
     int P, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offs,
     const uint2 *__restrict__ rects_sorted, const PGauss *__restrict__ pg,
     const uint32_t *__restrict__ win_start, uint32_t nwin, ViewRef vt,
@@ -1085,9 +1086,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
     __shared__ uint16_t s_pk[RCAP], s_pty[RCAP], s_pc0[RCAP], s_pn[RCAP];
     __shared__ uint32_t s_tk[WIN];
     __shared__ uint32_t s_tg[WIN];
-    __shared__ uint32_t s_scan[WAVES];
+    __shared__ uint32_t s_scan[EMIT_THREADS_P / 64];
     const uint32_t N = *n_splats;
-    const uint32_t m = stage_window<WIN, SORT_THREADS, MULTI>(P, order, offs, rects_sorted, win_start,
+    const uint32_t m = stage_window<WIN, EMIT_THREADS_P, MULTI>(P, order, offs, rects_sorted, win_start,
                                                        nwin, N, cap, vt, n_vis, s_off, s_rect,
                                                        s_id);
     if (m == 0) return;  // block-uniform
@@ -1101,11 +1102,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
         s_tk[s0 + i - o0] = 0u;
         s_tg[s0 + i - o0] = 0u;
     }
-    for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS) s_hoff[k] = s_rect[k].y >> 16;
+    for (uint32_t k = threadIdx.x; k < m; k += EMIT_THREADS_P) s_hoff[k] = s_rect[k].y >> 16;
     __syncthreads();
-    const uint32_t R = block_scan_array<SORT_THREADS>(s_hoff, m, s_scan);
+    const uint32_t R = block_scan_array<EMIT_THREADS_P>(s_hoff, m, s_scan);
     if (R <= (uint32_t)RCAP) {
-        for (uint32_t p = threadIdx.x; p < R; p += SORT_THREADS) {
+        for (uint32_t p = threadIdx.x; p < R; p += EMIT_THREADS_P) {
             const uint32_t k = last_le(s_hoff, m, p);
             const RectDec d = dec_rect(s_rect[k]);
             const int ty = d.ty0 + (int)(p - s_hoff[k]);
@@ -1120,12 +1121,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
             s_pslot[p] = n;
         }
         __syncthreads();
-        block_scan_array<SORT_THREADS>(s_pslot, R, s_scan);
+        block_scan_array<EMIT_THREADS_P>(s_pslot, R, s_scan);
         // absolute first slots: Gaussian k's first run starts at s_off[k]
-        for (uint32_t k = threadIdx.x; k < m; k += SORT_THREADS)
+        for (uint32_t k = threadIdx.x; k < m; k += EMIT_THREADS_P)
             s_hoff[k] = s_off[k] - s_pslot[s_hoff[k]];
         __syncthreads();
-        for (uint32_t p = threadIdx.x; p < R; p += SORT_THREADS) s_pslot[p] += s_hoff[s_pk[p]];
+        for (uint32_t p = threadIdx.x; p < R; p += EMIT_THREADS_P) s_pslot[p] += s_hoff[s_pk[p]];
         __syncthreads();
         if (s0 < oend) {
             // the last run starting at or before s0 is non-empty and holds it
@@ -1190,7 +1191,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_emit_precise(
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < oend - o0; i += SORT_THREADS) {
+    for (uint32_t i = threadIdx.x; i < oend - o0; i += EMIT_THREADS_P) {
         tkey[o0 + i] = s_tk[i];
         tid[o0 + i] = s_tg[i];
     }
@@ -1495,7 +1496,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     if (eblocks > 0) {
         if (precise) {
             hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks),
-                               dim3(SORT_THREADS), 0, s, n, order,
+                               dim3(EMIT_THREADS_P), 0, s, n, order,
                                U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
                                U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
                                capacity, U(L.tkey0), emit_ids);
