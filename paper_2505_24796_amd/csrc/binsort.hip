@@ -350,21 +350,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
 }
 
 // With DROP, the first block of each segment also writes the number of keys
-// the segment keeps to n_kept[s].
-template <int ITEMS, int BITS, bool DROP>
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+// the segment keeps to n_kept[s].  NT threads of ITEMS keys per block.
+template <int ITEMS, int BITS, bool DROP, int NT>
+__global__ __launch_bounds__(NT) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, SegTable st, int shift, const uint32_t *__restrict__ hist_scan,
     const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept) {
     constexpr int NDIG = 1 << BITS;
-    __shared__ uint32_t wcnt[WAVES][NDIG];
+    __shared__ uint32_t wcnt[(NT / 64)][NDIG];
     __shared__ uint32_t gbase[NDIG];   // segment position of this block's first key of digit d
     __shared__ uint32_t lstart[NDIG];  // local position of this block's first key of digit d
-    constexpr int TILE = SORT_THREADS * ITEMS;
-    constexpr int W_ITEMS = TILE / WAVES, W_CHUNKS = W_ITEMS / 64;
+    constexpr int TILE = NT * ITEMS;
+    constexpr int W_ITEMS = TILE / (NT / 64), W_CHUNKS = W_ITEMS / 64;
     __shared__ uint32_t skey[TILE];
     __shared__ uint32_t sval[TILE];
-    __shared__ uint32_t lds_scan[WAVES];
+    __shared__ uint32_t lds_scan[(NT / 64)];
     int sg;
     uint32_t lb, sbase, n, col0;
     if (!seg_block<TILE>(st, blockIdx.x, sg, lb, sbase, n, col0)) return;  // idle: uniform exit
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < NDIG) {
 #pragma unroll
-        for (int i = 0; i < WAVES; ++i) wcnt[i][threadIdx.x] = 0;
+        for (int i = 0; i < (NT / 64); ++i) wcnt[i][threadIdx.x] = 0;
     }
     {
         // exclusive scan of the segment's digit totals -> digit base
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         uint32_t d = threadIdx.x, off = 0;
         if (d < NDIG) {
 #pragma unroll
-            for (int i = 0; i < WAVES; ++i) {
+            for (int i = 0; i < (NT / 64); ++i) {
                 uint32_t t = wcnt[i][d];
                 wcnt[i][d] = off;
                 off += t;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __syncthreads();
     // ... and write runs of equal digits to consecutive global addresses
     const uint32_t nloc = nloc_kept;
-    for (uint32_t lp = threadIdx.x; lp < nloc; lp += SORT_THREADS) {
+    for (uint32_t lp = threadIdx.x; lp < nloc; lp += NT) {
         uint32_t k = skey[lp];
         uint32_t d = ((k - kb) >> shift) & (NDIG - 1);
         uint32_t dst = sbase + gbase[d] + (lp - lstart[d]);
@@ -472,11 +472,17 @@ struct SortBufs {
 };
 
 // The scatter of a pass from buffer pair cur into cur ^ 1 (hist and totals
-// already scanned).
+// already scanned).  A pass's blocks hold SORT_THREADS * ITEMS keys; the
+// scatter takes each with SCATTER_THREADS threads (wider workgroups: more
+// waves per CU hide the latency of its ranking and staging steps).
+constexpr int SCATTER_THREADS = 512;
 template <int ITEMS, int BITS, bool DROP>
 void scatter_launch(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols,
                     uint32_t *hist, uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS, DROP>), dim3(ncols), dim3(SORT_THREADS), 0, s,
+    constexpr int IT = ITEMS * SORT_THREADS / SCATTER_THREADS;
+    static_assert(IT >= 1 && IT * SCATTER_THREADS == ITEMS * SORT_THREADS, "same block of keys");
+    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS>), dim3(ncols),
+                       dim3(SCATTER_THREADS), 0, s,
                        b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], st, shift, hist, totals,
                        n_kept);
 }
