@@ -118,10 +118,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
     __shared__ uint64_t lds[WAVES];
     // the block partials before this block, and all of them
     uint64_t before = 0, all = 0;
-    for (uint32_t i = threadIdx.x; i < nparts; i += SORT_THREADS) {
-        const uint64_t v = part[i];
-        all += v;
-        before += i < blockIdx.x ? v : 0ull;
+    for (uint32_t i0 = threadIdx.x; i0 < nparts; i0 += 4 * SORT_THREADS) {
+        uint64_t v[4];  // four loads in flight (index clamped; nparts >= 1 here)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t i = i0 + r * SORT_THREADS;
+            v[r] = part[i < nparts ? i : nparts - 1];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t i = i0 + r * SORT_THREADS;
+            if (i < nparts) {
+                all += v[r];
+                before += i < blockIdx.x ? v[r] : 0ull;
+            }
+        }
     }
     uint64_t ex0;
     const uint64_t pre = block_excl_scan<uint64_t>(before, ex0, lds);
@@ -262,12 +273,12 @@ __device__ __forceinline__ bool seg_block(const SegTable &st, uint32_t b, int &s
     return false;
 }
 
-template <int ITEMS, int BITS, bool DROP>
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
+template <int ITEMS, int BITS, bool DROP, int NT>
+__global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              SegTable st, int shift,
                                                              uint32_t *__restrict__ hist) {
     constexpr int NDIG = 1 << BITS;
-    constexpr int TILE = SORT_THREADS * ITEMS;
+    constexpr int TILE = NT * ITEMS;
     __shared__ uint32_t h[NDIG];
     int sg;
     uint32_t lb, base, n, col0;
@@ -279,14 +290,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
     uint32_t kv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const size_t i = b0 + (size_t)k * SORT_THREADS + threadIdx.x;
+        const size_t i = b0 + (size_t)k * NT + threadIdx.x;
         kv[k] = keys[base + (i < n ? i : (size_t)n - 1)];
     }
     if (threadIdx.x < NDIG) h[threadIdx.x] = 0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const size_t i = b0 + (size_t)k * SORT_THREADS + threadIdx.x;
+        const size_t i = b0 + (size_t)k * NT + threadIdx.x;
         if (i < n && (!DROP || kv[k] != DROP_KEY))
             atomicAdd(&h[((kv[k] - kb) >> shift) & (NDIG - 1)], 1u);
     }
@@ -491,8 +502,9 @@ template <int ITEMS, int BITS, bool DROP>
 void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols, uint32_t *hist,
                 uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
     constexpr int TILE = SORT_THREADS * ITEMS;
-    hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS, DROP>), dim3(ncols), dim3(SORT_THREADS), 0, s,
-                       b.k[cur], st, shift, hist);
+    constexpr int IT = TILE / SCATTER_THREADS;  // the histogram takes the same wide workgroups
+    hipLaunchKernelGGL((k_radix_hist<IT, BITS, DROP, SCATTER_THREADS>), dim3(ncols),
+                       dim3(SCATTER_THREADS), 0, s, b.k[cur], st, shift, hist);
     hipLaunchKernelGGL(k_hist_rows<TILE>, dim3(1 << BITS, st.nseg), dim3(SORT_THREADS), 0, s, hist,
                        st, ncols, totals);
     scatter_launch<ITEMS, BITS, DROP>(b, cur, st, shift, ncols, hist, totals, n_kept, s);
