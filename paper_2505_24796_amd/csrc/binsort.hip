@@ -36,7 +36,7 @@ constexpr int TILE_ITEMS = 16;
 // blocks of twice as many keys (longer runs of equal digits per block to
 // write; below it, more and shorter blocks measure faster)
 constexpr int TILE_ITEMS_BIG = 32;
-constexpr uint32_t BIG_SORT_CAP = 32u << 20;
+constexpr uint32_t BIG_SORT_CAP = 24u << 20;
 // 3-sigma expansion: windows of EMIT_TILE output slots, 512 threads of 4
 // slots each (the window's staged Gaussians fill 33 KB of LDS, so wider
 // workgroups are what keeps more waves per CU in flight)

@@ -105,7 +105,7 @@ def test_fullsize_sampled(workload, poses, precs):
 
 
 def test_tile_sort_block_sizes_agree():
-    """A one-view call with room for 32M+ splats sorts by tile in 8192-key
+    """A one-view call with room for 24M+ splats sorts by tile in 8192-key
     blocks, smaller ones in 4096-key blocks: the 1080p/1M lists (3-sigma and
     precise) are the same either way."""
     cfg = scenegen.CONFIGS["fwd_1080p_1M"]
@@ -119,9 +119,9 @@ def test_tile_sort_block_sizes_agree():
         kw = dict(conics=pre["conics"], opacities=opac, precise=True) if precise else {}
         small = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, **kw)
         N = small.n_splats()
-        big = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, capacity=(32 << 20) + 5,
+        big = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, capacity=(24 << 20) + 5,
                           **kw)
-        say(f"  precise={precise}: N={N}, capacities {N} and {(32 << 20) + 5}")
+        say(f"  precise={precise}: N={N}, capacities {N} and {(24 << 20) + 5}")
         assert big.n_splats() == N
         assert torch.equal(big.ranges, small.ranges)
         assert torch.equal(big.sorted_ids[:N], small.sorted_ids[:N])
