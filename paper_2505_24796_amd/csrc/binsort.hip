@@ -207,9 +207,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
 // values over independent segments of the arrays (the views of a multi-view
 // frame; one segment for a single image): per-block digit histograms ->
 // per-(segment, digit) scan over the segment's blocks -> scatter.  Each
-// segment is split into blocks of ITEMS * SORT_THREADS keys; workgroup b of
-// a pass takes block b of the concatenation of the segments' blocks (idle
-// past the last one), so one launch serves every segment.
+// segment is split into blocks of TILE keys (the kernels' NT threads times
+// ITEMS keys each); workgroup b of a launch takes block b of the
+// concatenation of the segments' blocks (idle past the last one), so one
+// launch serves every segment.
 // ---------------------------------------------------------------------------
 // With DROP, keys equal to DROP_KEY are left out (counted nowhere, written
 // nowhere): the pass also compacts.
