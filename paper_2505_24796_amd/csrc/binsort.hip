@@ -23,8 +23,11 @@
 namespace {
 
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per block
+// the counts and scan kernels: blocks of SORT_TILE counts, COUNT_THREADS
+// threads of SORT_ITEMS each
+constexpr int COUNT_THREADS = 512;
+constexpr int SORT_ITEMS = 8;
+constexpr int SORT_TILE = COUNT_THREADS * SORT_ITEMS;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int WAVES = SORT_THREADS / 64;
@@ -105,7 +108,7 @@ template <typename T> __device__ __forceinline__ T block_excl_scan(T v, T &excl,
 // window of `win` output slots, the Gaussian that owns the window's first
 // slot.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__restrict__ cnt,
+__global__ __launch_bounds__(COUNT_THREADS) void k_scan_down(const uint32_t *__restrict__ cnt,
                                                             uint32_t *__restrict__ offs, uint32_t n,
                                                             const uint64_t *__restrict__ part,
                                                             uint32_t nparts,
@@ -115,19 +118,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
                                                             uint32_t *__restrict__ seg_bounds,
                                                             int nv, uint32_t Pv) {
     const uint64_t win = 1ull << wshift;  // window size (a power of two)
-    __shared__ uint64_t lds[WAVES];
+    __shared__ uint64_t lds[COUNT_THREADS / 64];
     // the block partials before this block, and all of them
     uint64_t before = 0, all = 0;
-    for (uint32_t i0 = threadIdx.x; i0 < nparts; i0 += 4 * SORT_THREADS) {
+    for (uint32_t i0 = threadIdx.x; i0 < nparts; i0 += 4 * COUNT_THREADS) {
         uint64_t v[4];  // four loads in flight (index clamped; nparts >= 1 here)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const uint32_t i = i0 + r * SORT_THREADS;
+            const uint32_t i = i0 + r * COUNT_THREADS;
             v[r] = part[i < nparts ? i : nparts - 1];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const uint32_t i = i0 + r * SORT_THREADS;
+            const uint32_t i = i0 + r * COUNT_THREADS;
             if (i < nparts) {
                 all += v[r];
                 before += i < blockIdx.x ? v[r] : 0ull;
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_down(const uint32_t *__re
     static_assert(SORT_ITEMS % 4 == 0, "16-byte loads");
     uint32_t v[SORT_ITEMS];
     uint64_t s = 0;
-    if (base + SORT_ITEMS <= n) {  // (cnt is 256-byte aligned, base a multiple of 16)
+    if (base + SORT_ITEMS <= n) {  // (cnt is 256-byte aligned, base a multiple of SORT_ITEMS)
 #pragma unroll
         for (int k = 0; k < SORT_ITEMS; k += 4) {
             const uint4 q = *(const uint4 *)(cnt + base + k);
@@ -811,14 +814,14 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
 // zero past the n_vis[v] instances of view v that have splats), and each
 // block's sum of counts.
 template <bool PRECISE, bool MULTI>
-__global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *__restrict__ order,
+__global__ __launch_bounds__(COUNT_THREADS) void k_counts(int P, const uint32_t *__restrict__ order,
                                                          const uint2 *__restrict__ rects,
                                                          const uint32_t *__restrict__ cnt_g,
                                                          uint2 *__restrict__ rects_sorted,
                                                          uint32_t *__restrict__ cnt,
                                                          const uint32_t *__restrict__ n_vis,
                                                          uint64_t *__restrict__ part, ViewRef vt) {
-    __shared__ uint64_t lds[WAVES];
+    __shared__ uint64_t lds[COUNT_THREADS / 64];
     const size_t base = (size_t)blockIdx.x * SORT_TILE;
     uint64_t sum = 0;
     const uint32_t nvis0 = n_vis[0];
@@ -831,7 +834,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
     bool has[SORT_ITEMS];
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        const size_t j = base + (size_t)k * SORT_THREADS + threadIdx.x;
+        const size_t j = base + (size_t)k * COUNT_THREADS + threadIdx.x;
         const size_t jc = j < (size_t)P ? j : (size_t)P - 1;
         const int v = vt.view_of<MULTI>((uint32_t)jc);
         has[k] = j < (size_t)P && jc - (size_t)v * vt.P < (MULTI ? n_vis[v] : nvis0);
@@ -847,7 +850,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_counts(int P, const uint32_t *
     }
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        const size_t j = base + (size_t)k * SORT_THREADS + threadIdx.x;
+        const size_t j = base + (size_t)k * COUNT_THREADS + threadIdx.x;
         if (j < (size_t)P) {
             const uint2 rr = has[k] ? r[k] : make_uint2(0u, 0u);
             const uint32_t c = !has[k] ? 0u : PRECISE ? cg[k] : (rr.y & 0xFFFFu) * (rr.y >> 16);
@@ -1475,7 +1478,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     {
         auto kc = precise ? (nv > 1 ? k_counts<true, true> : k_counts<true, false>)
                           : (nv > 1 ? k_counts<false, true> : k_counts<false, false>);
-        hipLaunchKernelGGL(kc, dim3(sblocks), dim3(SORT_THREADS), 0, s, n, order,
+        hipLaunchKernelGGL(kc, dim3(sblocks), dim3(COUNT_THREADS), 0, s, n, order,
                            (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
                            (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part,
                            vt);
@@ -1484,7 +1487,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     static_assert((EMIT_TILE & (EMIT_TILE - 1)) == 0 && (EMIT_TILE_P & (EMIT_TILE_P - 1)) == 0,
                   "windows are powers of two");
     uint32_t *bounds = U(L.bounds);
-    hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(SORT_THREADS), 0, s, U(L.cnt), U(L.offs),
+    hipLaunchKernelGGL(k_scan_down, dim3(sblocks), dim3(COUNT_THREADS), 0, s, U(L.cnt), U(L.offs),
                        (uint32_t)n, (const uint64_t *)part, sblocks, U(L.win), L.nwin,
                        ceil_log2(win), d_num_splats, bounds, nv, (uint32_t)P);
     if (d_view_splats)
