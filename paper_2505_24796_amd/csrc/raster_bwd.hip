@@ -286,12 +286,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const uint32_t nscan = min(end - start, last);
     const int nb = (int)((nscan + BATCH - 1) / BATCH);
     const float4 *rgbs = (const float4 *)(stage + Stage<VAR>::A1 + Stage<VAR>::A2);
+    // the splat ids of each batch are loaded one round ahead (one register;
+    // gathering the whole next batch ahead measured no better)
+    uint32_t id_next = 0u;
+    if (nb > 0) {
+        const uint32_t q = (uint32_t)(nb - 1) * BATCH + threadIdx.x;
+        id_next = q < nscan ? a.f.ids[start + q] : 0u;
+    }
     for (int b = nb - 1; b >= 0; --b) {
         // splats of batch b (only positions up to the tile's last blended one
         // can contribute; the staging of the rest matches the forward's)
-        const uint32_t kb = start + (uint32_t)b * BATCH + threadIdx.x;
         const bool in_scan = (uint32_t)b * BATCH + threadIdx.x < nscan;
-        SplatRegs cur = gather(a.f, in_scan ? a.f.ids[kb] : 0u, in_scan);
+        const uint32_t my_id = id_next;
+        SplatRegs cur = gather(a.f, my_id, in_scan);
+        if (b > 0) {
+            const uint32_t q = (uint32_t)(b - 1) * BATCH + threadIdx.x;
+            id_next = q < nscan ? a.f.ids[start + q] : 0u;
+        }
         const bool keep = tile_alive(cur, bx0, by0);
         const uint64_t kmask = __ballot(keep);
         __syncthreads();  // previous batch fully consumed
@@ -310,7 +321,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             const int jj = wofs + (int)gs::lanes_below(kmask);
             stage_splat<VAR>(stage, jj, cur, ox, oy, (uint32_t)b * BATCH + threadIdx.x);
             s_p0[jj] = make_float4(cur.mu.x, cur.mu.y, cur.s11, cur.s12);
-            s_p1[jj] = make_float4(cur.s22, cur.o, __uint_as_float(a.f.ids[kb]), 0.0f);
+            s_p1[jj] = make_float4(cur.s22, cur.o, __uint_as_float(my_id), 0.0f);
         }
         __syncthreads();
         const int nsub = (total + SUB - 1) / SUB;
