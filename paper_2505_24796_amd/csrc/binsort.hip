@@ -710,11 +710,12 @@ __device__ __forceinline__ RectDec dec_rect(uint2 r) {
     return RectDec{(int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu), (int)(r.y >> 16)};
 }
 
-// Depth keys, the packed tile rectangle and the splat count of every
-// Gaussian (coalesced; with PRECISE the count is that of the precise rule
-// and the ellipse parameters are kept for the emission); also clears the
-// tile ranges.  A Gaussian without splats gets the largest key, so it sorts
-// after every Gaussian that has splats.
+// Depth keys and the packed tile rectangle of every Gaussian (coalesced);
+// with PRECISE, a 16-byte record {rectangle, precise splat count, 0} (one
+// gather for the counts kernel) and the ellipse parameters for the
+// emission.  Also clears the tile ranges.  A Gaussian without splats gets
+// the largest key, so it sorts after every Gaussian that has splats.
+// `rects` holds uint2 rectangles, or with PRECISE uint4 records.
 template <bool PRECISE, bool MULTI>
 __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restrict__ means2d,
                                                     const int *__restrict__ radii,
@@ -723,8 +724,7 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     const float *__restrict__ opac, ViewRef vt,
                                                     uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
-                                                    uint2 *__restrict__ rects,
-                                                    uint32_t *__restrict__ cnt_g,
+                                                    void *__restrict__ rects,
                                                     PGauss *__restrict__ pg,
                                                     uint32_t *__restrict__ ranges, int n2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -804,10 +804,13 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
     }
     keys[i] = c > 0 ? depth_key(d) : 0xFFFFFFFFu;
     ids[i] = (uint32_t)i;
-    rects[i] = c > 0 ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
-                                  (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16))
-                     : make_uint2(0u, 0u);
-    cnt_g[i] = c;
+    const uint2 r = c > 0 ? make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16),
+                                       (uint32_t)(tx1 - tx0 + 1) | ((uint32_t)(ty1 - ty0 + 1) << 16))
+                          : make_uint2(0u, 0u);
+    if (PRECISE)
+        ((uint4 *)rects)[i] = make_uint4(r.x, r.y, c, 0u);
+    else
+        ((uint2 *)rects)[i] = r;
 }
 
 // Rectangle and splat count of each instance in depth order (view by view;
@@ -815,8 +818,7 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
 // block's sum of counts.
 template <bool PRECISE, bool MULTI>
 __global__ __launch_bounds__(COUNT_THREADS) void k_counts(int P, const uint32_t *__restrict__ order,
-                                                         const uint2 *__restrict__ rects,
-                                                         const uint32_t *__restrict__ cnt_g,
+                                                         const void *__restrict__ rects,
                                                          uint2 *__restrict__ rects_sorted,
                                                          uint32_t *__restrict__ cnt,
                                                          const uint32_t *__restrict__ n_vis,
@@ -845,8 +847,14 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_counts(int P, const uint32_t 
     uint32_t cg[SORT_ITEMS];
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        r[k] = rects[g[k]];
-        cg[k] = PRECISE ? cnt_g[g[k]] : 0u;
+        if (PRECISE) {
+            const uint4 q = ((const uint4 *)rects)[g[k]];
+            r[k] = make_uint2(q.x, q.y);
+            cg[k] = q.z;
+        } else {
+            r[k] = ((const uint2 *)rects)[g[k]];
+            cg[k] = 0u;
+        }
     }
 #pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
@@ -1259,7 +1267,7 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tke
 // Workspace carve-up (every region 256-byte aligned) for n = V * P
 // instances and room for `cap` splats.
 struct Layout {
-    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt_g, cnt, offs, pg, tkey0, tkey1, tid,
+    size_t dkey0, dkey1, did0, did1, rects, rects_sorted, cnt, offs, pg, tkey0, tkey1, tid,
         hist, totals, nvis, bounds, vdims, part, win, total;
     uint32_t nwin, ncols_depth, ncols_tile;
 };
@@ -1288,11 +1296,10 @@ Layout layout(uint32_t nv, uint32_t P, uint32_t cap, bool precise) {
     L.dkey1 = take(4 * n);
     L.did0 = take(4 * n);
     L.did1 = take(4 * n);
-    L.rects = take(8 * n);
+    L.rects = take((precise ? 16 : 8) * n);  // uint2 rectangles, or {rectangle, count} records
     L.rects_sorted = take(8 * n);
     L.cnt = take(4 * n);
     L.offs = take(4 * n);
-    L.cnt_g = take(4 * n);
     L.pg = take(precise ? sizeof(PGauss) * n : 0);
     L.tkey0 = take(4ull * cap);
     L.tkey1 = take(4ull * cap);
@@ -1442,8 +1449,8 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
         hipLaunchKernelGGL((k_depth_keys<false, false>), dim3((2 * ntiles + 255) / 256), dim3(256), 0, s,
                            0, (const float2 *)nullptr, (const int *)nullptr,
                            (const float *)nullptr, (const float *)nullptr, (const float *)nullptr,
-                           vt, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint2 *)nullptr,
-                           (uint32_t *)nullptr, (PGauss *)nullptr, tile_ranges, 2 * ntiles);
+                           vt, (uint32_t *)nullptr, (uint32_t *)nullptr, (void *)nullptr,
+                           (PGauss *)nullptr, tile_ranges, 2 * ntiles);
         // a kernel rather than a memset node, so the call can be graph-captured
         hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, s, d_num_splats, 0u);
         if (d_view_splats)
@@ -1459,8 +1466,8 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
         auto kk = precise ? (nv > 1 ? k_depth_keys<true, true> : k_depth_keys<true, false>)
                           : (nv > 1 ? k_depth_keys<false, true> : k_depth_keys<false, false>);
         hipLaunchKernelGGL(kk, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2, radii, depths,
-                           conics, opacities, vt, U(L.dkey0), U(L.did0), (uint2 *)(ws + L.rects),
-                           U(L.cnt_g), pg, tile_ranges, 2 * ntiles);
+                           conics, opacities, vt, U(L.dkey0), U(L.did0), (void *)(ws + L.rects),
+                           pg, tile_ranges, 2 * ntiles);
     }
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
     // one segment of P per view; Gaussians without splats (key DROP_KEY)
@@ -1479,7 +1486,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
         auto kc = precise ? (nv > 1 ? k_counts<true, true> : k_counts<true, false>)
                           : (nv > 1 ? k_counts<false, true> : k_counts<false, false>);
         hipLaunchKernelGGL(kc, dim3(sblocks), dim3(COUNT_THREADS), 0, s, n, order,
-                           (const uint2 *)(ws + L.rects), (const uint32_t *)U(L.cnt_g),
+                           (const void *)(ws + L.rects),
                            (uint2 *)(ws + L.rects_sorted), U(L.cnt), (const uint32_t *)n_vis, part,
                            vt);
     }
