@@ -997,8 +997,8 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
 //
 // With HIST (one view), the window also counts its keys' lowest digit (key &
 // dmask, at most RADIX digits) for the first tile pass and writes the counts
-// to hist2[d * gridDim.x + window], so that pass needs no histogram kernel of
-// its own; windows past the splats write nothing.
+// to hist2[window * RADIX + d], so that pass needs no histogram kernel of its
+// own; windows past the splats write nothing.
 template <bool MULTI, bool HIST>
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ offs,
@@ -1031,20 +1031,20 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__
         emit_slots<MULTI, HIST>(s0, oend, s_off, s_rect, s_id, m, vt, tkey, tid, dmask, hcount);
     if (HIST) {
         __syncthreads();
-        if (threadIdx.x <= dmask)
-            hist2[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = hcount[threadIdx.x];
+        if (threadIdx.x <= dmask)  // one contiguous row of counts per window
+            hist2[(size_t)blockIdx.x * RADIX + threadIdx.x] = hcount[threadIdx.x];
     }
 }
 
 // Workgroup d: digit d's counts of the first tile pass per block of BLK
 // keys (the sum of the counts of the block's G = BLK / WIN
 // emission windows of WIN slots, from hist2 as k_emit<false, true> wrote
-// it over nw_cols windows), scanned exclusively over the blocks into
+// it: one row of RADIX counts per window), scanned exclusively over the blocks into
 // hist[d * ncols + block]; the total goes to totals[d].  One segment (one
 // view).
 template <int WIN, int BLK>
 __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32_t *__restrict__ hist2,
-                                                                    uint32_t nw_cols, SegTable st,
+                                                                    SegTable st,
                                                                     uint32_t ncols,
                                                                     uint32_t *__restrict__ hist,
                                                                     uint32_t *__restrict__ totals) {
@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32
     st.get(0, base, n);
     const uint32_t nb = (n + BLK - 1u) / BLK;
     const uint32_t nw = (n + WIN - 1u) / WIN;
-    const uint32_t *src = hist2 + (size_t)blockIdx.x * nw_cols;
+    const uint32_t *src = hist2 + blockIdx.x;  // digit d of window w: src[w * RADIX]
     uint32_t *row = hist + (size_t)blockIdx.x * ncols;
     // block i's count: its windows G i .. G i + G - 1 that hold splats
     // (nw >= 1 whenever nb >= 1)
@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32
 #pragma unroll
         for (uint32_t g = 0; g < G; ++g) {
             const uint32_t w = G * i + g;
-            const uint32_t x = src[w < nw ? w : nw - 1u];
+            const uint32_t x = src[(size_t)(w < nw ? w : nw - 1u) * RADIX];
             v += w < nw ? x : 0u;
         }
         return v;
@@ -1386,17 +1386,17 @@ extern "C" size_t gs_bin_sort_multiview_workspace_bytes(int32_t nviews, int32_t 
 namespace {
 
 // The tile sort of a call, ITEMS keys per thread.  With emit_hist, the
-// expansion has counted the first pass's digits per window into hist2
-// (eblocks windows): the pass then only scans and scatters.  Returns the
-// buffer pair holding the result.
+// expansion has counted the first pass's digits per window into hist2: the
+// pass then only scans and scatters.  Returns the buffer pair holding the
+// result.
 template <int ITEMS>
 int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool emit_hist,
-              const uint32_t *hist2, uint32_t eblocks, uint32_t *hist, uint32_t *totals,
+              const uint32_t *hist2, uint32_t *hist, uint32_t *totals,
               hipStream_t s) {
     if (emit_hist) {
         const int w0 = radix_width(tbits, 0);
         hipLaunchKernelGGL((k_hist_rows_windows<EMIT_TILE, SORT_THREADS * ITEMS>), dim3(1 << w0),
-                           dim3(SORT_THREADS), 0, s, hist2, eblocks, st, ncols, hist, totals);
+                           dim3(SORT_THREADS), 0, s, hist2, st, ncols, hist, totals);
         switch (w0) {
         case 4: scatter_launch<ITEMS, 4, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
         case 5: scatter_launch<ITEMS, 5, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
@@ -1542,9 +1542,9 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     // within the view)
     int tcur = tile_items((uint32_t)nv, capacity) == TILE_ITEMS_BIG
                    ? tile_sort<TILE_ITEMS_BIG>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
-                                               eblocks, U(L.hist), U(L.totals), s)
+                                               U(L.hist), U(L.totals), s)
                    : tile_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
-                                           eblocks, U(L.hist), U(L.totals), s);
+                                           U(L.hist), U(L.totals), s);
     // 4. ranges (tile indices are unique across views)
     Count nc{0u, d_num_splats, capacity};
     uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
