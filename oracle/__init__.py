@@ -6,9 +6,9 @@ module; the product library never does, and this module never imports the
 product package.  See ``gs_oracle.c`` for what each function computes and
 which passage of the TC-GS paper it follows.
 
-Functions whose correctness is pinned only by agreement with the GPU (and by
-textbook checks) rather than by a value the paper fixes are marked
-"parity unpinned" below.
+Every function here is pinned in ``tests/test_oracle_pins.py`` by closed
+forms, invariants, brute force or library routines written independently of
+``gs_oracle.c``; none is left "parity unpinned".
 """
 from __future__ import annotations
 
@@ -111,8 +111,11 @@ def sh_basis(dirs: np.ndarray, deg: int = 3) -> np.ndarray:
 
 
 def preprocess_3d(scene, cam) -> dict:
-    """FP64 projection of a 3D scene (parity unpinned against the paper, which
-    prints no projection example; pinned by textbook checks in the tests)."""
+    """FP64 projection of a 3D scene.  The paper prints no projection example,
+    so the conventions are readings; their implementation is pinned by
+    independent routes in the tests (Hamilton-product rotations, Rodrigues'
+    formula for the SH basis, finite-difference Jacobians including the
+    frustum-guard clamp)."""
     P = scene.P
     means, scales, quats = _f32(scene.means), _f32(scene.scales), _f32(scene.quats)
     sh = _f32(scene.sh.reshape(P, 48))

@@ -14,7 +14,7 @@
  *   - conditional alpha-blending                         (Sec. 3.1, Algorithm 1,
  *                                                          eqs. alpha_raw, vanilla
  *                                                          pruning, alpha-blending)
- *   - fragment categories culled / blended / skipped     (Sec. 3.2, Table 1)
+ *   - fragment categories culled / blended / skipped     (Sec. 3.2, Table 2)
  *   - exponent form beta = ln o - 1/2 d^T S d            (Sec. 4.1, EarlyCull)
  *   - Frag2Mat coefficients v0..v5 and B = U^T V         (Sec. 4.2)
  *   - G2L local coordinates about the tile centre        (Sec. 4.3)
@@ -41,9 +41,15 @@
  *
  * Pins: Algorithm 1, binning and the emulated exponent are pinned by closed
  * forms, invariants, brute force and library routines in the tests.  The 3D
- * projection conventions above are readings (the paper prints no projection
- * example): parity unpinned against the paper, checked only by textbook
- * properties (optical axis, isotropic size, finite-difference Jacobian).
+ * projection conventions above are readings of the 3DGS pipeline the paper
+ * builds on (it prints no projection example); how this file implements each
+ * of them is pinned by a route that shares nothing with the code below:
+ * R(q) by rotations built from Hamilton products and a closed-form rotation
+ * about a world axis, the SH basis function by function by Rodrigues'
+ * formula for the associated Legendre functions plus the addition theorem,
+ * Sigma' by finite-difference Jacobians of the pinhole map (at the clamped
+ * point outside the guard band), and the optical axis and isotropic size by
+ * closed forms.
  *
  * Everything here is double precision except where a function emulates the
  * rounding of a reduced-precision format on purpose (the *_emu modes), which

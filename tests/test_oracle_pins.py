@@ -186,7 +186,7 @@ def test_emulated_beta_identity_and_bound(orc, mode, unit):
 
 
 def test_global_fp16_collapses_local_recovers(orc):
-    """Sec. 4.3 / Table 5: FP16 in global coordinates loses beta (quadratic
+    """Sec. 4.3 / Table 6: FP16 in global coordinates loses beta (quadratic
     terms of size w^2), local coordinates keep it at O(w + h) eps."""
     g = np.random.default_rng(5)
     err_g, err_l = [], []
@@ -351,6 +351,219 @@ def test_preprocess_3d_near_plane_and_rotation_invariance(orc):
     out = orc.preprocess_3d(sc, cam)
     assert out["radii"][0] == 0 and out["radii"][1] == 0   # depth 0.1 and -5
     np.testing.assert_allclose(out["cov2d"][2], out["cov2d"][3], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- R(q) -----
+def _hamilton(p, q):
+    """Hamilton product of quaternions (w, x, y, z)."""
+    w1, x1, y1, z1 = p
+    w2, x2, y2, z2 = q
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
+                     w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
+                     w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def _rotate(q, v):
+    """v rotated by the unit quaternion q as the product q (0, v) q*."""
+    q = np.asarray(q, np.float64) / np.linalg.norm(q)
+    qc = q * np.array([1.0, -1.0, -1.0, -1.0])
+    return _hamilton(_hamilton(q, np.concatenate([[0.0], v])), qc)[1:]
+
+
+def _cov2d_expected(cam, mean, Sigma, h=1e-5):
+    """Sigma' = J Sigma J^T + 0.3 I with J the central finite-difference
+    Jacobian of the pinhole map world -> pixel at the mean (Sec. 3.1)."""
+    V = cam.viewmat.astype(np.float64)
+
+    def proj(x):
+        t = V[:3, :3] @ x + V[:3, 3]
+        return np.array([cam.fx * t[0] / t[2] + cam.cx, cam.fy * t[1] / t[2] + cam.cy])
+
+    J = np.stack([(proj(mean + h * e) - proj(mean - h * e)) / (2 * h) for e in np.eye(3)], 1)
+    C2 = J @ Sigma @ J.T + 0.3 * np.eye(2)
+    return np.array([C2[0, 0], C2[0, 1], C2[1, 1]])
+
+
+def _scene(means, scales, quats, opac=None, sh=None):
+    P = len(means)
+    return scenegen.Scene3D(means=np.asarray(means, np.float32), scales=np.asarray(scales, np.float32),
+                            quats=np.asarray(quats, np.float32),
+                            opacities=np.full(P, 0.5, np.float32) if opac is None else np.asarray(opac, np.float32),
+                            sh=np.zeros((P, 16, 3), np.float32) if sh is None else sh)
+
+
+def test_rotation_from_hamilton_products(orc):
+    """R(q) enters Sigma = R diag(s^2) R^T.  Here R is built column by column
+    from the quaternion rotation v -> q v q* (Hamilton products, a route that
+    shares nothing with a matrix formula), so a transposed or mis-signed R(q)
+    changes the anisotropic 2D covariance and fails.  Non-unit quaternions
+    are normalised first (the same result for q and 3.7 q)."""
+    cam = scenegen.orbit_camera(0, 1, 640, 480)
+    g = np.random.default_rng(31)
+    P = 12
+    means = np.column_stack([g.uniform(-2, 2, P), g.uniform(-1.5, 1.5, P), g.uniform(-3, 3, P)])
+    scales = np.exp(g.uniform(np.log(0.02), np.log(0.3), (P, 3)))
+    quats = g.standard_normal((P, 4))
+    quats[1::2] *= 3.7  # not normalised on input
+    sc = _scene(means, scales, quats)
+    out = orc.preprocess_3d(sc, cam)
+    assert (out["radii"] > 0).all()
+    for i in range(P):
+        q = sc.quats[i].astype(np.float64)
+        R = np.stack([_rotate(q, e) for e in np.eye(3)], 1)
+        # sanity of the independent route: orthonormal, det +1, composition
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-12)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-12
+        Sigma = R @ np.diag(sc.scales[i].astype(np.float64) ** 2) @ R.T
+        want = _cov2d_expected(cam, sc.means[i].astype(np.float64), Sigma)
+        np.testing.assert_allclose(out["cov2d"][i], want, rtol=1e-6)
+    q1, q2 = quats[0] / np.linalg.norm(quats[0]), quats[2] / np.linalg.norm(quats[2])
+    R1 = np.stack([_rotate(q1, e) for e in np.eye(3)], 1)
+    R2 = np.stack([_rotate(q2, e) for e in np.eye(3)], 1)
+    R12 = np.stack([_rotate(_hamilton(q1, q2), e) for e in np.eye(3)], 1)
+    np.testing.assert_allclose(R12, R1 @ R2, atol=1e-12)
+
+
+@pytest.mark.parametrize("deg", [30.0, -50.0])
+def test_rotation_about_world_axis_closed_form(orc, deg):
+    """A needle-like Gaussian (std s along its own x axis, eps across) turned
+    by +theta about the world z axis (q = (cos theta/2, 0, 0, sin theta/2))
+    points along (cos theta, sin theta, 0).  Seen by the pose-0 orbit camera
+    (camera x = world x, camera y = -world y) at the optical axis, depth 15:
+    Sigma' = (f/15)^2 s^2 [[c^2, -c s_], [-c s_, s_^2]] + eps terms + 0.3 I.
+    The sign of the off-diagonal pins the direction of rotation."""
+    cam = scenegen.orbit_camera(0, 1, 640, 480)
+    th = math.radians(deg)
+    s, eps = 0.4, 0.01
+    q = [math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)]
+    out = orc.preprocess_3d(_scene([[0, 0, 0]], [[s, eps, eps]], [q]), cam)
+    k = (cam.fx / 15.0) ** 2
+    c, sn = math.cos(th), math.sin(th)
+    # the eps axis in the image plane is (-sin, cos) in world -> (-sin, -cos) in camera
+    want = [k * (s * s * c * c + eps * eps * sn * sn) + 0.3,
+            k * (-s * s * c * sn + eps * eps * sn * c),
+            k * (s * s * sn * sn + eps * eps * c * c) + 0.3]
+    # inputs are stored as float32 (relative rounding ~6e-8)
+    np.testing.assert_allclose(out["cov2d"][0], want, rtol=1e-6)
+    assert np.sign(out["cov2d"][0][1]) == -np.sign(sn)
+
+
+# ---------------------------------------------------------------- SH l=2,3 -
+def _legendre_rodrigues(l, m, x):
+    """Associated Legendre function with the Condon-Shortley phase from
+    Rodrigues' formula: P_l(x) = 1/(2^l l!) d^l/dx^l (x^2 - 1)^l and
+    P_l^m(x) = (-1)^m (1 - x^2)^(m/2) d^m/dx^m P_l(x) (exact polynomial
+    derivatives, no recurrence)."""
+    from numpy.polynomial import polynomial as Pn
+    c = Pn.polypow([-1.0, 0.0, 1.0], l)
+    c = Pn.polyder(c, l + m) / (2.0 ** l * math.factorial(l))
+    return (-1.0) ** m * (1.0 - x * x) ** (m / 2.0) * Pn.polyval(x, c)
+
+
+def test_sh_each_function_from_rodrigues(orc):
+    """Every real SH function of degrees 0..3 (index l*l + l + m) equals
+    sqrt(2) K_lm P_l^m(cos t) cos(m phi) for m > 0, sqrt(2) K_l|m|
+    P_l^|m|(cos t) sin(|m| phi) for m < 0 and K_l0 P_l(cos t) for m = 0,
+    K_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), with P_l^m from Rodrigues'
+    formula above.  Pins sign and order within each degree, which
+    orthonormality alone leaves free."""
+    g = np.random.default_rng(8)
+    dirs = g.standard_normal((64, 3))
+    dirs = np.vstack([dirs, [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, -1, 0]]])
+    Y = orc.sh_basis(dirs, 3)
+    for i, d in enumerate(dirs):
+        x, y, z = d / np.linalg.norm(d)
+        phi = math.atan2(y, x)
+        for l in range(4):
+            for m in range(-l, l + 1):
+                am = abs(m)
+                K = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
+                P = _legendre_rodrigues(l, am, z)
+                if m > 0:
+                    want = math.sqrt(2) * K * P * math.cos(am * phi)
+                elif m < 0:
+                    want = math.sqrt(2) * K * P * math.sin(am * phi)
+                else:
+                    want = K * P
+                assert abs(Y[i, l * l + l + m] - want) < 1e-13, (l, m, Y[i, l * l + l + m], want)
+
+
+def test_sh_addition_theorem(orc):
+    """For each degree l: sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a . b)
+    (P_l from numpy's Legendre series), which holds for any orthonormal real
+    basis of the degree and so pins each degree's span and normalisation."""
+    from numpy.polynomial import legendre
+    g = np.random.default_rng(9)
+    a = g.standard_normal((40, 3))
+    b = g.standard_normal((40, 3))
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    b /= np.linalg.norm(b, axis=1, keepdims=True)
+    Ya, Yb = orc.sh_basis(a, 3), orc.sh_basis(b, 3)
+    for l in range(4):
+        sl = slice(l * l, (l + 1) * (l + 1))
+        lhs = np.sum(Ya[:, sl] * Yb[:, sl], axis=1)
+        cos = np.sum(a * b, axis=1)
+        rhs = (2 * l + 1) / (4 * math.pi) * legendre.legval(cos, [0] * l + [1])
+        np.testing.assert_allclose(lhs, rhs, atol=1e-13)
+
+
+# ---------------------------------------------------------------- guard ----
+@pytest.mark.parametrize("side", ["+x", "-x", "+y", "+xy"])
+def test_preprocess_3d_frustum_guard_clamp(orc, side):
+    """Outside the guard band |t_x/t_z| > 1.3 tan(fov_x/2) (likewise y), the
+    Jacobian J of the projection is taken at the camera-space point whose
+    t_x/t_z (t_y/t_z) is clamped to the band edge, depth unchanged; the mean
+    itself is projected unclamped.  Pinned with the finite-difference
+    Jacobian of the pinhole map (t -> (f t_x/t_z + c_x, f t_y/t_z + c_y)) at
+    that clamped point, and shown to differ from the unclamped Jacobian."""
+    W, H = 320, 240
+    cam = scenegen.orbit_camera(0, 1, W, H)
+    V = cam.viewmat.astype(np.float64)
+    limx, limy = 1.3 * (0.5 * W / cam.fx), 1.3 * (0.5 * H / cam.fy)
+    tz = 5.0
+    ratio = {"+x": (0.9, 0.1), "-x": (-1.1, 0.0), "+y": (0.2, 0.75), "+xy": (0.95, -0.7)}[side]
+    tcam = np.array([ratio[0] * tz, ratio[1] * tz, tz])
+    # camera -> world: x_w = R^T (t - t_wc)
+    mean = V[:3, :3].T @ (tcam - V[:3, 3])
+    scales = [0.9, 0.6, 1.2]
+    q = np.array([0.8, 0.3, -0.4, 0.33])
+    out = orc.preprocess_3d(_scene([mean], [scales], [q]), cam)
+    assert out["radii"][0] > 0, "the test Gaussian must reach the image"
+    R = np.stack([_rotate(q, e) for e in np.eye(3)], 1)
+    Sigma = R @ np.diag(np.asarray(np.float32(scales), np.float64) ** 2) @ R.T
+    m32 = np.asarray(np.float32(mean), np.float64)
+    t = V[:3, :3] @ m32 + V[:3, 3]
+    tc = np.array([np.clip(t[0] / t[2], -limx, limx) * t[2], np.clip(t[1] / t[2], -limy, limy) * t[2], t[2]])
+
+    def pin(tt):
+        return np.array([cam.fx * tt[0] / tt[2] + cam.cx, cam.fy * tt[1] / tt[2] + cam.cy])
+
+    h = 1e-6
+    Jc = np.stack([(pin(tc + h * e) - pin(tc - h * e)) / (2 * h) for e in np.eye(3)], 1)
+    Ju = np.stack([(pin(t + h * e) - pin(t - h * e)) / (2 * h) for e in np.eye(3)], 1)
+
+    def cov(J):
+        C2 = J @ V[:3, :3] @ Sigma @ V[:3, :3].T @ J.T + 0.3 * np.eye(2)
+        return np.array([C2[0, 0], C2[0, 1], C2[1, 1]])
+
+    np.testing.assert_allclose(out["cov2d"][0], cov(Jc), rtol=1e-6)
+    assert np.max(np.abs(cov(Ju) - cov(Jc)) / np.abs(cov(Jc)).max()) > 1e-2
+    np.testing.assert_allclose(out["means2d"][0], pin(t), rtol=1e-12)
+
+
+def test_preprocess_3d_invalid_inputs_dropped(orc):
+    """Gaussians whose mean, scale or quaternion is not finite (or whose
+    quaternion is zero) get radius 0 and no tiles; a finite neighbour is
+    unaffected."""
+    cam = scenegen.orbit_camera(0, 1, 320, 240)
+    nan, inf = float("nan"), float("inf")
+    means = [[0, 0, 0], [nan, 0, 0], [0, inf, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0]]
+    scales = [[0.1] * 3, [0.1] * 3, [0.1] * 3, [nan, 0.1, 0.1], [0.1, inf, 0.1], [0.1] * 3, [0.1] * 3]
+    quats = [[1, 0, 0, 0]] * 5 + [[0, 0, 0, 0], [nan, 0, 0, 1]]
+    out = orc.preprocess_3d(_scene(means, scales, quats), cam)
+    assert out["radii"][0] > 0 and out["tiles_touched"][0] > 0
+    assert (out["radii"][1:] == 0).all() and (out["tiles_touched"][1:] == 0).all()
 
 
 # ---------------------------------------------------------------- P5 / P6 --
