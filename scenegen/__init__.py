@@ -162,6 +162,32 @@ def scene_2d(P: int, width: int, height: int, seed: int, s_min: float = 0.5,
                    depths=depth.astype(np.float32), width=width, height=height)
 
 
+def scene_2d_needles(P: int, width: int, height: int, seed: int, s_major=(4.0, 30.0),
+                     ratio=(100.0, 300.0), theta_deg=(40.0, 50.0)) -> Scene2D:
+    """Pre-projected needle-like Gaussians: major std exp(U[ln lo, ln hi]) px,
+    minor std = major / exp(U[ln ratio_lo, ln ratio_hi]), rotation angle
+    U[theta_lo, theta_hi] degrees, every second one turned by a further 90
+    degrees.  Draw order: means (P x 2), major std (P), ratio (P), angle (P),
+    opacity U[0.05, 0.99] (P), rgb (P x 3), depth U[1, 100] (P).  Near 45
+    degrees the covariance entries a, c and b are of one size while
+    ac - b^2 is (ratio)^-2 smaller: the FP32 determinant cancels."""
+    g = _rng(seed)
+    mu = g.uniform(0.0, 1.0, (P, 2)) * np.array([width, height], np.float64)
+    s1 = np.exp(g.uniform(np.log(s_major[0]), np.log(s_major[1]), P))
+    s2 = s1 / np.exp(g.uniform(np.log(ratio[0]), np.log(ratio[1]), P))
+    th = np.deg2rad(g.uniform(theta_deg[0], theta_deg[1], P)) + 0.5 * np.pi * (np.arange(P) % 2)
+    o = g.uniform(0.05, 0.99, P)
+    rgb = g.uniform(0.0, 1.0, (P, 3))
+    depth = g.uniform(1.0, 100.0, P)
+    c, sn = np.cos(th), np.sin(th)
+    a = c * c * s1 ** 2 + sn * sn * s2 ** 2
+    b = c * sn * (s1 ** 2 - s2 ** 2)
+    cc = sn * sn * s1 ** 2 + c * c * s2 ** 2
+    return Scene2D(means2d=mu.astype(np.float32), cov2d=np.stack([a, b, cc], 1).astype(np.float32),
+                   opacities=o.astype(np.float32), rgb=rgb.astype(np.float32),
+                   depths=depth.astype(np.float32), width=width, height=height)
+
+
 # Workloads.  "2d" configs are pre-projected; "3d" configs go through the
 # projection stage.  Sizes follow the benchmark definitions.
 CONFIGS = {

@@ -37,71 +37,121 @@ def sample_tiles(ranges, gx, gy, n_random=24, n_heavy=8, seed=0):
     return np.unique(np.concatenate([heavy, rnd, corner])).astype(np.int32)
 
 
-@pytest.mark.parametrize("workload,poses,precs", [
-    ("fwd_1080p_1M", [0], ["fp16_g2l_split", "bf16_g2l_split", "fp16_g2l"]),
-    ("fwd_4k_6M", [0, 4], ["fp16_g2l_split", "bf16_g2l_split"]),
-])
-def test_fullsize_sampled(workload, poses, precs):
+_SCENES = {}
+
+
+def scene_of(workload):
+    if workload not in _SCENES:
+        _SCENES.clear()
+        cfg = scenegen.CONFIGS[workload]
+        say(f"{workload}: generating P={cfg['P']}")
+        sc = scenegen.make_scene(cfg)
+        _SCENES[workload] = (sc, [dev(a) for a in (sc.means, sc.scales, sc.quats, sc.sh, sc.opacities)])
+    return _SCENES[workload]
+
+
+GPU_INPUT_CASES = {("fwd_1080p_1M", 0), ("fwd_4k_6M", 0), ("fwd_4k_6M", 4)}
+
+
+@pytest.mark.parametrize("workload,pose,precs", [
+    ("fwd_1080p_1M", 0, ["fp16_g2l_split", "bf16_g2l_split", "fp16_g2l"]),
+] + [("fwd_4k_6M", k, ["fp16_g2l_split", "bf16_g2l_split"]) for k in range(10)])
+def test_fullsize_sampled(workload, pose, precs):
+    """One frame at full size in the benchmark's launch configuration.
+    (a) Against the FP64 oracle's own chain (its preprocess and binning of
+    every Gaussian, Algorithm 1 on sampled tiles): the error of the whole
+    path for FP32 and each matrix-core precision, every pose.
+    (b) For the listed poses, stage by stage on the GPU's own intermediates:
+    preprocess on a sample, exact lists on the sampled tiles, the FP32
+    raster against the admissible set."""
     cfg = scenegen.CONFIGS[workload]
     W, H = cfg["width"], cfg["height"]
     gx, gy = (W + 15) // 16, (H + 15) // 16
-    say(f"{workload}: generating P={cfg['P']}")
-    sc = scenegen.make_scene(cfg)
-    means, scales, quats, sh, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), dev(sc.opacities)
-    for pose in poses:
-        cam_np = scenegen.make_camera(cfg, pose)
-        cam = gs.make_camera(cam_np.viewmat, cam_np.fx, cam_np.fy, cam_np.cx, cam_np.cy, W, H,
-                             campos=cam_np.campos)
-        pre = gs.preprocess(means, scales, quats, sh, cam)
-        probe = gs.BinSorter(sc.P, 0, W, H)
-        probe(pre["means2d"], pre["radii"], pre["depths"])
-        N = probe.n_splats()
-        bs = gs.BinSorter(sc.P, int(N * 1.1) + 1024, W, H)
-        bs(pre["means2d"], pre["radii"], pre["depths"])
-        assert bs.n_splats() == N
-        say(f"  pose {pose}: N = {N}")
-        m2, rad, dep = host(pre["means2d"]), host(pre["radii"]), host(pre["depths"])
-        conics, rgb = host(pre["conics"]).astype(np.float64), host(pre["rgb"])
-        # preprocess vs the FP64 oracle on a sample of Gaussians
-        sel = np.random.default_rng(pose).choice(sc.P, 200_000, replace=False)
-        sub = scenegen.Scene3D(means=sc.means[sel], scales=sc.scales[sel], quats=sc.quats[sel],
-                               opacities=sc.opacities[sel], sh=sc.sh[sel])
-        o = oracle.preprocess_3d(sub, cam_np)
-        same = rad[sel] == o["radii"]
-        assert np.mean(same) > 0.999
-        vis = same & (o["radii"] > 0)
-        np.testing.assert_allclose(m2[sel][vis], o["means2d"][vis], rtol=1e-5, atol=2e-3)
-        np.testing.assert_allclose(rgb[sel][vis], o["rgb"][vis], atol=3e-5)
-        # lists of sampled tiles equal the oracle's, exactly
-        ranges_g = host(bs.ranges).astype(np.int64)
-        ids_g = host(bs.sorted_ids)
-        tiles = sample_tiles(ranges_g, gx, gy, seed=pose)
-        r_o, i_o = oracle.bin_tiles(m2, rad, dep, W, H, tiles)
-        for j, t in enumerate(tiles):
-            a = ids_g[ranges_g[t, 0]:ranges_g[t, 1]].astype(np.uint32)
-            b = i_o[r_o[j, 0]:r_o[j, 1]]
-            assert np.array_equal(a, b), (workload, pose, t, len(a), len(b))
-        full_r = np.zeros((gx * gy, 2), np.uint32)
-        full_r[tiles] = r_o
-        # FP32 path: admissible-set parity on the sampled tiles
-        r32 = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,
-                               pre["rgb"], "fp32")
-        img32, T32 = host(r32.rgb), host(r32.T)
-        assert np.isfinite(img32).all() and T32.min() >= 1e-4 and T32.max() <= 1.0
-        st = fp32_check(W, H, full_r, i_o, m2, conics, sc.opacities, rgb, img32, T32, tiles=tiles)
-        say(f"  fp32: max|err| {st['max_abs']:.2e} on {st['n_pix']} px, ambiguous {st['n_amb']}")
-        ref = st["ref"]
-        mask = ~np.isnan(ref["T"])
-        for prec in precs:
-            r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,
-                                 pre["rgb"], prec)
-            img, T = host(r.rgb), host(r.T)
-            assert np.isfinite(img).all() and T.min() >= 1e-4 and T.max() <= 1.0
-            q = quality(img, ref["rgb"], mask)
-            say(f"  {prec}: PSNR {q['psnr']:.1f} dB, within 2/255 {q['frac_2_255']:.5f}, max {q['max_abs']:.2e}")
-            assert q["psnr"] >= 50.0
-            if prec != "fp16_g2l":  # the paper's K = 8 layout meets the PSNR bar only
-                assert q["frac_2_255"] >= 0.999
+    sc, (means, scales, quats, sh, opac) = scene_of(workload)
+    cam_np = scenegen.make_camera(cfg, pose)
+    cam = gs.make_camera(cam_np.viewmat, cam_np.fx, cam_np.fy, cam_np.cx, cam_np.cy, W, H,
+                         campos=cam_np.campos)
+    pre = gs.preprocess(means, scales, quats, sh, cam)
+    probe = gs.BinSorter(sc.P, 0, W, H)
+    probe(pre["means2d"], pre["radii"], pre["depths"])
+    N = probe.n_splats()
+    bs = gs.BinSorter(sc.P, int(N * 1.1) + 1024, W, H)
+    bs(pre["means2d"], pre["radii"], pre["depths"])
+    assert bs.n_splats() == N
+    say(f"  {workload} pose {pose}: N = {N}")
+    m2, rad, dep = host(pre["means2d"]), host(pre["radii"]), host(pre["depths"])
+    conics, rgb = host(pre["conics"]).astype(np.float64), host(pre["rgb"])
+    ranges_g = host(bs.ranges).astype(np.int64)
+    tiles = sample_tiles(ranges_g, gx, gy, seed=pose)
+    imgs = {}
+    for prec in ["fp32"] + precs:
+        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,
+                             pre["rgb"], prec)
+        img, T = host(r.rgb), host(r.T)
+        assert np.isfinite(img).all() and T.min() >= 1e-4 and T.max() <= 1.0
+        imgs[prec] = (img, T)
+
+    # (a) whole path against the FP64 chain on the sampled tiles
+    o = oracle.preprocess_3d(sc, cam_np)
+    r_c, i_c = oracle.bin_tiles(o["means2d"].astype(np.float32), o["radii"],
+                                o["depths"].astype(np.float32), W, H, tiles)
+    full_c = np.zeros((gx * gy, 2), np.uint32)
+    full_c[tiles] = r_c
+    chain = oracle.render(W, H, full_c, i_c, o["means2d"], o["conics"], sc.opacities, o["rgb"],
+                          tiles=tiles)
+    mask_c = ~np.isnan(chain["T"])
+    for prec, (img, _) in imgs.items():
+        q = quality(img, chain["rgb"], mask_c)
+        d = np.abs(img - chain["rgb"]).max(axis=0)[mask_c]
+        say(f"  chain {prec}: PSNR {q['psnr']:.1f} dB, max|err| {q['max_abs']:.2e}, "
+            f"within 1e-4 {np.mean(d <= 1e-4):.5f}, within 2/255 {q['frac_2_255']:.6f} "
+            f"({mask_c.sum()} px)")
+        assert q["psnr"] >= 50.0
+        if prec != "fp16_g2l":
+            assert q["frac_2_255"] >= 0.999
+        if prec == "fp32":
+            assert np.mean(d <= 1e-4) >= 0.99
+    del o, chain
+    if (workload, pose) not in GPU_INPUT_CASES:
+        return
+
+    # (b) stage by stage on the GPU's intermediates
+    sel = np.random.default_rng(pose).choice(sc.P, 200_000, replace=False)
+    sub = scenegen.Scene3D(means=sc.means[sel], scales=sc.scales[sel], quats=sc.quats[sel],
+                           opacities=sc.opacities[sel], sh=sc.sh[sel])
+    o = oracle.preprocess_3d(sub, cam_np)
+    same = rad[sel] == o["radii"]
+    assert np.mean(same) > 0.999
+    vis = same & (o["radii"] > 0)
+    np.testing.assert_allclose(m2[sel][vis], o["means2d"][vis], rtol=1e-5, atol=2e-3)
+    np.testing.assert_allclose(rgb[sel][vis], o["rgb"][vis], atol=3e-5)
+    cs, co = conics[sel][vis], o["conics"][vis]
+    crel = np.abs(cs - co) / np.abs(co).max(axis=1, keepdims=True)
+    say(f"  preprocess conics: max scaled rel err {crel.max():.2e}, 99.9th pct "
+        f"{np.percentile(crel, 99.9):.2e}")
+    assert np.percentile(crel, 99.9) < 1e-3 and crel.max() < 1e-1
+    # lists of sampled tiles equal the oracle's, exactly
+    ids_g = host(bs.sorted_ids)
+    r_o, i_o = oracle.bin_tiles(m2, rad, dep, W, H, tiles)
+    for j, t in enumerate(tiles):
+        a = ids_g[ranges_g[t, 0]:ranges_g[t, 1]].astype(np.uint32)
+        b = i_o[r_o[j, 0]:r_o[j, 1]]
+        assert np.array_equal(a, b), (workload, pose, t, len(a), len(b))
+    full_r = np.zeros((gx * gy, 2), np.uint32)
+    full_r[tiles] = r_o
+    # FP32 path: admissible-set parity on the sampled tiles
+    img32, T32 = imgs["fp32"]
+    st = fp32_check(W, H, full_r, i_o, m2, conics, sc.opacities, rgb, img32, T32, tiles=tiles)
+    say(f"  fp32 raster: max|err| {st['max_abs']:.2e} on {st['n_pix']} px, ambiguous {st['n_amb']}")
+    ref = st["ref"]
+    mask = ~np.isnan(ref["T"])
+    for prec in precs:
+        q = quality(imgs[prec][0], ref["rgb"], mask)
+        say(f"  {prec} raster: PSNR {q['psnr']:.1f} dB, within 2/255 {q['frac_2_255']:.5f}, "
+            f"max {q['max_abs']:.2e}")
+        assert q["psnr"] >= 50.0
+        if prec != "fp16_g2l":  # the paper's K = 8 layout meets the PSNR bar only
+            assert q["frac_2_255"] >= 0.999
 
 
 def test_tile_sort_block_sizes_agree():
