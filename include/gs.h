@@ -367,6 +367,21 @@ gs_status gs_clock_stamp(uint64_t *d_dst, void *stream);
 /* Frequency of the device wall clock in kHz (host call, current device). */
 gs_status gs_wall_clock_khz(int32_t *khz);
 
+/*
+ * gs_peak_probe -- diagnostic: enqueue one peak-rate probe of the device, for
+ * roofline fractions stated against measured rather than assumed rates.
+ * blocks workgroups of 256 threads each run `iters` rounds of independent
+ * operations (timed by the caller with events on `stream`):
+ *   kind 0  v_exp_f32 (x <- 2^-x), 8 per lane per round;
+ *   kind 1  v_fma_f32 (2 flop), 8 per lane per round;
+ *   kind 2  v_mfma_f32_32x32x16_f16 (32768 flop per wave instruction), 4 per
+ *           wave per round.
+ * d_out [blocks * 256] floats receives one value per thread (keeps the work
+ * live).  Errors: GS_ERR_INVALID_ARG (kind, iters < 1, blocks outside
+ * 1..2^20, null or misaligned d_out), GS_ERR_HIP.
+ */
+gs_status gs_peak_probe(int32_t kind, int32_t iters, int32_t blocks, float *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

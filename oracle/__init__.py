@@ -204,7 +204,11 @@ def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0
     rendered (other pixels are NaN / -1).  Colour is planar (3, H, W).
     A cull decision is flagged as near-threshold when |ln alpha + ln 255| <
     delta_c + delta_r * (sum of |terms| of q/2); a termination decision when
-    |T(1 - alpha) - 1e-4| < delta_t * 1e-4."""
+    |T(1 - alpha) - 1e-4| < delta_t * 1e-4.  ``sens`` (exact-definition mode)
+    is, per pixel, the sum over composited fragments of alpha T times half
+    the sum of |terms| of q: an evaluation whose exponent errs by at most
+    rho times that term size moves the colour by at most 2 max|c| rho sens
+    and T by at most rho sens (to first order)."""
     rg, idv = np.ascontiguousarray(ranges, np.uint32), np.ascontiguousarray(ids, np.uint32)
     if idv.size == 0:
         idv = np.zeros(1, np.uint32)
@@ -214,14 +218,16 @@ def render(W: int, H: int, ranges, ids, means2d, conics, opac, rgb, bg=(0.0, 0.0
     out = dict(rgb=np.full((3, H, W), np.nan), T=np.full((H, W), np.nan),
                n_contrib=np.full((H, W), -1, np.int32), n_proc=np.full((H, W), -1, np.int32),
                f_blend=np.full((H, W), -1, np.int32), f_cull=np.full((H, W), -1, np.int32),
-               term=np.full((H, W), -1, np.int32), n_amb=np.full((H, W), -1, np.int32))
+               term=np.full((H, W), -1, np.int32), n_amb=np.full((H, W), -1, np.int32),
+               sens=np.full((H, W), np.nan))
     if tiles is not None and ntl == 0:
         return out
     lib().orc_render(c_int(W), c_int(H), _p(rg), _p(idv), _p(m), _p(c), _p(o), _p(col), _p(b),
                      c_int(mode), c_double(delta_c), c_double(delta_r), c_double(delta_t), c_int(ntl),
                      _p(tl) if ntl else c_void_p(0),
                      _p(out["rgb"]), _p(out["T"]), _p(out["n_contrib"]), _p(out["n_proc"]),
-                     _p(out["f_blend"]), _p(out["f_cull"]), _p(out["term"]), _p(out["n_amb"]))
+                     _p(out["f_blend"]), _p(out["f_cull"]), _p(out["term"]), _p(out["n_amb"]),
+                     _p(out["sens"]))
     return out
 
 

@@ -516,7 +516,7 @@ int64_t orc_bin_tiles(int P, const float *means2d, const int32_t *radii, const f
 /*  the dot product itself is exact (double):                               */
 /*  1 FP16, global coordinates, K = 8 layout (Sec. 5.1)                     */
 /*  2 FP16, local coordinates (Sec. 4.3), K = 8 layout                      */
-/*  3 FP16, local, v split into hi + lo FP16 parts                          */
+/*  3 FP16, local, v split into hi (v/256, met by 256 u) + lo FP16 parts    */
 /*  4 BF16, local, v split into hi + mid + lo BF16 parts                    */
 /* ------------------------------------------------------------------------ */
 enum { MODE_DEF = 0, MODE_F16_GLOBAL = 1, MODE_F16_G2L = 2, MODE_F16_SPLIT = 3, MODE_BF16_SPLIT = 4 };
@@ -553,8 +553,9 @@ double orc_beta_emulated(int mode, const double *mu, const double *S, double opa
         beta = 3.0 * w0;
         for (int i = 1; i < 6; ++i) beta += rnd_h(u[i]) * rnd_h(v[i]);
     } else if (mode == MODE_F16_SPLIT) {
+        /* hi part stored as v/256 in FP16 (met by 256 u), lo = v - 256 hi */
         for (int i = 0; i < 6; ++i) {
-            double hi = rnd_h(v[i]);
+            double hi = 256.0 * rnd_h(v[i] / 256.0);
             double lo = rnd_h(v[i] - hi);
             beta += rnd_h(u[i]) * hi + rnd_h(u[i]) * lo;
         }
@@ -579,6 +580,7 @@ typedef struct {
     int32_t f_blend, f_cull;
     int32_t term;      /* 1 when the pixel stopped at a fragment (T - aT < 1e-4) */
     int32_t n_amb;     /* decisions within delta of a threshold */
+    double sens;       /* sum over composited fragments of alpha T * (1/2 sum of |terms| of q) */
 } pix_out_t;
 
 typedef struct {
@@ -600,11 +602,12 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
     const double cull_ln = -log(255.0);
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
     int nb = 0, nc = 0, term = 0, last = 0, namb = 0, nflag = 0;
+    double sens = 0.0;
     for (uint32_t k = start; k < end; ++k) {
         uint32_t g = s->ids[k];
         const double *mu = s->means2d + 2 * g, *S = s->conics + 3 * g;
         double o = s->opac[g];
-        double alpha, margin, band = s->dc;
+        double alpha, margin, band = s->dc, terms = 0.0;
         int cull;
         if (s->mode == MODE_DEF) {
             double dx = mu[0] - p[0], dy = mu[1] - p[1];
@@ -614,7 +617,8 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
             margin = (log(o) - 0.5 * q) - cull_ln;        /* distance in ln(alpha) */
             /* a reduced-precision evaluation errs relative to the size of the
              * quadratic form's terms, not of q itself */
-            band += s->dr * 0.5 * (fabs(S[0]) * dx * dx + 2.0 * fabs(S[1] * dx * dy) + fabs(S[2]) * dy * dy);
+            terms = 0.5 * (fabs(S[0]) * dx * dx + 2.0 * fabs(S[1] * dx * dy) + fabs(S[2]) * dy * dy);
+            band += s->dr * terms;
         } else {
             /* EarlyCull (Sec. 4.1): the test on the exponent, here in log2 units */
             double b2 = orc_beta_emulated(s->mode, mu, S, o, p, tc);
@@ -639,6 +643,13 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
         if (stop) { term = 1; break; }
         const double *c = s->rgb + 3 * g;
         for (int ch = 0; ch < 3; ++ch) C[ch] += c[ch] * alpha * T;
+        /* First-order size of the result's response to errors in the
+         * exponents: an error e_k in fragment k's exponent moves C by at most
+         * alpha_k T_k (|c_k| + max |c|) |e_k| and T_final by at most
+         * alpha_k T_k |e_k| (the fragments behind k carry at most T_{k+1}).
+         * An evaluation that errs by rho times the size of q/2's terms moves
+         * C by at most 2 max|c| rho sens and T by rho sens. */
+        sens += alpha * T * terms;
         T = test;
         ++nb;
         last = (int)(k - start) + 1;
@@ -651,6 +662,7 @@ static void render_pixel(const scene_ref_t *s, int x, int y, unsigned flip_mask,
     o->f_cull = nc;
     o->term = term;
     o->n_amb = namb;
+    o->sens = sens;
 }
 
 /* Render the image (or only the listed tiles when ntl > 0).  Planar colour
@@ -660,7 +672,7 @@ void orc_render(int W, int H, const uint32_t *ranges, const uint32_t *ids,
                 const double *rgb, const double *bg, int mode, double delta_c, double delta_r,
                 double delta_t, int ntl, const int32_t *tile_list,
                 double *out_rgb, double *out_T, int32_t *n_contrib, int32_t *n_proc,
-                int32_t *f_blend, int32_t *f_cull, int32_t *term, int32_t *n_amb)
+                int32_t *f_blend, int32_t *f_cull, int32_t *term, int32_t *n_amb, double *sens)
 {
     scene_ref_t s = {ranges, ids, means2d, conics, opac, rgb, W, H, mode, delta_c, delta_r, delta_t};
     int gx = (W + ORC_TILE - 1) / ORC_TILE, gy = (H + ORC_TILE - 1) / ORC_TILE;
@@ -684,6 +696,7 @@ void orc_render(int W, int H, const uint32_t *ranges, const uint32_t *ids,
                 f_cull[pi] = o.f_cull;
                 term[pi] = o.term;
                 n_amb[pi] = o.n_amb;
+                if (sens) sens[pi] = o.sens;
             }
     }
 }

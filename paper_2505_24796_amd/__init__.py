@@ -134,6 +134,8 @@ def lib() -> ctypes.CDLL:
         L.gs_rasterize_fwd_batched.restype = ctypes.c_int
         L.gs_rasterize_fwd_batched.argtypes = [c_int32, vp, c_int32, POINTER(gs_batch_tune), vp,
                                                c_size_t, vp, vp]
+        L.gs_peak_probe.restype = ctypes.c_int
+        L.gs_peak_probe.argtypes = [c_int32, c_int32, c_int32, vp, vp]
         L.gs_clock_stamp.restype = ctypes.c_int
         L.gs_clock_stamp.argtypes = [vp, vp]
         L.gs_wall_clock_khz.restype = ctypes.c_int
@@ -467,6 +469,32 @@ def render(means3d, scales, quats, sh, opacities, cam: gs_camera, precision="fp1
     r(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opacities, pre["rgb"], precision,
       background)
     return r, bs, pre
+
+
+PEAK_PROBES = {"exp": (0, 8), "fma": (1, 16), "mfma_f16": (2, 4 * 32768)}
+
+
+def peak_probe(kind: str, iters: int, blocks: int, reps: int = 3) -> float:
+    """Measured peak rate of the device for one operation kind (gs_peak_probe):
+    "exp" -> v_exp_f32 per second, "fma" -> FP32 FMA flop/s, "mfma_f16" ->
+    flop/s of v_mfma_f32_32x32x16_f16.  Best of `reps` timed launches (after
+    one warm-up) on the current stream."""
+    k, per = PEAK_PROBES[kind]
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for r in range(reps + 1):
+        ev0.record()
+        _check("gs_peak_probe", lib().gs_peak_probe(k, iters, blocks, _ptr(out), _stream()))
+        ev1.record()
+        torch.cuda.synchronize()
+        if r:
+            best = min(best, ev0.elapsed_time(ev1) / 1e3)
+    if kind == "mfma_f16":
+        ops = blocks * 4 * iters * per  # four waves per workgroup
+    else:
+        ops = blocks * 256 * iters * per
+    return ops / best
 
 
 def wall_clock_khz() -> int:

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgsmfma.so")
-SOURCES = ["preprocess.hip", "binsort.hip", "raster.hip", "raster_bwd.hip", "raster_batched.hip"]
+SOURCES = ["preprocess.hip", "binsort.hip", "raster.hip", "raster_bwd.hip", "raster_batched.hip",
+           "peaks.hip"]
 ARCH = "gfx950"
 
 CFLAGS = [

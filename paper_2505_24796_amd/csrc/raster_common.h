@@ -79,7 +79,8 @@ template <int VAR> struct VarTraits;
 // K = 8: [v0/3 x3, v1..v5] against [1 x3, dx, dy, dx^2, dxdy, dy^2]
 template <> struct VarTraits<VAR_F16_GLOBAL> { static constexpr int ROW1 = 16, ROW2 = 0; static constexpr bool LOCAL = false; };
 template <> struct VarTraits<VAR_F16_G2L> { static constexpr int ROW1 = 16, ROW2 = 0; static constexpr bool LOCAL = true; };
-// K = 16: [hi(6), 0, 0 | lo(6), 0, 0] against [u(6), 0, 0 | u(6), 0, 0]
+// K = 16: [hi(6), 0, 0 | lo(6), 0, 0] against [256 u(6), 0, 0 | u(6), 0, 0],
+// hi = fp16(v / 256), lo = fp16(v - 256 hi)
 template <> struct VarTraits<VAR_F16_SPLIT> { static constexpr int ROW1 = 32, ROW2 = 0; static constexpr bool LOCAL = true; };
 // K = 16 + 8: [hi(6),0,0 | mid(6),0,0] then [lo0..3 | lo4, lo5, 0, 0]
 template <> struct VarTraits<VAR_BF16_SPLIT> { static constexpr int ROW1 = 32, ROW2 = 16; static constexpr bool LOCAL = true; };
@@ -97,21 +98,41 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_val(float x) { return (float)(__bf16)x; }
 
+// a*b + c*d, rounded once more than a single product: the rounding error
+// of c*d is recovered exactly with an FMA and added back, so the result is
+// accurate to a few ulps of itself even when the two products cancel.
+__device__ __forceinline__ float dot2_acc(float a, float b, float c, float d) {
+    const float p = c * d;
+    const float e = fmaf(c, d, -p);
+    return fmaf(a, b, p) + e;
+}
+
 // Write the operand-A row of one splat.  Coefficients (Sec. 4.2) in the frame
 // with origin (ox, oy), scaled by log2(e):
 //   v0 = log2 o - 1/2 log2e dmu^T S dmu, v1 = log2e (s11 dx + s12 dy),
 //   v2 = log2e (s12 dx + s22 dy), v3 = -1/2 log2e s11, v4 = -log2e s12,
 //   v5 = -1/2 log2e s22,  dmu = mu' - origin.
+// They are computed once per splat and tile, so they are evaluated with
+// care: dmu^T S dmu as s11 (dx + (s12/s11) dy)^2 + (det S / s11) dy^2, two
+// non-negative terms with det S = s11 s22 - s12^2 from Kahan's FMA scheme,
+// and v1, v2 with dot2_acc.  The plain expansion loses to cancellation all
+// the digits of near-degenerate (needle-like) splats, whose terms are far
+// larger than their sum; these forms keep the error near the size of the
+// result.
 template <int VAR>
 __device__ __forceinline__ void build_row(bool valid, float2 mu, float s11, float s12, float s22,
                                           float o, float ox, float oy, uint8_t *row1, uint8_t *row2) {
     float v[6];
     if (valid) {
-        float dx = mu.x - ox, dy = mu.y - oy;
-        float q = fmaf(s11 * dx, dx, fmaf(2.0f * s12 * dx, dy, s22 * dy * dy));
-        v[0] = __log2f(o) - 0.5f * LOG2E * q;
-        v[1] = LOG2E * fmaf(s11, dx, s12 * dy);
-        v[2] = LOG2E * fmaf(s12, dx, s22 * dy);
+        const float dx = mu.x - ox, dy = mu.y - oy;
+        const float w = s12 * s12;
+        const float det = fmaf(s11, s22, -w) - fmaf(s12, s12, -w);
+        const float r11 = 1.0f / s11;
+        const float t = fmaf(s12 * r11, dy, dx);
+        const float q = fmaf(s11 * t, t, (det * r11) * dy * dy);
+        v[0] = fmaf(-0.5f * LOG2E, q, __log2f(o));
+        v[1] = LOG2E * dot2_acc(s11, dx, s12, dy);
+        v[2] = LOG2E * dot2_acc(s12, dx, s22, dy);
         v[3] = -0.5f * LOG2E * s11;
         v[4] = -LOG2E * s12;
         v[5] = -0.5f * LOG2E * s22;
@@ -125,12 +146,16 @@ __device__ __forceinline__ void build_row(bool valid, float2 mu, float s11, floa
                      (_Float16)v[5]};
         *(half8_t *)row1 = r;
     } else if (VAR == VAR_F16_SPLIT) {
+        // hi holds v / 256 (its pixel features are 256 u, exact in FP16), so
+        // coefficients up to 256 x 65504 stay finite: the exponent at the
+        // tile centre of a needle-thin splat crossing the tile can be far
+        // below -65504 while pixels on its axis still blend
         half8_t hi, lo;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            _Float16 h = (_Float16)v[i];
+            _Float16 h = (_Float16)(v[i] * (1.0f / 256.0f));
             hi[i] = h;
-            lo[i] = valid ? (_Float16)(v[i] - (float)h) : (_Float16)0.0f;
+            lo[i] = valid ? (_Float16)(v[i] - 256.0f * (float)h) : (_Float16)0.0f;
         }
         hi[6] = hi[7] = lo[6] = lo[7] = (_Float16)0.0f;
         *(half8_t *)row1 = hi;
@@ -174,8 +199,10 @@ __device__ __forceinline__ UOperand make_u(float ux, float uy, int slice) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) u.k8[i] = (_Float16)e[4 * slice + i];
     } else if (VAR == VAR_F16_SPLIT) {
+        // K 0-7 (slice 0) meet the hi row, K 8-15 (slice 1) the lo row
+        const float sc = slice == 0 ? 256.0f : 1.0f;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) u.k16[i] = (_Float16)f[i];
+        for (int i = 0; i < 6; ++i) u.k16[i] = (_Float16)(sc * f[i]);
         u.k16[6] = u.k16[7] = (_Float16)0.0f;
     } else {
 #pragma unroll

@@ -30,18 +30,30 @@ def psnr(x, ref):
 
 def fp32_check(W, H, ranges, ids, means2d, conics, opac, rgb, gpu_rgb, gpu_T, tol=1e-4,
                tiles=None, bg=(0.0, 0.0, 0.0)):
-    """FP32 path vs FP64 oracle: every pixel must be within `tol` of some
-    admissible result (decisions within delta of a threshold may go either
-    way).  Returns a stats dict."""
+    """FP32 path vs FP64 oracle: every pixel must be within its tolerance of
+    some admissible result (decisions within delta of a threshold may go
+    either way).  The tolerance is `tol` plus the FP32 evaluation error of
+    Algorithm 1's exponent: an exponent computed from the conic's raw terms
+    errs by up to ~DELTA_R times half their summed magnitude, which moves the
+    colour by at most 2 max|c| DELTA_R sens and T by DELTA_R sens (the
+    oracle's first-order bound, pinned on the CPU).  For well-conditioned
+    splats the added term is far below `tol`; for near-degenerate needles,
+    whose terms are large and cancel, it is what FP32 can do.  Returns a
+    stats dict."""
     ref = oracle.render(W, H, ranges, ids, means2d, conics, opac, rgb, bg=bg,
                         delta_c=DELTA_C, delta_t=DELTA_T, delta_r=DELTA_R, tiles=tiles)
     mask = ~np.isnan(ref["T"])
+    cm = max(float(np.abs(rgb).max()) if len(rgb) else 0.0, float(np.abs(bg).max()))
+    sens = np.where(mask, ref["sens"], 0.0)
+    tolC = tol + 2.0 * cm * DELTA_R * sens
+    tolT = tol + DELTA_R * sens
     err = np.abs(gpu_rgb - ref["rgb"]).max(axis=0)
     errT = np.abs(gpu_T - ref["T"])
     amb = ref["n_amb"] > 0
-    bad = mask & ((err > tol) | (errT > tol))
+    bad = mask & ((err > tolC) | (errT > tolT))
     hard = bad & ~amb
-    assert not hard.any(), f"{hard.sum()} unambiguous pixels off by up to {err[hard].max():.3e}"
+    assert not hard.any(), (f"{hard.sum()} unambiguous pixels off by up to {err[hard].max():.3e} "
+                            f"(tolerance there {tolC[hard].min():.3e})")
     ys, xs = np.nonzero(bad & amb)
     if len(ys):
         alt, altT = oracle.render_alternatives(W, H, ranges, ids, means2d, conics, opac, rgb,
@@ -50,11 +62,11 @@ def fp32_check(W, H, ranges, ids, means2d, conics, opac, rgb, gpu_rgb, gpu_T, to
         for j, (x, y) in enumerate(zip(xs, ys)):
             e = np.abs(alt[j] - gpu_rgb[:, y, x]).max(axis=1)
             eT = np.abs(altT[j] - gpu_T[y, x])
-            assert np.any((e <= tol) & (eT <= tol)), (x, y, e.min())
+            assert np.any((e <= tolC[y, x]) & (eT <= tolT[y, x])), (x, y, e.min())
     good = mask & ~bad
     return dict(max_abs=float(err[good].max()) if good.any() else 0.0,
                 n_pix=int(mask.sum()), n_amb=int((mask & amb).sum()), n_flip=int(len(ys)),
-                ref=ref)
+                n_wide=int(np.sum(mask & (tolC > 2 * tol))), ref=ref)
 
 
 def quality(gpu_rgb, ref_rgb, mask=None):

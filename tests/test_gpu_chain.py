@@ -114,7 +114,12 @@ def test_near_degenerate_conic_takes_fp64_branch():
     FP32 determinant ac - b^2 cancels (det < 2^-10 ac), so the GPU forms it
     and the inverse in FP64.  Conics equal the oracle's FP64 conics to FP32
     rounding; a well-conditioned half of the scene takes the FP32 branch and
-    is checked the same way; the images meet the raster bars."""
+    is checked the same way; the images of the FP32 path and of the FP16 and
+    BF16 split variants meet the raster bars (the paper's K = 8 layout
+    overflows FP16 on these splats, shown below).  The FP32
+    raster evaluates Algorithm 1's exponent from the conic's raw terms, which
+    for these needles are large and cancel: its per-pixel tolerance adds the
+    first-order effect of that evaluation error (see fp32_check)."""
     W, H = 256, 200
     nd = scenegen.scene_2d_needles(1500, W, H, seed=41)
     ok = scenegen.scene_2d(1500, W, H, seed=42)
@@ -148,20 +153,30 @@ def test_near_degenerate_conic_takes_fp64_branch():
     bs = gs.bin_sort(dev(m2), pre["radii"], dev(dep), W, H)
     N = bs.n_splats()
     assert N == len(ids) and np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids)
+    results = {}
     for prec in PRECS:
         r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"], dev(opac),
                              dev(rgb), prec)
         img = host(r.rgb)
         if prec.startswith("fp32"):
             st = fp32_check(W, H, ranges, ids, m2, cg, opac, rgb, img, host(r.T))
-            say(f"  {prec}: max|err| {st['max_abs']:.2e}, ambiguous {st['n_amb']}, flips {st['n_flip']}")
+            say(f"  {prec}: max|err| {st['max_abs']:.2e}, ambiguous {st['n_amb']}, flips {st['n_flip']}, "
+                f"pixels whose FP32 exponent bound exceeds 1e-4: {st['n_wide']}")
         else:
             ref = oracle.render(W, H, ranges, ids, m2, cg, opac, rgb)
-            q = quality(img, ref["rgb"])
-            say(f"  {prec}: PSNR {q['psnr']:.1f} dB, within 2/255 {q['frac_2_255']:.6f}")
-            assert q["psnr"] >= 50.0
-            if prec != "fp16_g2l":
-                assert q["frac_2_255"] >= 0.999
+            results[prec] = q = quality(img, ref["rgb"])
+            say(f"  {prec}: PSNR {q['psnr']:.1f} dB, max|err| {q['max_abs']:.2e}, "
+                f"within 2/255 {q['frac_2_255']:.6f}")
+    # The paper's K = 8 layout stores v0/3 and v1..v5 in plain FP16: at the
+    # centre of a tile that a needle crosses off-centre, q/2 runs to 1e5 and
+    # more, beyond FP16's 65504, so the row overflows and the splat is lost
+    # at pixels on its axis.  The hi/lo split stores v/256 in its high part
+    # (range 256 x 65504) and BF16 has FP32's range: those two meet the bars.
+    assert results["fp16_g2l"]["psnr"] < 50.0
+    for prec in ("fp16_g2l_split", "bf16_g2l_split"):
+        q = results[prec]
+        assert q["psnr"] >= 50.0, (prec, q)
+        assert q["frac_2_255"] >= 0.999, (prec, q)
 
 
 def test_degenerate_inputs_2d():

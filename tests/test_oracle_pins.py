@@ -136,6 +136,52 @@ def test_invariants_random_scene(orc):
     assert np.all(out2["n_proc"] == out2["f_blend"] + out2["f_cull"] + out2["term"])
 
 
+def test_sensitivity_single_gaussian_closed_form(orc):
+    """One composited fragment: sens = alpha * (s11 dx^2 + 2 |s12 dx dy| +
+    s22 dy^2) / 2 (with T = 1 in front of it); culled pixels carry 0."""
+    ranges, ids = one_tile_lists(1)
+    mu, S, o = np.array([6.3, 8.7]), np.array([0.31, -0.17, 0.22]), 0.7
+    out = orc.render(16, 16, ranges, ids, mu[None], S[None], [o], [[0.2, 0.5, 0.9]])
+    Sm = np.array([[S[0], S[1]], [S[1], S[2]]])
+    for y in range(16):
+        for x in range(16):
+            d = mu - np.array([x, y], float)
+            a = min(0.99, o * math.exp(-0.5 * d @ Sm @ d))
+            terms = 0.5 * (abs(S[0]) * d[0] ** 2 + 2 * abs(S[1] * d[0] * d[1]) + abs(S[2]) * d[1] ** 2)
+            want = a * terms if a >= 1 / 255 else 0.0
+            assert abs(out["sens"][y, x] - want) <= 1e-14 * max(1.0, want)
+
+
+def test_sensitivity_bounds_a_perturbed_exponent(orc):
+    """The first-order bound the FP32 parity check uses: the conic
+    (s11, s12, s22) -> (s11 (1 + r), s12 (1 - r), s22 (1 + r)) changes each
+    exponent by at most r (sum of |terms| of q)/2, reaching it wherever the
+    cross term opposes the squares (near a needle's axis, where q cancels).
+    On pixels with no near-threshold decision the colour then moves by at
+    most 2 max|c| r sens and T by at most r sens (plus second-order slack),
+    and the bound is reached to within a small factor, so it is not vacuous,
+    for well-conditioned splats and for near-degenerate needles alike."""
+    W, H = 96, 80
+    for sc in (scenegen.scene_2d(800, W, H, seed=12),
+               scenegen.scene_2d_needles(300, W, H, seed=13)):
+        pre = orc.preprocess_2d(sc.means2d, sc.cov2d, W, H)
+        ranges, ids = orc.bin_splats(sc.means2d, pre["radii"], sc.depths, W, H)
+        r = 1e-7
+        base = orc.render(W, H, ranges, ids, sc.means2d, pre["conics"], sc.opacities, sc.rgb,
+                          delta_c=1e-5, delta_t=1e-3, delta_r=2 * r)
+        con = pre["conics"] * np.array([1 + r, 1 - r, 1 + r])
+        pert = orc.render(W, H, ranges, ids, sc.means2d, con, sc.opacities, sc.rgb)
+        ok = base["n_amb"] == 0
+        cm = float(np.abs(sc.rgb).max())
+        dC = np.abs(pert["rgb"] - base["rgb"]).max(axis=0)[ok]
+        dT = np.abs(pert["T"] - base["T"])[ok]
+        sens = base["sens"][ok]
+        assert np.all(dC <= 2 * cm * r * sens * (1 + 1e-3) + 1e-15)
+        assert np.all(dT <= r * sens * (1 + 1e-3) + 1e-15)
+        big = sens > np.percentile(sens, 90)
+        assert np.max(dT[big] / (r * sens[big])) > 0.3
+
+
 # ---------------------------------------------------------------- P4 / P7 --
 def _exact_beta_log2(mu, S, o, p):
     d = np.asarray(mu, float) - np.asarray(p, float)
