@@ -22,7 +22,8 @@
  *     coordinate (x, y).
  *   - Per-Gaussian arrays are indexed by Gaussian id in [0, P).
  *   - No exceptions cross the ABI.  The functions keep no global state apart
- *     from a lazily initialised, thread-safe cache of device properties.
+ *     from a lazily initialised, thread-safe cache of device properties and
+ *     the per-device scratch array of gs_bin_sort_noalloc.
  */
 #ifndef GS_H
 #define GS_H
@@ -142,6 +143,32 @@ gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t *radii, con
                       int32_t width, int32_t height, uint32_t capacity, void *workspace,
                       size_t workspace_bytes, uint32_t *sorted_ids, uint32_t *tile_ranges,
                       uint32_t *d_num_splats, void *stream);
+
+/* Size of the device scratch array gs_bin_sort_noalloc works in (128 MiB:
+ * room for gs_bin_sort_workspace_bytes() of, e.g., 1M Gaussians with up to
+ * 7.2M splats, the 1920x1080 frame of a 1M-Gaussian scene). */
+#define GS_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/*
+ * gs_bin_sort_noalloc -- gs_bin_sort without a workspace argument, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The lists, counts
+ * and overflow behaviour are exactly gs_bin_sort's.  The workspace is a
+ * file-scope device array of GS_NOALLOC_SCRATCH_BYTES bytes that each GPU the
+ * library runs on holds until the process ends; its device address is looked
+ * up on the first call on a device (the only call that does more than
+ * enqueue work), and no call allocates or frees memory.  Every call on one
+ * GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (several streams or threads at once) race, so order them
+ * on one stream.  Nothing in the array needs to start at zero.
+ * Errors: as gs_bin_sort; GS_ERR_CAPACITY if gs_bin_sort_workspace_bytes(P,
+ * capacity, width, height) exceeds GS_NOALLOC_SCRATCH_BYTES (nothing is
+ * enqueued); GS_ERR_HIP if the array's address cannot be found.
+ */
+gs_status gs_bin_sort_noalloc(int32_t P, const float *means2d, const int32_t *radii,
+                              const float *depths, int32_t width, int32_t height,
+                              uint32_t capacity, uint32_t *sorted_ids, uint32_t *tile_ranges,
+                              uint32_t *d_num_splats, void *stream);
 
 /* Workspace bytes gs_bin_sort_precise needs (0 for invalid sizes). */
 size_t gs_bin_sort_precise_workspace_bytes(int32_t P, uint32_t capacity, int32_t width,

@@ -100,6 +100,9 @@ def lib() -> ctypes.CDLL:
         L.gs_bin_sort.restype = ctypes.c_int
         L.gs_bin_sort.argtypes = [c_int32, vp, vp, vp, c_int32, c_int32, c_uint32, vp, c_size_t,
                                   vp, vp, vp, vp]
+        L.gs_bin_sort_noalloc.restype = ctypes.c_int
+        L.gs_bin_sort_noalloc.argtypes = [c_int32, vp, vp, vp, c_int32, c_int32, c_uint32, vp, vp,
+                                          vp, vp]
         L.gs_rasterize_fwd.restype = ctypes.c_int
         L.gs_rasterize_fwd.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp,
                                        POINTER(c_float), c_int32, vp, vp, vp, vp, vp]
@@ -367,6 +370,29 @@ def bin_sort(means2d, radii, depths, width: int, height: int, capacity: int | No
     bs = BinSorter(P, capacity, width, height, device=means2d.device, precise=precise)
     bs(means2d, radii, depths, conics, opacities)
     return bs
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20  # GS_NOALLOC_SCRATCH_BYTES of gs.h
+
+
+def bin_sort_noalloc(means2d, radii, depths, width: int, height: int, sorted_ids, ranges,
+                     num_splats):
+    """gs_bin_sort_noalloc into caller-owned outputs (sorted_ids int32
+    [capacity], ranges int32 [tiles][2], num_splats int32 [1]); the library
+    works in its static device scratch array and allocates nothing.  Calls
+    on one GPU must not overlap (they share that array)."""
+    for n, t, dt in (("means2d", means2d, torch.float32), ("radii", radii, torch.int32),
+                     ("depths", depths, torch.float32), ("sorted_ids", sorted_ids, torch.int32),
+                     ("ranges", ranges, torch.int32), ("num_splats", num_splats, torch.int32)):
+        _dev(t, dt, n)
+    gx, gy = grid(width, height)
+    if ranges.numel() != 2 * gx * gy or num_splats.numel() < 1:
+        raise ValueError("ranges must hold 2 x tiles entries, num_splats one")
+    st = lib().gs_bin_sort_noalloc(means2d.shape[0], _ptr(means2d), _ptr(radii), _ptr(depths),
+                                   width, height, sorted_ids.numel(), _ptr(sorted_ids),
+                                   _ptr(ranges), _ptr(num_splats), _stream())
+    _check("gs_bin_sort_noalloc", st)
+    return sorted_ids, ranges, num_splats
 
 
 class Rasterizer:

@@ -20,6 +20,8 @@
 // (Gaussian, view) pairs, and the two sorts over per-view segments.
 #include "common.h"
 
+#include <mutex>
+
 namespace {
 
 constexpr int SORT_THREADS = 256;
@@ -1588,4 +1590,52 @@ extern "C" gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int3
     return bin_sort_views(nviews, P, widths, heights, means2d, radii, depths, conics, opacities,
                           precise != 0, capacity, workspace, workspace_bytes, sorted_ids,
                           tile_ranges, d_num_splats, d_view_splats, stream);
+}
+
+// ---------------------------------------------------------------------------
+// gs_bin_sort_noalloc: gs_bin_sort with its workspace in a file-scope device
+// array, for callers that cannot allocate.  Each device the library runs on
+// holds its own copy of the array until the process ends.  In host code the
+// array's name is only a host-side stand-in, so its device address is looked
+// up once per device (with that device current) and only that address is
+// passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices];
+
+gs_status scratch_of_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
+    if (dev < 0 || dev >= kMaxScratchDevices) return GS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GS_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" gs_status gs_bin_sort_noalloc(int32_t P, const float *means2d, const int32_t *radii,
+                                         const float *depths, int32_t width, int32_t height,
+                                         uint32_t capacity, uint32_t *sorted_ids,
+                                         uint32_t *tile_ranges, uint32_t *d_num_splats,
+                                         void *stream) {
+    const size_t need = gs_bin_sort_workspace_bytes(P, capacity, width, height);
+    if (need == 0) return GS_ERR_INVALID_ARG;
+    if (need > (size_t)GS_NOALLOC_SCRATCH_BYTES) return GS_ERR_CAPACITY;
+    void *ws = nullptr;
+    const gs_status st = scratch_of_current_device(&ws);
+    if (st != GS_OK) return st;
+    return bin_sort_views(1, P, &width, &height, means2d, radii, depths, nullptr, nullptr, false,
+                          capacity, ws, (size_t)GS_NOALLOC_SCRATCH_BYTES, sorted_ids, tile_ranges,
+                          d_num_splats, nullptr, stream);
 }
