@@ -86,6 +86,11 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (for timing)."""
+    lib().orc_set_num_threads(c_int(int(n)))
+
+
 def round_format(x: float, p: int, emin: int, maxval: float) -> float:
     return float(lib().orc_round_format(float(x), int(p), int(emin), float(maxval)))
 

@@ -815,6 +815,16 @@ void orc_render_backward(int W, int H, const uint32_t *ranges, const uint32_t *i
         }
 }
 
+/* Set the number of OpenMP threads of later parallel loops (timing only). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads the parallel loops use (1 without OpenMP). */
 int orc_num_threads(void)
 {

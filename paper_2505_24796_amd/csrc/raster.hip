@@ -45,26 +45,57 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
         }
         __syncthreads();
         int cnt = (int)min((uint32_t)BATCH, end - b0);
-        if (!done) {
+        if (EARLY) {
+            // EarlyCull at wave level: the exponent beta = ln o - q/2 is
+            // tested against -ln 255 first; the exp and the blend run only
+            // for splats that survive at some pixel of the wave (a uniform
+            // branch on the ballot), masked per lane; a wave whose pixels
+            // have all stopped leaves the round
+            for (int j = 0; j < cnt; ++j) {
+                const bool alive = !done;
+                float2 m = s_mu[j];
+                float4 c = s_co[j];
+                float dx = m.x - fx, dy = m.y - fy;
+                float power = -0.5f * (c.x * dx * dx + c.z * dy * dy) - c.y * dx * dy;
+                float beta = c.w + power;
+                const bool culled = beta < CULL_LN;
+                const bool keep = alive && !culled;
+                if (COUNT) nc += (alive && culled) ? 1u : 0u;
+                if (__ballot(keep) == 0) {
+                    if (__ballot(alive) == 0) break;
+                    continue;
+                }
+                float alpha = fminf(ALPHA_MAX, __expf(beta));
+                float test = fmaf(-alpha, T, T);
+                const bool stop = keep && test < T_MIN;
+                const bool blend = keep && !stop;
+                if (stop) {
+                    done = true;
+                    if (COUNT) nt = 1;
+                }
+                if (blend) {
+                    float w = alpha * T;
+                    float4 col = s_rgb[j];
+                    C0 = fmaf(col.x, w, C0);
+                    C1 = fmaf(col.y, w, C1);
+                    C2 = fmaf(col.z, w, C2);
+                    T = test;
+                    last = b0 - start + (uint32_t)j + 1u;
+                    if (COUNT) ++nb;
+                }
+            }
+        } else if (!done) {
+            // Algorithm 1 as written, per lane: alpha = o exp(-q/2), then the
+            // 1/255 test
             for (int j = 0; j < cnt; ++j) {
                 float2 m = s_mu[j];
                 float4 c = s_co[j];
                 float dx = m.x - fx, dy = m.y - fy;
                 float power = -0.5f * (c.x * dx * dx + c.z * dy * dy) - c.y * dx * dy;
-                float alpha;
-                if (EARLY) {
-                    float beta = c.w + power;
-                    if (beta < CULL_LN) {
-                        if (COUNT) ++nc;
-                        continue;
-                    }
-                    alpha = fminf(ALPHA_MAX, __expf(beta));
-                } else {
-                    alpha = fminf(ALPHA_MAX, c.w * __expf(power));
-                    if (alpha < CULL_ALPHA) {
-                        if (COUNT) ++nc;
-                        continue;
-                    }
+                float alpha = fminf(ALPHA_MAX, c.w * __expf(power));
+                if (alpha < CULL_ALPHA) {
+                    if (COUNT) ++nc;
+                    continue;
                 }
                 float test = fmaf(-alpha, T, T);
                 if (test < T_MIN) {

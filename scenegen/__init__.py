@@ -117,6 +117,23 @@ def scene_3d(P: int, seed: int, n_clusters: int = 64) -> Scene3D:
                    sh=sh.astype(np.float32))
 
 
+def perturbed_scene(sc: Scene3D, seed: int, mean_std: float = 0.01, logit_std: float = 0.5,
+                    sh_std: float = 0.05) -> Scene3D:
+    """A perturbed copy of a 3D scene (the training step's target scene).
+    Draw order: mean offsets N(0, mean_std) (P x 3), opacity-logit offsets
+    N(0, logit_std) (P), SH offsets N(0, sh_std) (P x 48); scales and
+    rotations are kept."""
+    g = _rng(seed)
+    P = sc.P
+    means = sc.means.astype(np.float64) + g.normal(0.0, mean_std, (P, 3))
+    o = np.clip(sc.opacities.astype(np.float64), 1e-7, 1.0 - 1e-7)
+    logit = np.log(o) - np.log1p(-o) + g.normal(0.0, logit_std, P)
+    opac = 1.0 / (1.0 + np.exp(-logit))
+    sh = sc.sh.astype(np.float64) + g.normal(0.0, sh_std, (P, SH_COEFFS * 3)).reshape(P, SH_COEFFS, 3)
+    return Scene3D(means=means.astype(np.float32), scales=sc.scales.copy(), quats=sc.quats.copy(),
+                   opacities=opac.astype(np.float32), sh=sh.astype(np.float32))
+
+
 @dataclass
 class Scene2D:
     """Already-projected Gaussians (the rasteriser's own input format,
@@ -197,7 +214,7 @@ CONFIGS = {
     "fwd_4k_6M": dict(kind="3d", P=6_000_000, width=3840, height=2160, seed=1003,
                       pose=0, n_poses=10),
     "train_1600x1064_1M": dict(kind="3d", P=1_000_000, width=1600, height=1064, seed=1004,
-                               pose=0, n_poses=1),
+                               pose=0, n_poses=1, target_seed=2004),
     # one scene, 16 cameras on the orbit; camera k has resolution k mod 4
     "multiview_2M_16": dict(kind="3d", P=2_000_000, seed=1005, n_views=16,
                             resolutions=((640, 480), (1280, 720), (1920, 1080), (2560, 1440))),
