@@ -146,12 +146,13 @@ def train_step(args):
     means, scales, quats, sh, opac = dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), dev(sc.opacities)
     # target: the perturbed copy of the scene rendered once by the FP32 path
     tsc = scenegen.perturbed_scene(sc, cfg["target_seed"])
-    tpre = gs.preprocess(dev(tsc.means), dev(tsc.scales), dev(tsc.quats), dev(tsc.sh), cam)
+    tpre = gs.preprocess(dev(tsc.means), dev(tsc.scales), dev(tsc.quats), dev(tsc.opacities),
+                         dev(tsc.sh), cam)
     tbs = gs.bin_sort(tpre["means2d"], tpre["radii"], tpre["depths"], W, H)
     target = gs.rasterize_fwd(W, H, tbs.ranges, tbs.sorted_ids, tpre["means2d"], tpre["conics"],
-                              dev(tsc.opacities), tpre["rgb"], "fp32").rgb.clone()
+                              tpre["log_opacities"], tpre["rgb"], "fp32").rgb.clone()
     del tsc, tpre, tbs
-    pre = gs.preprocess(means, scales, quats, sh, cam)
+    pre = gs.preprocess(means, scales, quats, opac, sh, cam)
     probe = gs.BinSorter(sc.P, 0, W, H)
     probe(pre["means2d"], pre["radii"], pre["depths"])
     bs = gs.BinSorter(sc.P, int(probe.n_splats() * 1.1) + 1024, W, H)
@@ -161,15 +162,15 @@ def train_step(args):
     def step(ev=None):
         if ev:
             ev[0].record()
-        p = gs.preprocess(means, scales, quats, sh, cam)
+        p = gs.preprocess(means, scales, quats, opac, sh, cam)
         bs(p["means2d"], p["radii"], p["depths"])
-        rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], prec)
+        rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec)
         if ev:
             ev[1].record()
         dimg = torch.sign(rz.rgb - target) / rz.rgb.numel()
         if ev:
             ev[2].record()
-        gs.rasterize_bwd(W, H, bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"],
+        gs.rasterize_bwd(W, H, bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"],
                          rz.T, rz.n_contrib, dimg, prec)
         if ev:
             ev[3].record()
@@ -218,13 +219,13 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
     for pose in poses:
         c = scenegen.make_camera(cfg, pose)
         cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
-        pre = gs.preprocess(means, scales, quats, sh, cam)
+        pre = gs.preprocess(means, scales, quats, opac, sh, cam)
         probe = gs.BinSorter(P, 0, W, H)
         probe(pre["means2d"], pre["radii"], pre["depths"])
         N = probe.n_splats()
         bs = gs.BinSorter(P, int(N * 1.1) + 1024, W, H)
         bs(pre["means2d"], pre["radii"], pre["depths"])
-        rz(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac, pre["rgb"], "fp32", count=True)
+        rz(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], pre["log_opacities"], pre["rgb"], "fp32", count=True)
         torch.cuda.synchronize()
         cnt = rz.counters.cpu().numpy()
         pairs, surv = int(cnt[3]), int(cnt[0] + cnt[2])
@@ -233,10 +234,10 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
         for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split"):
             def frame(ev):
                 ev[0].record()
-                p = gs.preprocess(means, scales, quats, sh, cam)
+                p = gs.preprocess(means, scales, quats, opac, sh, cam)
                 bs(p["means2d"], p["radii"], p["depths"])
                 ev[1].record()
-                rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], prec)
+                rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec)
                 ev[2].record()
             evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(warmup + steps)]
             for e in evs:
@@ -255,16 +256,16 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
         row["speedup_frame_fp16_vs_fp32"] = row["fp32"]["ms_per_frame"] / row["fp16_g2l_split"]["ms_per_frame"]
         # the FP16 frame with precise Gaussian-tile intersection
         probe_p = gs.BinSorter(P, 0, W, H, precise=True)
-        probe_p(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], opac)
+        probe_p(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], pre["log_opacities"])
         Np = probe_p.n_splats()
         bsp = gs.BinSorter(P, int(Np * 1.1) + 1024, W, H, precise=True)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(warmup + steps)]
         for e in evs:
             e[0].record()
-            p = gs.preprocess(means, scales, quats, sh, cam)
-            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], opac)
+            p = gs.preprocess(means, scales, quats, opac, sh, cam)
+            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], p["log_opacities"])
             e[1].record()
-            rz(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], "fp16_g2l_split")
+            rz(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], "fp16_g2l_split")
             e[2].record()
         torch.cuda.synchronize()
         row["fp16_g2l_split_precise"] = {
@@ -344,7 +345,8 @@ def multiview(args):
                                                reps=5, warmup=1)))
     per_view_raster = float(np.median(autotune.time_ms(mv.raster_per_view, reps=5, warmup=1)))
     single_pre = float(np.median(autotune.time_ms(
-        lambda: [gs.preprocess(scene["means3d"], scene["scales"], scene["quats"], scene["sh"], c)
+        lambda: [gs.preprocess(scene["means3d"], scene["scales"], scene["quats"], scene["opacities"],
+                               scene["sh"], c)
                  for c in cams], reps=3, warmup=1)))
 
     g = mv.capture()
@@ -457,15 +459,15 @@ def binsort_only(args):
     cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     opac = dev(sc.opacities)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), opac, dev(sc.sh), cam)
     bp = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, conics=pre["conics"],
-                     opacities=opac, precise=True)
+                     log_opacities=pre["log_opacities"], precise=True)
     b3 = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     tp, t3 = [], []
     for _ in range(args.steps):
         ev[0].record()
-        bp(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], opac)
+        bp(pre["means2d"], pre["radii"], pre["depths"], pre["conics"], pre["log_opacities"])
         ev[1].record()
         b3(pre["means2d"], pre["radii"], pre["depths"])
         ev[2].record()
@@ -529,7 +531,7 @@ def main():
     P = scene.P
 
     # sizing pass (one host sync): splat count -> capacity
-    pre = gs.preprocess(means, scales, quats, sh, cam)
+    pre = gs.preprocess(means, scales, quats, opac, sh, cam)
     probe = gs.BinSorter(P, 0, W, H)
     probe(pre["means2d"], pre["radii"], pre["depths"])
     N = probe.n_splats()
@@ -540,7 +542,7 @@ def main():
 
     # pair count (numerator) from the FP32 path with counters
     bs(pre["means2d"], pre["radii"], pre["depths"])
-    rz(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac, pre["rgb"], "fp32", count=True)
+    rz(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], pre["log_opacities"], pre["rgb"], "fp32", count=True)
     torch.cuda.synchronize()
     cnt = rz.counters.cpu().numpy()
     pairs, survivors = int(cnt[3]), int(cnt[0] + cnt[2])
@@ -559,13 +561,13 @@ def main():
     def frame(prec, ev=None):
         if ev is not None:
             ev[0].record()
-        p = gs.preprocess(means, scales, quats, sh, cam)
+        p = gs.preprocess(means, scales, quats, opac, sh, cam)
         if ev is not None:
             ev[1].record()
         bs(p["means2d"], p["radii"], p["depths"])
         if ev is not None:
             ev[2].record()
-        rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"], prec)
+        rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec)
         if ev is not None:
             ev[3].record()
 
@@ -601,16 +603,16 @@ def main():
     # kernel only, same lists, PSNR against the FP32 path's image
     sweep = {}
     if not args.no_sweep:
-        p2 = gs.preprocess(means, scales, quats, sh, cam)
+        p2 = gs.preprocess(means, scales, quats, opac, sh, cam)
         bs(p2["means2d"], p2["radii"], p2["depths"])
         for prec in gs.PRECISIONS:
             for _ in range(3):
-                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], opac, p2["rgb"], prec)
+                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], p2["log_opacities"], p2["rgb"], prec)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ts = []
             for _ in range(10):
                 ev0.record()
-                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], opac, p2["rgb"], prec)
+                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], p2["log_opacities"], p2["rgb"], prec)
                 ev1.record()
                 torch.cuda.synchronize()
                 ts.append(ev0.elapsed_time(ev1))
@@ -622,9 +624,9 @@ def main():
     # (fewer splats; same image up to near-threshold fragments)
     precise = None
     if not args.no_precise:
-        pp = gs.preprocess(means, scales, quats, sh, cam)
+        pp = gs.preprocess(means, scales, quats, opac, sh, cam)
         probe_p = gs.BinSorter(P, 0, W, H, precise=True)
-        probe_p(pp["means2d"], pp["radii"], pp["depths"], pp["conics"], opac)
+        probe_p(pp["means2d"], pp["radii"], pp["depths"], pp["conics"], pp["log_opacities"])
         Np = probe_p.n_splats()
         bsp = gs.BinSorter(P, int(Np * 1.1) + 1024, W, H, precise=True)
         rzp = gs.Rasterizer(W, H)
@@ -632,13 +634,13 @@ def main():
         def frame_p(ev=None):
             if ev is not None:
                 ev[0].record()
-            p = gs.preprocess(means, scales, quats, sh, cam)
+            p = gs.preprocess(means, scales, quats, opac, sh, cam)
             if ev is not None:
                 ev[1].record()
-            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], opac)
+            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], p["log_opacities"])
             if ev is not None:
                 ev[2].record()
-            rzp(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], opac, p["rgb"],
+            rzp(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"],
                 args.precision)
             if ev is not None:
                 ev[3].record()
@@ -716,9 +718,9 @@ def main():
                                          "unit": "TFLOP/s", "frac": mfma_exec / FP16_MFMA_PEAK_TFLOPS,
                                          "source": "SQ_INSTS_MFMA x 32768 flop (counters)"}
         other["raster_valu_issue_frac"] = counters.get("valu_issue_utilisation")
-    # preprocess: 236 B read + 44 B written per Gaussian; bin/sort: per
+    # preprocess: 240 B read + 48 B written per Gaussian; bin/sort: per
     # Gaussian 4 x 16 B (depth passes) + 40 B, per splat 52 B
-    pre_bytes = 280.0 * P
+    pre_bytes = 288.0 * P
     bin_bytes = P * (4 * 16 + 40) + 52.0 * N
     other["preprocess_hbm"] = {"achieved": pre_bytes / (mean[0] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": pre_bytes / (mean[0] / 1e3) / 1e9 / HBM_PEAK_GBS}

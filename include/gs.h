@@ -9,6 +9,12 @@
  * computation optionally recast as a matrix product on the matrix cores
  * (EarlyCull, Frag2Mat and G2L, Sec. 4.1-4.3).
  *
+ * Opacity crosses the boundary as its natural logarithm: preprocess turns
+ * each opacity o into ln o once per Gaussian, and the rasterisers and the
+ * precise binning take ln o, since the exponent the rasteriser evaluates is
+ * beta = ln o - 1/2 d^T Sigma'^-1 d (Sec. 4.1) and no per-tile logarithm is
+ * then needed.
+ *
  * General conventions (all entry points):
  *   - Every pointer argument except `cam`, `background` and explicit host
  *     pointers is a DEVICE pointer, owned by the caller; the library never
@@ -81,7 +87,7 @@ typedef struct {
 /* Returns a static, human-readable name for a gs_status value. */
 const char *gs_status_string(int status);
 
-/* Library ABI version (major * 100 + minor). */
+/* Library ABI version (major * 100 + minor); 200 = opacity as ln o. */
 int gs_version(void);
 
 /*
@@ -89,11 +95,13 @@ int gs_version(void);
  * mu' = W mu, Sigma' = J W Sigma W^T J^T).
  *   means3d  [P][3]  world-space means            scales [P][3] per-axis std
  *   quats    [P][4]  rotation (w, x, y, z), normalised internally
+ *   opacities [P]    o in [0, 1]
  *   sh       [P][16][3] real SH coefficients (Condon-Shortley phase), degree
  *            sh_degree in 0..3 (coefficients beyond the degree are ignored)
  * Outputs, per Gaussian:
  *   means2d [P][2] pixel-space centre; conics [P][3] = (s11, s12, s22) of
- *   Sigma'^-1; depths [P] view-space z; radii [P] = ceil(3 sqrt(lambda_max))
+ *   Sigma'^-1; log_opacities [P] = ln o (-inf for o = 0; written for every
+ *   Gaussian); depths [P] view-space z; radii [P] = ceil(3 sqrt(lambda_max))
  *   (0 = dropped: behind near_z, det(Sigma') <= 0, or touching no tile);
  *   rgb [P][3] = max(0, SH(view direction) + 0.5); tiles_touched [P].
  * The 2x2 determinant and inverse run in FP64 when FP32 would cancel.
@@ -101,17 +109,20 @@ int gs_version(void);
  * camera size or sh_degree; GS_ERR_HIP if the launch fails.
  */
 gs_status gs_preprocess(int32_t P, const float *means3d, const float *scales, const float *quats,
-                        const float *sh, int32_t sh_degree, const gs_camera *cam,
-                        float *means2d, float *conics, float *depths, int32_t *radii,
-                        float *rgb, uint32_t *tiles_touched, void *stream);
+                        const float *opacities, const float *sh, int32_t sh_degree,
+                        const gs_camera *cam, float *means2d, float *conics,
+                        float *log_opacities, float *depths, int32_t *radii, float *rgb,
+                        uint32_t *tiles_touched, void *stream);
 
 /*
  * gs_preprocess_2d -- pre-projected Gaussians: Sigma' = (a, b, c) given as
- * cov2d [P][3] (no dilation).  Writes conics, radii and tiles_touched as
- * gs_preprocess does.  Errors as gs_preprocess.
+ * cov2d [P][3] (no dilation), opacities [P] in [0, 1].  Writes conics,
+ * log_opacities, radii and tiles_touched as gs_preprocess does.  Errors as
+ * gs_preprocess.
  */
-gs_status gs_preprocess_2d(int32_t P, const float *means2d, const float *cov2d, int32_t width,
-                           int32_t height, float *conics, int32_t *radii, uint32_t *tiles_touched,
+gs_status gs_preprocess_2d(int32_t P, const float *means2d, const float *cov2d,
+                           const float *opacities, int32_t width, int32_t height, float *conics,
+                           float *log_opacities, int32_t *radii, uint32_t *tiles_touched,
                            void *stream);
 
 /*
@@ -134,7 +145,9 @@ size_t gs_bin_sort_workspace_bytes(int32_t P, uint32_t capacity, int32_t width, 
  * The count N is data-dependent and stays on the device.  If N > capacity the
  * lists are not built, every tile range is empty (the frame renders as
  * background) and *d_num_splats still receives N, so the caller can read it
- * after synchronising and retry with a larger capacity.
+ * after synchronising and retry with a larger capacity.  *d_num_splats is
+ * thus also the call's device-side status: N <= capacity means the lists are
+ * complete, N > capacity means they overflowed (no separate status word).
  * capacity must be below 2^31.
  * Errors: GS_ERR_INVALID_ARG for bad sizes or pointers; GS_ERR_CAPACITY if
  * workspace_bytes < gs_bin_sort_workspace_bytes(...); GS_ERR_HIP.
@@ -184,16 +197,22 @@ size_t gs_bin_sort_precise_workspace_bytes(int32_t P, uint32_t capacity, int32_t
  * (S = conic, d = point - mean).  Every dropped fragment is culled at each
  * pixel of its tile, so the rendered image is that of gs_bin_sort's lists;
  * fewer splats are sorted and visited.  Per tile row the kept tiles form one
- * contiguous run, computed in FP64 with the threshold enlarged by a
- * relative 1e-9 (rounding can keep a boundary tile, never drop one).
- *   conics [P][3] (s11, s12, s22) and opacities [P] as for gs_rasterize_fwd;
+ * contiguous run, found from the ellipse's chord in FP32 (determinant from
+ * exact FP64 products) with every bound enlarged beyond its rounding: the
+ * threshold 2 (ln o + ln 255) by a relative 4e-6 plus 4e-5, the ellipse's
+ * vertical extent and half-widths by a relative 1e-6, the row's band and run
+ * by 4e-6 (extent + |centre|) + 1e-4 px.  Rounding can thus keep a boundary
+ * tile, never drop one.
+ *   conics [P][3] (s11, s12, s22) and log_opacities [P] (ln o) as for
+ *   gs_rasterize_fwd;
  *   everything else exactly as gs_bin_sort (order within a tile, capacity
  *   and overflow behaviour, d_num_splats).
  * Errors: as gs_bin_sort; GS_ERR_CAPACITY if workspace_bytes <
  * gs_bin_sort_precise_workspace_bytes(...).
  */
 gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const int32_t *radii,
-                              const float *depths, const float *conics, const float *opacities,
+                              const float *depths, const float *conics,
+                              const float *log_opacities,
                               int32_t width, int32_t height, uint32_t capacity, void *workspace,
                               size_t workspace_bytes, uint32_t *sorted_ids, uint32_t *tile_ranges,
                               uint32_t *d_num_splats, void *stream);
@@ -216,7 +235,7 @@ size_t gs_bin_sort_multiview_workspace_bytes(int32_t nviews, int32_t P, uint32_t
  *   nviews in [1, GS_MAX_BIN_VIEWS]; widths[v], heights[v] HOST arrays;
  *   means2d [nviews][P][2], radii [nviews][P], depths [nviews][P] and, when
  *   precise, conics [nviews][P][3] (as gs_preprocess_multiview writes them)
- *   and opacities [P] (shared by the views);
+ *   and log_opacities [P] (ln o, shared by the views);
  *   sorted_ids [capacity]     Gaussian ids (0..P-1) of every view's lists
  *   tile_ranges [T][2]         T = sum over views of ceil(w/16) ceil(h/16);
  *                              view v's tiles come after those of views < v,
@@ -236,7 +255,7 @@ size_t gs_bin_sort_multiview_workspace_bytes(int32_t nviews, int32_t P, uint32_t
 gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths,
                                 const int32_t *heights, const float *means2d,
                                 const int32_t *radii, const float *depths, const float *conics,
-                                const float *opacities, int32_t precise, uint32_t capacity,
+                                const float *log_opacities, int32_t precise, uint32_t capacity,
                                 void *workspace, size_t workspace_bytes, uint32_t *sorted_ids,
                                 uint32_t *tile_ranges, uint32_t *d_num_splats,
                                 uint32_t *d_view_splats, void *stream);
@@ -249,7 +268,8 @@ gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths
  *   -ln 255, Sec. 4.1); stop the pixel, without compositing, when
  *   T - alpha T < 1e-4; otherwise C += c alpha T and T -= alpha T.
  * How beta is computed is selected by `precision` (gs_precision).
- *   means2d [P][2], conics [P][3], opacities [P] in (0, 1], rgb [P][3]
+ *   means2d [P][2], conics [P][3], log_opacities [P] = ln o (o in [0, 1],
+ *   as gs_preprocess writes it), rgb [P][3]
  *   background  HOST pointer to 3 floats composited as C + T * bg (NULL = 0)
  *   out_rgb [3][H][W] planar colour; out_T [H][W] final transmittance;
  *   out_ncontrib [H][W] 1-based position in the tile list of the last
@@ -261,7 +281,7 @@ gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths
  */
 gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
                            const uint32_t *sorted_ids, const float *means2d, const float *conics,
-                           const float *opacities, const float *rgb, const float *background,
+                           const float *log_opacities, const float *rgb, const float *background,
                            int32_t precision, float *out_rgb, float *out_T, uint32_t *out_ncontrib,
                            uint64_t *d_counters, void *stream);
 
@@ -272,7 +292,7 @@ gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_r
  * each pixel's blended fragments in reverse, recovering the transmittance by
  * division, and ADDS to (caller zeroes):
  *   dL_dmeans2d [P][2], dL_dconics [P][3] (d/d(s11, s12, s22)),
- *   dL_dopacities [P], dL_drgb [P][3].
+ *   dL_dopacities [P] (d/do, o = exp(log_opacities)), dL_drgb [P][3].
  * The derivative is that of alpha = min(0.99, o exp(beta)) with the clamp's
  * zero slope where it is active; culled and skipped fragments contribute
  * nothing.  `precision` must be the one the forward used: fragments are
@@ -283,7 +303,7 @@ gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_r
  */
 gs_status gs_rasterize_bwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
                            const uint32_t *sorted_ids, const float *means2d, const float *conics,
-                           const float *opacities, const float *rgb, const float *background,
+                           const float *log_opacities, const float *rgb, const float *background,
                            int32_t precision, const float *out_T, const uint32_t *out_ncontrib,
                            const float *dL_dimg, float *dL_dmeans2d, float *dL_dconics,
                            float *dL_dopacities, float *dL_drgb, void *stream);
@@ -298,7 +318,7 @@ gs_status gs_rasterize_bwd(int32_t width, int32_t height, const uint32_t *tile_r
  */
 gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t tile, const uint32_t *tile_ranges,
                             const uint32_t *sorted_ids, const float *means2d, const float *conics,
-                            const float *opacities, int32_t precision, int32_t count,
+                            const float *log_opacities, int32_t precision, int32_t count,
                             float *out_beta, void *stream);
 
 /*
@@ -309,13 +329,15 @@ gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t tile, const u
  * view-major with a stride of P entries: view v's means2d start at
  * means2d + 2 * v * P, conics at conics + 3 * v * P, depths/radii/
  * tiles_touched at + v * P, rgb at rgb + 3 * v * P; each view's slice is
- * what gs_preprocess with that camera writes.
+ * what gs_preprocess with that camera writes.  log_opacities [P] (ln o, view
+ * independent) is written once.
  * Errors: as gs_preprocess, plus GS_ERR_INVALID_ARG for nviews out of range.
  */
 gs_status gs_preprocess_multiview(int32_t P, const float *means3d, const float *scales,
-                                  const float *quats, const float *sh, int32_t sh_degree,
-                                  int32_t nviews, const gs_camera *cams, float *means2d,
-                                  float *conics, float *depths, int32_t *radii, float *rgb,
+                                  const float *quats, const float *opacities, const float *sh,
+                                  int32_t sh_degree, int32_t nviews, const gs_camera *cams,
+                                  float *means2d, float *conics, float *log_opacities,
+                                  float *depths, int32_t *radii, float *rgb,
                                   uint32_t *tiles_touched, void *stream);
 
 /* One view of a batched frame: its image size, its own gs_bin_sort lists,
@@ -327,7 +349,7 @@ typedef struct {
     const uint32_t *sorted_ids;  /* tile-major splat list of this view       */
     const float *means2d;        /* [P][2]                                   */
     const float *conics;         /* [P][3]                                   */
-    const float *opacities;      /* [P]                                      */
+    const float *log_opacities;  /* [P] ln o                                 */
     const float *rgb;            /* [P][3]                                   */
     float background[3];         /* composited as C + T * bg                 */
     float *out_rgb;              /* [3][H][W]                                */

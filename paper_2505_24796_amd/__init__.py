@@ -60,7 +60,7 @@ class gs_camera(ctypes.Structure):
 class gs_view(ctypes.Structure):
     _fields_ = [("width", c_int32), ("height", c_int32), ("tile_ranges", c_void_p),
                 ("sorted_ids", c_void_p), ("means2d", c_void_p), ("conics", c_void_p),
-                ("opacities", c_void_p), ("rgb", c_void_p), ("background", c_float * 3),
+                ("log_opacities", c_void_p), ("rgb", c_void_p), ("background", c_float * 3),
                 ("out_rgb", c_void_p), ("out_T", c_void_p), ("out_ncontrib", c_void_p)]
 
 
@@ -91,10 +91,10 @@ def lib() -> ctypes.CDLL:
         L.gs_status_string.argtypes = [ctypes.c_int]
         L.gs_version.restype = ctypes.c_int
         L.gs_preprocess.restype = ctypes.c_int
-        L.gs_preprocess.argtypes = [c_int32, vp, vp, vp, vp, c_int32, POINTER(gs_camera),
-                                    vp, vp, vp, vp, vp, vp, vp]
+        L.gs_preprocess.argtypes = [c_int32, vp, vp, vp, vp, vp, c_int32, POINTER(gs_camera),
+                                    vp, vp, vp, vp, vp, vp, vp, vp]
         L.gs_preprocess_2d.restype = ctypes.c_int
-        L.gs_preprocess_2d.argtypes = [c_int32, vp, vp, c_int32, c_int32, vp, vp, vp, vp]
+        L.gs_preprocess_2d.argtypes = [c_int32, vp, vp, vp, c_int32, c_int32, vp, vp, vp, vp, vp]
         L.gs_bin_sort_workspace_bytes.restype = c_size_t
         L.gs_bin_sort_workspace_bytes.argtypes = [c_int32, c_uint32, c_int32, c_int32]
         L.gs_bin_sort.restype = ctypes.c_int
@@ -126,8 +126,8 @@ def lib() -> ctypes.CDLL:
                                             vp, vp, vp, vp, vp, c_int32, c_uint32, vp, c_size_t,
                                             vp, vp, vp, vp, vp]
         L.gs_preprocess_multiview.restype = ctypes.c_int
-        L.gs_preprocess_multiview.argtypes = [c_int32, vp, vp, vp, vp, c_int32, c_int32,
-                                              POINTER(gs_camera), vp, vp, vp, vp, vp, vp, vp]
+        L.gs_preprocess_multiview.argtypes = [c_int32, vp, vp, vp, vp, vp, c_int32, c_int32,
+                                              POINTER(gs_camera), vp, vp, vp, vp, vp, vp, vp, vp]
         L.gs_batch_plan_bytes.restype = c_size_t
         L.gs_batch_plan_bytes.argtypes = [c_int32]
         L.gs_batch_workspace_bytes.restype = c_size_t
@@ -186,35 +186,44 @@ def make_camera(viewmat, fx, fy, cx, cy, width, height, near_z=0.2, frustum_guar
     return c
 
 
-def preprocess(means3d, scales, quats, sh, cam: gs_camera, sh_degree: int = 3) -> dict:
+def preprocess(means3d, scales, quats, opacities, sh, cam: gs_camera, sh_degree: int = 3) -> dict:
+    """gs_preprocess: means2d, conics, log_opacities (ln o), depths, radii,
+    rgb, tiles_touched."""
     P = means3d.shape[0]
     f32 = torch.float32
-    for n, t in (("means3d", means3d), ("scales", scales), ("quats", quats), ("sh", sh)):
+    for n, t in (("means3d", means3d), ("scales", scales), ("quats", quats),
+                 ("opacities", opacities), ("sh", sh)):
         _dev(t, f32, n)
     dev = means3d.device
     out = dict(means2d=torch.empty(P, 2, dtype=f32, device=dev),
                conics=torch.empty(P, 3, dtype=f32, device=dev),
+               log_opacities=torch.empty(P, dtype=f32, device=dev),
                depths=torch.empty(P, dtype=f32, device=dev),
                radii=torch.empty(P, dtype=torch.int32, device=dev),
                rgb=torch.empty(P, 3, dtype=f32, device=dev),
                tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
-    st = lib().gs_preprocess(P, _ptr(means3d), _ptr(scales), _ptr(quats), _ptr(sh), sh_degree,
-                             ctypes.byref(cam), _ptr(out["means2d"]), _ptr(out["conics"]),
+    st = lib().gs_preprocess(P, _ptr(means3d), _ptr(scales), _ptr(quats), _ptr(opacities),
+                             _ptr(sh), sh_degree, ctypes.byref(cam), _ptr(out["means2d"]),
+                             _ptr(out["conics"]), _ptr(out["log_opacities"]),
                              _ptr(out["depths"]), _ptr(out["radii"]), _ptr(out["rgb"]),
                              _ptr(out["tiles_touched"]), _stream())
     _check("gs_preprocess", st)
     return out
 
 
-def preprocess_2d(means2d, cov2d, width: int, height: int) -> dict:
+def preprocess_2d(means2d, cov2d, opacities, width: int, height: int) -> dict:
+    """gs_preprocess_2d: conics, log_opacities (ln o), radii, tiles_touched."""
     P = means2d.shape[0]
     _dev(means2d, torch.float32, "means2d")
     _dev(cov2d, torch.float32, "cov2d")
+    _dev(opacities, torch.float32, "opacities")
     dev = means2d.device
     out = dict(conics=torch.empty(P, 3, dtype=torch.float32, device=dev),
+               log_opacities=torch.empty(P, dtype=torch.float32, device=dev),
                radii=torch.empty(P, dtype=torch.int32, device=dev),
                tiles_touched=torch.empty(P, dtype=torch.int32, device=dev))
-    st = lib().gs_preprocess_2d(P, _ptr(means2d), _ptr(cov2d), width, height, _ptr(out["conics"]),
+    st = lib().gs_preprocess_2d(P, _ptr(means2d), _ptr(cov2d), _ptr(opacities), width, height,
+                                _ptr(out["conics"]), _ptr(out["log_opacities"]),
                                 _ptr(out["radii"]), _ptr(out["tiles_touched"]), _stream())
     _check("gs_preprocess_2d", st)
     return out
@@ -224,7 +233,7 @@ class BinSorter:
     """Owns a workspace and output buffers for gs_bin_sort at a fixed
     (P, capacity, width, height); reusable across frames (no allocation per
     call).  With ``precise`` it runs gs_bin_sort_precise (then the call
-    also takes the conics and opacities)."""
+    also takes the conics and ln o)."""
 
     def __init__(self, P: int, capacity: int, width: int, height: int, device="cuda",
                  workspace: torch.Tensor | None = None, precise: bool = False):
@@ -247,17 +256,18 @@ class BinSorter:
         self.ranges = torch.empty(gx * gy, 2, dtype=torch.int32, device=device)
         self.num_splats = torch.zeros(1, dtype=torch.int32, device=device)
 
-    def __call__(self, means2d, radii, depths, conics=None, opacities=None):
+    def __call__(self, means2d, radii, depths, conics=None, log_opacities=None):
         _dev(means2d, torch.float32, "means2d")
         _dev(radii, torch.int32, "radii")
         _dev(depths, torch.float32, "depths")
         if self.precise:
-            if conics is None or opacities is None:
-                raise ValueError("precise binning needs conics and opacities")
+            if conics is None or log_opacities is None:
+                raise ValueError("precise binning needs conics and log_opacities")
             _dev(conics, torch.float32, "conics")
-            _dev(opacities, torch.float32, "opacities")
+            _dev(log_opacities, torch.float32, "log_opacities")
             st = lib().gs_bin_sort_precise(self.P, _ptr(means2d), _ptr(radii), _ptr(depths),
-                                           _ptr(conics), _ptr(opacities), self.width, self.height,
+                                           _ptr(conics), _ptr(log_opacities), self.width,
+                                           self.height,
                                            self.capacity, _ptr(self.workspace),
                                            self.workspace.numel(), _ptr(self.sorted_ids),
                                            _ptr(self.ranges), _ptr(self.num_splats), _stream())
@@ -304,21 +314,21 @@ class MultiViewBinSorter:
     def ranges(self, v: int) -> torch.Tensor:
         return self.all_ranges[self.tile_base[v]:self.tile_base[v + 1]]
 
-    def __call__(self, means2d, radii, depths, conics=None, opacities=None):
+    def __call__(self, means2d, radii, depths, conics=None, log_opacities=None):
         """means2d [V, P, 2], radii [V, P], depths [V, P] (and, precise,
-        conics [V, P, 3] and opacities [P])."""
+        conics [V, P, 3] and log_opacities [P])."""
         _dev(means2d, torch.float32, "means2d")
         _dev(radii, torch.int32, "radii")
         _dev(depths, torch.float32, "depths")
         if self.precise:
-            if conics is None or opacities is None:
-                raise ValueError("precise binning needs conics and opacities")
+            if conics is None or log_opacities is None:
+                raise ValueError("precise binning needs conics and log_opacities")
             _dev(conics, torch.float32, "conics")
-            _dev(opacities, torch.float32, "opacities")
+            _dev(log_opacities, torch.float32, "log_opacities")
         st = lib().gs_bin_sort_multiview(self.V, self.P, self._w, self._h, _ptr(means2d),
                                          _ptr(radii), _ptr(depths),
                                          _ptr(conics) if self.precise else None,
-                                         _ptr(opacities) if self.precise else None,
+                                         _ptr(log_opacities) if self.precise else None,
                                          int(self.precise), self.capacity, _ptr(self.workspace),
                                          self.workspace.numel(), _ptr(self.sorted_ids),
                                          _ptr(self.all_ranges), _ptr(self.num_splats),
@@ -333,25 +343,29 @@ class MultiViewBinSorter:
         return [int(x) & 0xFFFFFFFF for x in self.view_splats.cpu().tolist()]
 
 
-def preprocess_multiview(means3d, scales, quats, sh, cams, sh_degree: int = 3, out: dict | None = None) -> dict:
+def preprocess_multiview(means3d, scales, quats, opacities, sh, cams, sh_degree: int = 3,
+                         out: dict | None = None) -> dict:
     """gs_preprocess for several cameras in one pass; every output has a
-    leading view axis (V, P, ...)."""
+    leading view axis (V, P, ...) except log_opacities (P,)."""
     P, V = means3d.shape[0], len(cams)
     f32 = torch.float32
-    for n, t in (("means3d", means3d), ("scales", scales), ("quats", quats), ("sh", sh)):
+    for n, t in (("means3d", means3d), ("scales", scales), ("quats", quats),
+                 ("opacities", opacities), ("sh", sh)):
         _dev(t, f32, n)
     dev = means3d.device
     if out is None:
         out = dict(means2d=torch.empty(V, P, 2, dtype=f32, device=dev),
                    conics=torch.empty(V, P, 3, dtype=f32, device=dev),
+                   log_opacities=torch.empty(P, dtype=f32, device=dev),
                    depths=torch.empty(V, P, dtype=f32, device=dev),
                    radii=torch.empty(V, P, dtype=torch.int32, device=dev),
                    rgb=torch.empty(V, P, 3, dtype=f32, device=dev),
                    tiles_touched=torch.empty(V, P, dtype=torch.int32, device=dev))
     arr = (gs_camera * V)(*cams)
-    st = lib().gs_preprocess_multiview(P, _ptr(means3d), _ptr(scales), _ptr(quats), _ptr(sh),
-                                       sh_degree, V, arr, _ptr(out["means2d"]),
-                                       _ptr(out["conics"]), _ptr(out["depths"]),
+    st = lib().gs_preprocess_multiview(P, _ptr(means3d), _ptr(scales), _ptr(quats),
+                                       _ptr(opacities), _ptr(sh), sh_degree, V, arr,
+                                       _ptr(out["means2d"]), _ptr(out["conics"]),
+                                       _ptr(out["log_opacities"]), _ptr(out["depths"]),
                                        _ptr(out["radii"]), _ptr(out["rgb"]),
                                        _ptr(out["tiles_touched"]), _stream())
     _check("gs_preprocess_multiview", st)
@@ -359,16 +373,16 @@ def preprocess_multiview(means3d, scales, quats, sh, cams, sh_degree: int = 3, o
 
 
 def bin_sort(means2d, radii, depths, width: int, height: int, capacity: int | None = None,
-             conics=None, opacities=None, precise: bool = False):
+             conics=None, log_opacities=None, precise: bool = False):
     """One-shot binning.  Without ``capacity`` the splat count is computed by
     a first call with capacity 0 (one host synchronisation)."""
     P = means2d.shape[0]
     if capacity is None:
         probe = BinSorter(P, 0, width, height, device=means2d.device, precise=precise)
-        probe(means2d, radii, depths, conics, opacities)
+        probe(means2d, radii, depths, conics, log_opacities)
         capacity = max(probe.n_splats(), 1)
     bs = BinSorter(P, capacity, width, height, device=means2d.device, precise=precise)
-    bs(means2d, radii, depths, conics, opacities)
+    bs(means2d, radii, depths, conics, log_opacities)
     return bs
 
 
@@ -405,45 +419,46 @@ class Rasterizer:
         self.n_contrib = torch.empty(height, width, dtype=torch.int32, device=device)
         self.counters = torch.zeros(4, dtype=torch.int64, device=device)
 
-    def __call__(self, ranges, sorted_ids, means2d, conics, opacities, rgb, precision="fp32",
+    def __call__(self, ranges, sorted_ids, means2d, conics, log_opacities, rgb, precision="fp32",
                  background=(0.0, 0.0, 0.0), count: bool = False):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         for n, t, dt in (("ranges", ranges, torch.int32), ("sorted_ids", sorted_ids, torch.int32),
                          ("means2d", means2d, torch.float32), ("conics", conics, torch.float32),
-                         ("opacities", opacities, torch.float32), ("rgb", rgb, torch.float32)):
+                         ("log_opacities", log_opacities, torch.float32),
+                         ("rgb", rgb, torch.float32)):
             _dev(t, dt, n)
         bg = (c_float * 3)(*[float(b) for b in background])
         if count:
             self.counters.zero_()
         st = lib().gs_rasterize_fwd(self.width, self.height, _ptr(ranges), _ptr(sorted_ids),
-                                    _ptr(means2d), _ptr(conics), _ptr(opacities), _ptr(rgb), bg,
+                                    _ptr(means2d), _ptr(conics), _ptr(log_opacities), _ptr(rgb), bg,
                                     prec, _ptr(self.rgb), _ptr(self.T), _ptr(self.n_contrib),
                                     _ptr(self.counters) if count else c_void_p(0), _stream())
         _check("gs_rasterize_fwd", st)
         return self.rgb, self.T, self.n_contrib
 
 
-def rasterize_fwd(width, height, ranges, sorted_ids, means2d, conics, opacities, rgb,
+def rasterize_fwd(width, height, ranges, sorted_ids, means2d, conics, log_opacities, rgb,
                   precision="fp32", background=(0.0, 0.0, 0.0), count=False):
     r = Rasterizer(width, height, device=means2d.device)
-    r(ranges, sorted_ids, means2d, conics, opacities, rgb, precision, background, count)
+    r(ranges, sorted_ids, means2d, conics, log_opacities, rgb, precision, background, count)
     return r
 
 
-def rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, opacities, rgb, out_T,
+def rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, log_opacities, rgb, out_T,
                   out_ncontrib, dL_dimg, precision="fp32", background=(0.0, 0.0, 0.0)):
     """Gradients through rasterize_fwd (same precision as the forward): returns
-    dict(means2d, conics, opacities, rgb) of freshly zeroed-then-accumulated
-    tensors."""
+    dict(means2d, conics, opacities (d/do), rgb) of freshly
+    zeroed-then-accumulated tensors."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     for n, t, dt in (("out_T", out_T, torch.float32), ("out_ncontrib", out_ncontrib, torch.int32),
                      ("dL_dimg", dL_dimg, torch.float32)):
         _dev(t, dt, n)
     g = dict(means2d=torch.zeros_like(means2d), conics=torch.zeros_like(conics),
-             opacities=torch.zeros_like(opacities), rgb=torch.zeros_like(rgb))
+             opacities=torch.zeros_like(log_opacities), rgb=torch.zeros_like(rgb))
     bg = (c_float * 3)(*[float(b) for b in background])
     st = lib().gs_rasterize_bwd(width, height, _ptr(ranges), _ptr(sorted_ids), _ptr(means2d),
-                                _ptr(conics), _ptr(opacities), _ptr(rgb), bg, prec, _ptr(out_T),
+                                _ptr(conics), _ptr(log_opacities), _ptr(rgb), bg, prec, _ptr(out_T),
                                 _ptr(out_ncontrib), _ptr(dL_dimg), _ptr(g["means2d"]),
                                 _ptr(g["conics"]), _ptr(g["opacities"]), _ptr(g["rgb"]), _stream())
     _check("gs_rasterize_bwd", st)
@@ -453,34 +468,38 @@ def rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, opacities,
 class RasterizeFn(torch.autograd.Function):
     """Differentiable tile rasteriser: (means2d, conics, opacities, rgb) ->
     image (3, H, W), for fixed per-tile lists.  Both directions run in
-    libgsmfma (gs_rasterize_fwd / gs_rasterize_bwd) with the same precision."""
+    libgsmfma (gs_rasterize_fwd / gs_rasterize_bwd) with the same precision.
+    The rasteriser reads ln o (`log_opacities`, as preprocess writes it from
+    the same `opacities`); the gradient returned for `opacities` is d/do."""
 
     @staticmethod
-    def forward(ctx, means2d, conics, opacities, rgb, ranges, sorted_ids, width, height,
-                precision="fp16_g2l_split", background=(0.0, 0.0, 0.0)):
+    def forward(ctx, means2d, conics, opacities, rgb, log_opacities, ranges, sorted_ids, width,
+                height, precision="fp16_g2l_split", background=(0.0, 0.0, 0.0)):
         r = Rasterizer(width, height, device=means2d.device)
         means2d, conics = means2d.contiguous(), conics.contiguous()
-        opacities, rgb = opacities.contiguous(), rgb.contiguous()
-        r(ranges, sorted_ids, means2d, conics, opacities, rgb, precision, background)
-        ctx.save_for_backward(means2d, conics, opacities, rgb, ranges, sorted_ids, r.T, r.n_contrib)
+        log_opacities, rgb = log_opacities.contiguous(), rgb.contiguous()
+        r(ranges, sorted_ids, means2d, conics, log_opacities, rgb, precision, background)
+        ctx.save_for_backward(means2d, conics, log_opacities, rgb, ranges, sorted_ids, r.T,
+                              r.n_contrib)
         ctx.cfg = (width, height, precision, tuple(background))
         return r.rgb
 
     @staticmethod
     def backward(ctx, dL_dimg):
-        means2d, conics, opacities, rgb, ranges, sorted_ids, T, nc = ctx.saved_tensors
+        means2d, conics, log_opacities, rgb, ranges, sorted_ids, T, nc = ctx.saved_tensors
         width, height, precision, background = ctx.cfg
-        g = rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, opacities, rgb, T, nc,
-                          dL_dimg.contiguous(), precision, background)
-        return g["means2d"], g["conics"], g["opacities"], g["rgb"], None, None, None, None, None, None
+        g = rasterize_bwd(width, height, ranges, sorted_ids, means2d, conics, log_opacities, rgb, T,
+                          nc, dL_dimg.contiguous(), precision, background)
+        return (g["means2d"], g["conics"], g["opacities"], g["rgb"], None, None, None, None, None,
+                None, None)
 
 
-def rasterize_beta(width, height, tile, ranges, sorted_ids, means2d, conics, opacities,
+def rasterize_beta(width, height, tile, ranges, sorted_ids, means2d, conics, log_opacities,
                    precision="fp16_g2l_split", count=32):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     out = torch.empty(count, 256, dtype=torch.float32, device=means2d.device)
     st = lib().gs_rasterize_beta(width, height, int(tile), _ptr(ranges), _ptr(sorted_ids),
-                                 _ptr(means2d), _ptr(conics), _ptr(opacities), prec, int(count),
+                                 _ptr(means2d), _ptr(conics), _ptr(log_opacities), prec, int(count),
                                  _ptr(out), _stream())
     _check("gs_rasterize_beta", st)
     return out
@@ -489,11 +508,11 @@ def rasterize_beta(width, height, tile, ranges, sorted_ids, means2d, conics, opa
 def render(means3d, scales, quats, sh, opacities, cam: gs_camera, precision="fp16_g2l_split",
            capacity=None, background=(0.0, 0.0, 0.0)):
     """Preprocess -> bin/sort -> rasterise, all on the current stream."""
-    pre = preprocess(means3d, scales, quats, sh, cam)
+    pre = preprocess(means3d, scales, quats, opacities, sh, cam)
     bs = bin_sort(pre["means2d"], pre["radii"], pre["depths"], cam.width, cam.height, capacity)
     r = Rasterizer(cam.width, cam.height, device=means3d.device)
-    r(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opacities, pre["rgb"], precision,
-      background)
+    r(bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], pre["log_opacities"], pre["rgb"],
+      precision, background)
     return r, bs, pre
 
 
@@ -554,7 +573,8 @@ class MultiViewRenderer:
         dev = self.scene["means3d"].device
         self.device = dev
         self.pre = preprocess_multiview(self.scene["means3d"], self.scene["scales"],
-                                        self.scene["quats"], self.scene["sh"], self.cams, sh_degree)
+                                        self.scene["quats"], self.scene["opacities"],
+                                        self.scene["sh"], self.cams, sh_degree)
         self.slack = slack
         self.joint = bool(joint_bin)
         self.K = max(1, min(int(bin_streams), self.V))
@@ -597,7 +617,7 @@ class MultiViewRenderer:
             g.tile_ranges, g.sorted_ids = rg.data_ptr(), ids.data_ptr()
             g.means2d = self.pre["means2d"][v].data_ptr()
             g.conics = self.pre["conics"][v].data_ptr()
-            g.opacities = self.scene["opacities"].data_ptr()
+            g.log_opacities = self.pre["log_opacities"].data_ptr()
             g.rgb = self.pre["rgb"][v].data_ptr()
             g.background[:] = [float(b) for b in background]
             g.out_rgb, g.out_T = r.rgb.data_ptr(), r.T.data_ptr()
@@ -615,15 +635,16 @@ class MultiViewRenderer:
     # -- stages -----------------------------------------------------------
     def preprocess(self):
         preprocess_multiview(self.scene["means3d"], self.scene["scales"], self.scene["quats"],
-                             self.scene["sh"], self.cams, self.sh_degree, out=self.pre)
+                             self.scene["opacities"], self.scene["sh"], self.cams, self.sh_degree,
+                             out=self.pre)
 
     def _bin_inputs(self, v):
         return (self.pre["means2d"][v], self.pre["radii"][v], self.pre["depths"][v],
-                self.pre["conics"][v], self.scene["opacities"])
+                self.pre["conics"][v], self.pre["log_opacities"])
 
     def _bin_inputs_all(self):
         return (self.pre["means2d"], self.pre["radii"], self.pre["depths"], self.pre["conics"],
-                self.scene["opacities"])
+                self.pre["log_opacities"])
 
     def _per_view_sorters(self):
         """One BinSorter per view (views are sorted K at a time on K streams,
@@ -727,7 +748,7 @@ class MultiViewRenderer:
         for v, r in enumerate(self.images):
             rg, ids = self._lists(v)
             r(rg, ids, self.pre["means2d"][v], self.pre["conics"][v],
-              self.scene["opacities"], self.pre["rgb"][v], self.precision,
+              self.pre["log_opacities"], self.pre["rgb"][v], self.precision,
               tuple(self.views[v].background))
 
     def frame(self, tune: gs_batch_tune | None = None):
@@ -759,7 +780,7 @@ class MultiViewRenderer:
             with torch.cuda.stream(side):
                 side.wait_event(self._events[v])
                 r(bs.ranges, bs.sorted_ids, self.pre["means2d"][v], self.pre["conics"][v],
-                  self.scene["opacities"], self.pre["rgb"][v], self.precision,
+                  self.pre["log_opacities"], self.pre["rgb"][v], self.precision,
                   tuple(self.views[v].background))
                 _check("gs_clock_stamp",
                        L.gs_clock_stamp(c_void_p(self.clock.data_ptr() + 8 * (v + 1)), _stream()))

@@ -639,16 +639,16 @@ struct PGauss {
     float det, ymax, dyl, cs;  // cs = c s = half-width of E in x; ymax = half-height
 };
 
-__device__ __forceinline__ PGauss make_pgauss(float2 m, float a, float b, float c, float o,
+__device__ __forceinline__ PGauss make_pgauss(float2 m, float a, float b, float c, float lno,
                                               bool &any) {
 #pragma clang fp contract(off)
     PGauss g{};
     g.mx = m.x;
     g.my = m.y;
     any = false;
-    if (!(o > 0.0f)) return g;
-    // T enlarged by more than the error of logf (a few ulp of |ln o| <= 104)
-    const float T = 2.0f * (logf(o) + 5.5412635f) * (1.0f + 4e-6f) + 4e-5f;
+    // T enlarged by more than the error of ln o (a few ulp of |ln o| <= 104,
+    // from preprocess) and of this sum
+    const float T = 2.0f * (lno + 5.5412635f) * (1.0f + 4e-6f) + 4e-5f;
     if (!(T >= 0.0f)) return g;  // o < 1/255: reaches the threshold nowhere
     any = true;
     const float det = (float)((double)a * (double)c - (double)b * (double)b);  // one rounding
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     const int *__restrict__ radii,
                                                     const float *__restrict__ depths,
                                                     const float *__restrict__ conics,
-                                                    const float *__restrict__ opac, ViewRef vt,
+                                                    const float *__restrict__ lno, ViewRef vt,
                                                     uint32_t *__restrict__ keys,
                                                     uint32_t *__restrict__ ids,
                                                     void *__restrict__ rects,
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
         if (n > 0) {
             bool any;
             q = make_pgauss(m, conics[3 * i], conics[3 * i + 1], conics[3 * i + 2],
-                            opac[i - view * (int)vt.P], any);
+                            lno[i - view * (int)vt.P], any);
             if (any) h = (uint32_t)(ty1 - ty0 + 1);
         }
         if (live) pg[i] = q;
@@ -1412,7 +1412,7 @@ int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool e
 
 gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t *heights,
                          const float *means2d, const int32_t *radii, const float *depths,
-                         const float *conics, const float *opacities, bool precise,
+                         const float *conics, const float *log_opacities, bool precise,
                          uint32_t capacity, void *workspace, size_t workspace_bytes,
                          uint32_t *sorted_ids, uint32_t *tile_ranges, uint32_t *d_num_splats,
                          uint32_t *d_view_splats, void *stream) {
@@ -1429,8 +1429,8 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     if (P > 0 && (!means2d || !radii || !depths || !gs::aligned(means2d, 8) ||
                   !gs::aligned(radii, 4) || !gs::aligned(depths, 4)))
         return GS_ERR_INVALID_ARG;
-    if (precise && P > 0 && (!conics || !opacities || !gs::aligned(conics, 4) ||
-                             !gs::aligned(opacities, 4)))
+    if (precise && P > 0 && (!conics || !log_opacities || !gs::aligned(conics, 4) ||
+                             !gs::aligned(log_opacities, 4)))
         return GS_ERR_INVALID_ARG;
     if (capacity >= 0x80000000u) return GS_ERR_INVALID_ARG;
     if (capacity > 0 && (!sorted_ids || !gs::aligned(sorted_ids, 4))) return GS_ERR_INVALID_ARG;
@@ -1468,7 +1468,7 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
         auto kk = precise ? (nv > 1 ? k_depth_keys<true, true> : k_depth_keys<true, false>)
                           : (nv > 1 ? k_depth_keys<false, true> : k_depth_keys<false, false>);
         hipLaunchKernelGGL(kk, dim3((nthr + 255) / 256), dim3(256), 0, s, n, m2, radii, depths,
-                           conics, opacities, vt, U(L.dkey0), U(L.did0), (void *)(ws + L.rects),
+                           conics, log_opacities, vt, U(L.dkey0), U(L.did0), (void *)(ws + L.rects),
                            pg, tile_ranges, 2 * ntiles);
     }
     SortBufs db{{U(L.dkey0), U(L.dkey1)}, {U(L.did0), U(L.did1)}};
@@ -1569,12 +1569,12 @@ extern "C" gs_status gs_bin_sort(int32_t P, const float *means2d, const int32_t 
 
 extern "C" gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const int32_t *radii,
                                          const float *depths, const float *conics,
-                                         const float *opacities, int32_t width, int32_t height,
+                                         const float *log_opacities, int32_t width, int32_t height,
                                          uint32_t capacity, void *workspace,
                                          size_t workspace_bytes, uint32_t *sorted_ids,
                                          uint32_t *tile_ranges, uint32_t *d_num_splats,
                                          void *stream) {
-    return bin_sort_views(1, P, &width, &height, means2d, radii, depths, conics, opacities, true,
+    return bin_sort_views(1, P, &width, &height, means2d, radii, depths, conics, log_opacities, true,
                           capacity, workspace, workspace_bytes, sorted_ids, tile_ranges,
                           d_num_splats, nullptr, stream);
 }
@@ -1582,12 +1582,12 @@ extern "C" gs_status gs_bin_sort_precise(int32_t P, const float *means2d, const 
 extern "C" gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths,
                                            const int32_t *heights, const float *means2d,
                                            const int32_t *radii, const float *depths,
-                                           const float *conics, const float *opacities,
+                                           const float *conics, const float *log_opacities,
                                            int32_t precise, uint32_t capacity, void *workspace,
                                            size_t workspace_bytes, uint32_t *sorted_ids,
                                            uint32_t *tile_ranges, uint32_t *d_num_splats,
                                            uint32_t *d_view_splats, void *stream) {
-    return bin_sort_views(nviews, P, widths, heights, means2d, radii, depths, conics, opacities,
+    return bin_sort_views(nviews, P, widths, heights, means2d, radii, depths, conics, log_opacities,
                           precise != 0, capacity, workspace, workspace_bytes, sorted_ids,
                           tile_ranges, d_num_splats, d_view_splats, stream);
 }

@@ -1,7 +1,7 @@
 // Preprocess: projection of 3D Gaussians to screen space (TC-GS paper,
 // Sec. 3.1 "Preprocess": mu' = W mu, Sigma' = J W Sigma W^T J^T), conic
 // inversion, radius and tile count.  One thread per Gaussian; the stage is
-// bound by HBM bandwidth (236 input bytes per Gaussian, 192 of them SH).
+// bound by HBM bandwidth (240 input bytes per Gaussian, 192 of them SH).
 #include "common.h"
 
 // No floating-point contraction in this file: every product and sum below is
@@ -222,6 +222,10 @@ __device__ __forceinline__ void store_footprint(size_t i, const Footprint &f,
     tiles_touched[i] = f.nt;
 }
 
+// ln o, the form in which opacity enters the exponent (Sec. 4.1); -inf for
+// o = 0.  Computed once per Gaussian here rather than per splat and tile.
+__device__ __forceinline__ float log_opacity(float o) { return logf(o); }
+
 __device__ __forceinline__ void store_rgb(size_t i, const float col[3], float *__restrict__ rgb) {
     rgb[3 * i] = col[0];
     rgb[3 * i + 1] = col[1];
@@ -231,9 +235,11 @@ __device__ __forceinline__ void store_rgb(size_t i, const float col[3], float *_
 __global__ __launch_bounds__(256) void k_preprocess_3d(int P, const float *__restrict__ means,
                                                        const float *__restrict__ scales,
                                                        const float4 *__restrict__ quats,
+                                                       const float *__restrict__ opac,
                                                        const float4 *__restrict__ sh, int sh_deg,
                                                        CamParams cam, float2 *__restrict__ means2d,
                                                        float *__restrict__ conics,
+                                                       float *__restrict__ lno,
                                                        float *__restrict__ depths,
                                                        int *__restrict__ radii,
                                                        float *__restrict__ rgb,
@@ -254,6 +260,7 @@ __global__ __launch_bounds__(256) void k_preprocess_3d(int P, const float *__res
     }
     store_footprint(i, f, means2d, conics, depths, radii, tiles_touched);
     store_rgb(i, col, rgb);
+    lno[i] = log_opacity(opac[i]);
 }
 
 // Up to MV_CHUNK cameras per launch, passed by value.
@@ -267,10 +274,12 @@ struct CamChunk {
 __global__ __launch_bounds__(256) void k_preprocess_mv(int P, const float *__restrict__ means,
                                                        const float *__restrict__ scales,
                                                        const float4 *__restrict__ quats,
+                                                       const float *__restrict__ opac,
                                                        const float4 *__restrict__ sh, int sh_deg,
                                                        CamChunk cams, int v0, int nv,
                                                        float2 *__restrict__ means2d,
                                                        float *__restrict__ conics,
+                                                       float *__restrict__ lno,
                                                        float *__restrict__ depths,
                                                        int *__restrict__ radii,
                                                        float *__restrict__ rgb,
@@ -278,6 +287,7 @@ __global__ __launch_bounds__(256) void k_preprocess_mv(int P, const float *__res
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const Gauss3 g = load_gauss(i, means, scales, quats);
+    if (v0 == 0) lno[i] = log_opacity(opac[i]);
     uint32_t drawn = 0;
     const float zero[3] = {0.f, 0.f, 0.f};
     for (int c = 0; c < nv; ++c) {
@@ -301,8 +311,10 @@ __global__ __launch_bounds__(256) void k_preprocess_mv(int P, const float *__res
 }
 
 __global__ __launch_bounds__(256) void k_preprocess_2d(int P, const float2 *__restrict__ means2d,
-                                                       const float *__restrict__ cov2d, int W, int H,
+                                                       const float *__restrict__ cov2d,
+                                                       const float *__restrict__ opac, int W, int H,
                                                        int gx, float *__restrict__ conics,
+                                                       float *__restrict__ lno,
                                                        int *__restrict__ radii,
                                                        uint32_t *__restrict__ tiles_touched) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -324,6 +336,7 @@ __global__ __launch_bounds__(256) void k_preprocess_2d(int P, const float2 *__re
     conics[3 * i + 2] = con.z;
     radii[i] = r;
     tiles_touched[i] = nt;
+    lno[i] = log_opacity(opac[i]);
 }
 
 CamParams cam_params(const gs_camera &cam) {
@@ -356,13 +369,15 @@ bool camera_ok(const gs_camera &cam) {
 }  // namespace
 
 extern "C" gs_status gs_preprocess(int32_t P, const float *means3d, const float *scales,
-                                   const float *quats, const float *sh, int32_t sh_degree,
-                                   const gs_camera *cam, float *means2d, float *conics,
-                                   float *depths, int32_t *radii, float *rgb,
-                                   uint32_t *tiles_touched, void *stream) {
+                                   const float *quats, const float *opacities, const float *sh,
+                                   int32_t sh_degree, const gs_camera *cam, float *means2d,
+                                   float *conics, float *log_opacities, float *depths,
+                                   int32_t *radii, float *rgb, uint32_t *tiles_touched,
+                                   void *stream) {
     if (P < 0 || !cam || sh_degree < 0 || sh_degree > 3 || !camera_ok(*cam)) return GS_ERR_INVALID_ARG;
     if (P == 0) return GS_OK;
-    const void *ptrs[] = {means3d, scales, quats, sh, means2d, conics, depths, radii, rgb, tiles_touched};
+    const void *ptrs[] = {means3d, scales, quats, opacities, sh, means2d, conics, log_opacities,
+                          depths, radii, rgb, tiles_touched};
     for (const void *p : ptrs)
         if (!p || !gs::aligned(p, 4)) return GS_ERR_INVALID_ARG;
     if (!gs::aligned(quats, 16) || !gs::aligned(sh, 16) || !gs::aligned(means2d, 8))
@@ -371,23 +386,24 @@ extern "C" gs_status gs_preprocess(int32_t P, const float *means3d, const float 
     hipStream_t s = (hipStream_t)stream;
     int blocks = (P + 255) / 256;
     hipLaunchKernelGGL(k_preprocess_3d, dim3(blocks), dim3(256), 0, s, P, means3d, scales,
-                       (const float4 *)quats, (const float4 *)sh, sh_degree, cp, (float2 *)means2d,
-                       conics, depths, radii, rgb, tiles_touched);
+                       (const float4 *)quats, opacities, (const float4 *)sh, sh_degree, cp,
+                       (float2 *)means2d, conics, log_opacities, depths, radii, rgb, tiles_touched);
     return gs::launch_status();
 }
 
 extern "C" gs_status gs_preprocess_multiview(int32_t P, const float *means3d, const float *scales,
-                                             const float *quats, const float *sh,
-                                             int32_t sh_degree, int32_t nviews,
+                                             const float *quats, const float *opacities,
+                                             const float *sh, int32_t sh_degree, int32_t nviews,
                                              const gs_camera *cams, float *means2d, float *conics,
-                                             float *depths, int32_t *radii, float *rgb,
-                                             uint32_t *tiles_touched, void *stream) {
+                                             float *log_opacities, float *depths, int32_t *radii,
+                                             float *rgb, uint32_t *tiles_touched, void *stream) {
     if (P < 0 || !cams || sh_degree < 0 || sh_degree > 3 || nviews < 1 || nviews > 64)
         return GS_ERR_INVALID_ARG;
     for (int v = 0; v < nviews; ++v)
         if (!camera_ok(cams[v])) return GS_ERR_INVALID_ARG;
     if (P == 0) return GS_OK;
-    const void *ptrs[] = {means3d, scales, quats, sh, means2d, conics, depths, radii, rgb, tiles_touched};
+    const void *ptrs[] = {means3d, scales, quats, opacities, sh, means2d, conics, log_opacities,
+                          depths, radii, rgb, tiles_touched};
     for (const void *p : ptrs)
         if (!p || !gs::aligned(p, 4)) return GS_ERR_INVALID_ARG;
     if (!gs::aligned(quats, 16) || !gs::aligned(sh, 16) || !gs::aligned(means2d, 8))
@@ -399,25 +415,28 @@ extern "C" gs_status gs_preprocess_multiview(int32_t P, const float *means3d, co
         CamChunk ch{};
         for (int c = 0; c < nv; ++c) ch.c[c] = cam_params(cams[v0 + c]);
         hipLaunchKernelGGL(k_preprocess_mv, dim3(blocks), dim3(256), 0, s, P, means3d, scales,
-                           (const float4 *)quats, (const float4 *)sh, sh_degree, ch, v0, nv,
-                           (float2 *)means2d, conics, depths, radii, rgb, tiles_touched);
+                           (const float4 *)quats, opacities, (const float4 *)sh, sh_degree, ch, v0,
+                           nv, (float2 *)means2d, conics, log_opacities, depths, radii, rgb,
+                           tiles_touched);
     }
     return gs::launch_status();
 }
 
 extern "C" gs_status gs_preprocess_2d(int32_t P, const float *means2d, const float *cov2d,
-                                      int32_t width, int32_t height, float *conics,
-                                      int32_t *radii, uint32_t *tiles_touched, void *stream) {
+                                      const float *opacities, int32_t width, int32_t height,
+                                      float *conics, float *log_opacities, int32_t *radii,
+                                      uint32_t *tiles_touched, void *stream) {
     if (P < 0 || width <= 0 || height <= 0 || width > GS_MAX_DIM || height > GS_MAX_DIM)
         return GS_ERR_INVALID_ARG;
     if (P == 0) return GS_OK;
-    const void *ptrs[] = {means2d, cov2d, conics, radii, tiles_touched};
+    const void *ptrs[] = {means2d, cov2d, opacities, conics, log_opacities, radii, tiles_touched};
     for (const void *p : ptrs)
         if (!p || !gs::aligned(p, 4)) return GS_ERR_INVALID_ARG;
     if (!gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     int blocks = (P + 255) / 256;
     hipLaunchKernelGGL(k_preprocess_2d, dim3(blocks), dim3(256), 0, s, P, (const float2 *)means2d,
-                       cov2d, width, height, gs::grid_x(width), conics, radii, tiles_touched);
+                       cov2d, opacities, width, height, gs::grid_x(width), conics, log_opacities,
+                       radii, tiles_touched);
     return gs::launch_status();
 }

@@ -20,7 +20,7 @@ namespace {
 template <bool EARLY, bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
     __shared__ float2 s_mu[BATCH];
-    __shared__ float4 s_co[BATCH];  // s11, s12, s22, o (or ln o with EARLY)
+    __shared__ float4 s_co[BATCH];  // s11, s12, s22, o (ln o with EARLY)
     __shared__ float4 s_rgb[BATCH];
     int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
     if (tile < 0) return;
@@ -37,10 +37,10 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
         if (k < end) {
             uint32_t id = a.ids[k];
             s_mu[threadIdx.x] = a.means2d[id];
-            float o = a.opac[id];
+            const float lno = a.lno[id];
             const Float3 c3 = *(const Float3 *)(a.conics + 3 * (size_t)id);
             const Float3 k3 = *(const Float3 *)(a.rgb + 3 * (size_t)id);
-            s_co[threadIdx.x] = make_float4(c3.x, c3.y, c3.z, EARLY ? __logf(o) : o);
+            s_co[threadIdx.x] = make_float4(c3.x, c3.y, c3.z, EARLY ? lno : __expf(lno));
             s_rgb[threadIdx.x] = make_float4(k3.x, k3.y, k3.z, 0.f);
         }
         __syncthreads();
@@ -190,11 +190,11 @@ void launch_mfma(const RasterArgs &a, int blocks, bool count, hipStream_t s) {
 
 extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
                                       const uint32_t *sorted_ids, const float *means2d,
-                                      const float *conics, const float *opacities,
+                                      const float *conics, const float *log_opacities,
                                       const float *rgb, const float *background, int32_t precision,
                                       float *out_rgb, float *out_T, uint32_t *out_ncontrib,
                                       uint64_t *d_counters, void *stream) {
-    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, opacities, rgb, out_rgb, out_T, out_ncontrib};
+    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, log_opacities, rgb, out_rgb, out_T, out_ncontrib};
     if (!valid_inputs(width, height, ptrs, 9) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     if (d_counters && !gs::aligned(d_counters, 8)) return GS_ERR_INVALID_ARG;
     if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
@@ -207,7 +207,7 @@ extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint3
     a.ids = sorted_ids;
     a.means2d = (const float2 *)means2d;
     a.conics = conics;
-    a.opac = opacities;
+    a.lno = log_opacities;
     a.rgb = rgb;
     a.bg0 = background ? background[0] : 0.f;
     a.bg1 = background ? background[1] : 0.f;
@@ -239,9 +239,9 @@ extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint3
 extern "C" gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t tile,
                                        const uint32_t *tile_ranges, const uint32_t *sorted_ids,
                                        const float *means2d, const float *conics,
-                                       const float *opacities, int32_t precision, int32_t count,
+                                       const float *log_opacities, int32_t precision, int32_t count,
                                        float *out_beta, void *stream) {
-    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, opacities, out_beta};
+    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, log_opacities, out_beta};
     if (!valid_inputs(width, height, ptrs, 6) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     int ntiles = gs::grid_x(width) * gs::grid_y(height);
     if (tile < 0 || tile >= ntiles || count <= 0) return GS_ERR_INVALID_ARG;
@@ -255,8 +255,8 @@ extern "C" gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t ti
     a.ids = sorted_ids;
     a.means2d = (const float2 *)means2d;
     a.conics = conics;
-    a.opac = opacities;
-    a.rgb = opacities;  // colours are not needed; any valid pointer
+    a.lno = log_opacities;
+    a.rgb = log_opacities;  // colours are not needed; any valid pointer
     hipStream_t s = (hipStream_t)stream;
     switch (precision) {
     case GS_PREC_FP16_GLOBAL: hipLaunchKernelGGL(k_beta_dump<VAR_F16_GLOBAL>, dim3(1), dim3(256), 0, s, a, tile, count, out_beta); break;
@@ -279,4 +279,4 @@ extern "C" const char *gs_status_string(int status) {
     }
 }
 
-extern "C" int gs_version(void) { return 100; }
+extern "C" int gs_version(void) { return 200; }

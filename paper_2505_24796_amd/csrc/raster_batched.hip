@@ -176,7 +176,7 @@ extern "C" gs_status gs_batch_plan_write(int32_t nviews, const gs_view *views, v
     uint64_t qtot[NQ + 1] = {};
     for (int v = 0; v < nviews; ++v) {
         const gs_view &g = views[v];
-        const void *ptrs[] = {g.tile_ranges, g.sorted_ids, g.means2d, g.conics, g.opacities,
+        const void *ptrs[] = {g.tile_ranges, g.sorted_ids, g.means2d, g.conics, g.log_opacities,
                               g.rgb, g.out_rgb, g.out_T, g.out_ncontrib};
         if (!valid_inputs(g.width, g.height, ptrs, 9) || !gs::aligned(g.means2d, 8))
             return GS_ERR_INVALID_ARG;
@@ -189,7 +189,7 @@ extern "C" gs_status gs_batch_plan_write(int32_t nviews, const gs_view *views, v
         a.ids = g.sorted_ids;
         a.means2d = (const float2 *)g.means2d;
         a.conics = g.conics;
-        a.opac = g.opacities;
+        a.lno = g.log_opacities;
         a.rgb = g.rgb;
         a.bg0 = g.background[0];
         a.bg1 = g.background[1];

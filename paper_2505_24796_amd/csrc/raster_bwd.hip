@@ -110,7 +110,7 @@ __device__ __forceinline__ float wave_sum8_transposed(const float v[8]) {
 // dL/dbeta = a dL/da, or 0 where the 0.99 clamp is active.
 __device__ __forceinline__ void fragment_grad(PixState &ps, bool bl, float alpha, bool clamped,
                                               float4 col, float mx, float my, float s11, float s12,
-                                              float s22, float o, float fx, float fy,
+                                              float s22, float inv_o, float fx, float fy,
                                               float *s_grad) {
     float g[NGRAD];
     // T before this fragment (1 - alpha >= 0.01: a reciprocal-based divide
@@ -127,7 +127,7 @@ __device__ __forceinline__ void fragment_grad(PixState &ps, bool bl, float alpha
     g[2] = -0.5f * dbeta * dx * dx;
     g[3] = -dbeta * dx * dy;
     g[4] = -0.5f * dbeta * dy * dy;
-    g[5] = dbeta / o;
+    g[5] = dbeta * inv_o;  // dbeta/do = 1/o
     g[6] = ps.d0 * wT;
     g[7] = ps.d1 * wT;
     g[8] = ps.d2 * wT;
@@ -207,11 +207,12 @@ __global__ __launch_bounds__(256) void k_raster_bwd_fp32(BwdArgs a) {
         if (threadIdx.x < cnt) {
             uint32_t id = a.f.ids[start + j0 + threadIdx.x];
             s_mu[threadIdx.x] = a.f.means2d[id];
-            float o = a.f.opac[id];
+            const float lno = a.f.lno[id];
             const Float3 c3 = *(const Float3 *)(a.f.conics + 3 * (size_t)id);
             const Float3 k3 = *(const Float3 *)(a.f.rgb + 3 * (size_t)id);
-            s_co[threadIdx.x] = make_float4(c3.x, c3.y, c3.z, EARLY ? __logf(o) : o);
-            s_rgb[threadIdx.x] = make_float4(k3.x, k3.y, k3.z, o);
+            // the forward's staging exactly: ln o, or o = exp(ln o)
+            s_co[threadIdx.x] = make_float4(c3.x, c3.y, c3.z, EARLY ? lno : __expf(lno));
+            s_rgb[threadIdx.x] = make_float4(k3.x, k3.y, k3.z, __expf(-lno));
             s_id[threadIdx.x] = id;
         }
 #pragma unroll
@@ -256,7 +257,7 @@ template <int VAR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_bwd_mfma(BwdArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR>::BYTES];
     __shared__ float4 s_p0[BATCH];   // mu'x, mu'y, s11, s12
-    __shared__ float4 s_p1[BATCH];   // s22, o, id, -
+    __shared__ float4 s_p1[BATCH];   // s22, 1/o, id, -
     __shared__ float s_grad[BATCH][NGRAD];
     __shared__ int s_wcnt[4];
     __shared__ uint32_t s_max;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             const int jj = wofs + (int)gs::lanes_below(kmask);
             stage_splat<VAR>(stage, jj, cur, ox, oy, (uint32_t)b * BATCH + threadIdx.x);
             s_p0[jj] = make_float4(cur.mu.x, cur.mu.y, cur.s11, cur.s12);
-            s_p1[jj] = make_float4(cur.s22, cur.o, __uint_as_float(my_id), 0.0f);
+            s_p1[jj] = make_float4(cur.s22, __expf(-cur.lno), __uint_as_float(my_id), 0.0f);
         }
         __syncthreads();
         const int nsub = (total + SUB - 1) / SUB;
@@ -358,13 +359,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
 
 extern "C" gs_status gs_rasterize_bwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
                                       const uint32_t *sorted_ids, const float *means2d,
-                                      const float *conics, const float *opacities,
+                                      const float *conics, const float *log_opacities,
                                       const float *rgb, const float *background, int32_t precision,
                                       const float *out_T, const uint32_t *out_ncontrib,
                                       const float *dL_dimg, float *dL_dmeans2d,
                                       float *dL_dconics, float *dL_dopacities, float *dL_drgb,
                                       void *stream) {
-    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, opacities, rgb, out_T,
+    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, log_opacities, rgb, out_T,
                           out_ncontrib, dL_dimg, dL_dmeans2d, dL_dconics, dL_dopacities, dL_drgb};
     if (!valid_inputs(width, height, ptrs, 13) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
@@ -377,7 +378,7 @@ extern "C" gs_status gs_rasterize_bwd(int32_t width, int32_t height, const uint3
     a.f.ids = sorted_ids;
     a.f.means2d = (const float2 *)means2d;
     a.f.conics = conics;
-    a.f.opac = opacities;
+    a.f.lno = log_opacities;
     a.f.rgb = rgb;
     a.f.bg0 = background ? background[0] : 0.f;
     a.f.bg1 = background ? background[1] : 0.f;

@@ -30,7 +30,7 @@ struct RasterArgs {
     const uint32_t *ids;
     const float2 *means2d;
     const float *conics;
-    const float *opac;
+    const float *lno;  // ln o per Gaussian
     const float *rgb;
     float bg0, bg1, bg2;
     float *out_rgb;
@@ -109,7 +109,7 @@ __device__ __forceinline__ float dot2_acc(float a, float b, float c, float d) {
 
 // Write the operand-A row of one splat.  Coefficients (Sec. 4.2) in the frame
 // with origin (ox, oy), scaled by log2(e):
-//   v0 = log2 o - 1/2 log2e dmu^T S dmu, v1 = log2e (s11 dx + s12 dy),
+//   v0 = log2e (ln o - 1/2 dmu^T S dmu), v1 = log2e (s11 dx + s12 dy),
 //   v2 = log2e (s12 dx + s22 dy), v3 = -1/2 log2e s11, v4 = -log2e s12,
 //   v5 = -1/2 log2e s22,  dmu = mu' - origin.
 // They are computed once per splat and tile, so they are evaluated with
@@ -121,7 +121,7 @@ __device__ __forceinline__ float dot2_acc(float a, float b, float c, float d) {
 // result.
 template <int VAR>
 __device__ __forceinline__ void build_row(bool valid, float2 mu, float s11, float s12, float s22,
-                                          float o, float ox, float oy, uint8_t *row1, uint8_t *row2) {
+                                          float lno, float ox, float oy, uint8_t *row1, uint8_t *row2) {
     float v[6];
     if (valid) {
         const float dx = mu.x - ox, dy = mu.y - oy;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void build_row(bool valid, float2 mu, float s11, floa
         const float r11 = 1.0f / s11;
         const float t = fmaf(s12 * r11, dy, dx);
         const float q = fmaf(s11 * t, t, (det * r11) * dy * dy);
-        v[0] = fmaf(-0.5f * LOG2E, q, __log2f(o));
+        v[0] = LOG2E * fmaf(-0.5f, q, lno);
         v[1] = LOG2E * dot2_acc(s11, dx, s12, dy);
         v[2] = LOG2E * dot2_acc(s12, dx, s22, dy);
         v[3] = -0.5f * LOG2E * s11;
@@ -258,7 +258,7 @@ template <int VAR, int NB = BATCH> struct Stage {
 
 struct SplatRegs {
     float2 mu;
-    float s11, s12, s22, o, r, g, b;
+    float s11, s12, s22, lno, r, g, b;
     bool valid;
 };
 
@@ -268,7 +268,7 @@ struct __attribute__((aligned(4))) Float3 {
     float x, y, z;
 };
 
-// One splat's parameters: four loads (mean, conic, opacity, colour) rather
+// One splat's parameters: four loads (mean, conic, ln o, colour) rather
 // than one per float, so a wave's gather touches each array's lines once.
 __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bool valid) {
     SplatRegs s;
@@ -279,7 +279,7 @@ __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bo
         s.s11 = c.x;
         s.s12 = c.y;
         s.s22 = c.z;
-        s.o = a.opac[id];
+        s.lno = a.lno[id];
         const Float3 k = *(const Float3 *)(a.rgb + 3 * (size_t)id);
         s.r = k.x;
         s.g = k.y;
@@ -287,7 +287,7 @@ __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bo
     } else {
         s.mu = make_float2(0.f, 0.f);
         s.s11 = s.s12 = s.s22 = 0.f;
-        s.o = 1.f;
+        s.lno = 0.f;
         s.r = s.g = s.b = 0.f;
     }
     return s;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void stage_splat(uint8_t *stage, int j, const SplatRe
     int sub = j / SUB, row = row_of_splat(j % SUB);
     uint8_t *row1 = stage + sub * SUB * VarTraits<VAR>::ROW1 + row * VarTraits<VAR>::ROW1;
     uint8_t *row2 = stage + Stage<VAR, NB>::A1 + sub * SUB * VarTraits<VAR>::ROW2 + row * VarTraits<VAR>::ROW2;
-    build_row<VAR>(s.valid, s.mu, s.s11, s.s12, s.s22, s.o, ox, oy, row1, row2);
+    build_row<VAR>(s.valid, s.mu, s.s11, s.s12, s.s22, s.lno, ox, oy, row1, row2);
     float4 *rgb = (float4 *)(stage + Stage<VAR, NB>::A1 + Stage<VAR, NB>::A2);
     // w: 1-based position of the splat in the tile list (for n_contrib)
     rgb[j] = make_float4(s.r, s.g, s.b, __uint_as_float(list_pos + 1u));
@@ -344,7 +344,7 @@ __device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y
         }
     }
     float margin = 1e-3f * (1.0f + fmin) + 1e-5f * fabs_terms;
-    return __logf(s.o) - fmin >= CULL_LN - margin;
+    return s.lno - fmin >= CULL_LN - margin;
 }
 
 inline bool valid_inputs(int32_t width, int32_t height, const void *const *p, int n) {

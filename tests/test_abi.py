@@ -54,7 +54,7 @@ def test_status_strings(gslib):
     assert gslib.gs_status_string(0) == b"GS_OK"
     assert gslib.gs_status_string(4) == b"GS_ERR_CAPACITY"
     assert gslib.gs_status_string(99) == b"GS_ERR_UNKNOWN"
-    assert gslib.gs_version() >= 100
+    assert gslib.gs_version() == 200  # opacity crosses the boundary as ln o
 
 
 def test_invalid_arguments_rejected_on_host(gslib):
@@ -62,19 +62,27 @@ def test_invalid_arguments_rejected_on_host(gslib):
     v = ctypes.c_void_p
     cam = gs.make_camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1], 100, 100, 50, 50, 100, 100)
     # negative P
-    assert gslib.gs_preprocess(-1, v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(16), v(16),
-                               v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess(-1, v(16), v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(16),
+                               v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
     # bad SH degree
-    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), 4, ctypes.byref(cam), v(16), v(16),
-                               v(16), v(16), v(16), v(16), v(0)) == 1
-    # null output
-    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(0), v(16),
-                               v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), v(16), 4, ctypes.byref(cam), v(16),
+                               v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
+    # null output (means2d, then ln o)
+    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(0),
+                               v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(16), v(16), 3, ctypes.byref(cam), v(16),
+                               v(16), v(0), v(16), v(16), v(16), v(16), v(0)) == 1
+    # null opacities
+    assert gslib.gs_preprocess(1, v(16), v(16), v(16), v(0), v(16), 3, ctypes.byref(cam), v(16),
+                               v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
     # misaligned quaternions (16 B required)
-    assert gslib.gs_preprocess(1, v(16), v(16), v(20), v(16), 3, ctypes.byref(cam), v(16), v(16),
-                               v(16), v(16), v(16), v(16), v(0)) == 1
-    # oversized image
-    assert gslib.gs_preprocess_2d(1, v(16), v(16), 20000, 10, v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess(1, v(16), v(16), v(20), v(16), v(16), 3, ctypes.byref(cam), v(16),
+                               v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
+    # oversized image; null opacities
+    assert gslib.gs_preprocess_2d(1, v(16), v(16), v(16), 20000, 10, v(16), v(16), v(16), v(16),
+                                  v(0)) == 1
+    assert gslib.gs_preprocess_2d(1, v(16), v(16), v(0), 64, 64, v(16), v(16), v(16), v(16),
+                                  v(0)) == 1
     assert gslib.gs_bin_sort_workspace_bytes(10, 100, 0, 10) == 0
     assert gslib.gs_bin_sort_workspace_bytes(10, 100, 64, 64) > 0
     # workspace too small -> capacity error
@@ -101,13 +109,13 @@ def test_batched_and_precise_arguments_rejected_on_host(gslib):
     cam = gs.make_camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1], 100, 100, 50, 50, 100, 100)
     cams = (gs.gs_camera * 2)(cam, cam)
     # multi-camera preprocess: no cameras, too many, a bad camera
-    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), 3, 0, cams, v(16), v(16),
-                                         v(16), v(16), v(16), v(16), v(0)) == 1
-    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), 3, 65, cams, v(16), v(16),
-                                         v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), v(16), 3, 0, cams, v(16),
+                                         v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), v(16), 3, 65, cams, v(16),
+                                         v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
     bad = (gs.gs_camera * 2)(cam, gs.make_camera([1] * 16, 100, 100, 50, 50, 0, 100))
-    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), 3, 2, bad, v(16), v(16),
-                                         v(16), v(16), v(16), v(16), v(0)) == 1
+    assert gslib.gs_preprocess_multiview(1, v(16), v(16), v(16), v(16), v(16), 3, 2, bad, v(16),
+                                         v(16), v(16), v(16), v(16), v(16), v(16), v(0)) == 1
     # batched raster: plan and workspace sizes, view count, alignment, precision, shape
     assert gslib.gs_batch_plan_bytes(0) == 0 and gslib.gs_batch_plan_bytes(65) == 0
     assert gslib.gs_batch_plan_bytes(16) > 0 and gslib.gs_batch_workspace_bytes(16) >= 4 * (16 + 16)
@@ -159,7 +167,7 @@ def test_multiview_bin_sort_arguments_rejected_on_host(gslib):
              v(16), v(16), v(0)) == 1
     assert f(3, 10, W, H, *ok, 0, 100, v(260), 1 << 20, v(16), v(16), v(16), v(16), v(0)) == 1
     assert f(3, 10, W, H, *ok, 0, 100, v(256), 1 << 20, v(16), v(16), v(16), v(18), v(0)) == 1
-    # precise needs conics and opacities
+    # precise needs conics and ln o
     assert f(3, 10, W, H, v(16), v(16), v(16), v(0), v(16), 1, 100, v(256), 1 << 20, v(16), v(16),
              v(16), v(16), v(0)) == 1
     # workspace too small
@@ -168,7 +176,7 @@ def test_multiview_bin_sort_arguments_rejected_on_host(gslib):
 
 def test_zero_gaussians_is_noop(gslib):
     v = ctypes.c_void_p
-    assert gslib.gs_preprocess_2d(0, v(0), v(0), 64, 64, v(0), v(0), v(0), v(0)) == 0
+    assert gslib.gs_preprocess_2d(0, v(0), v(0), v(0), 64, 64, v(0), v(0), v(0), v(0), v(0)) == 0
 
 
 def test_oracle_independent_of_product():

@@ -42,14 +42,15 @@ def test_backward_vs_oracle(prec, W, H, P, seed):
     say(f"backward {prec} {W}x{H} P={P}")
     sc = scenegen.scene_2d(P, W, H, seed, s_min=1.0 if P == 200 else 0.5, s_max=6.0 if P == 200 else 8.0)
     m2, cv, op, col = dev(sc.means2d), dev(sc.cov2d), dev(sc.opacities), dev(sc.rgb)
-    pre = gs.preprocess_2d(m2, cv, W, H)
+    pre = gs.preprocess_2d(m2, cv, op, W, H)
+    lno = pre["log_opacities"]
     ranges, ids = oracle.bin_splats(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     rg = dev(ranges.astype(np.int32))
     idg = dev(ids.astype(np.int32))
     bg = (0.2, 0.1, 0.3)
-    r = gs.rasterize_fwd(W, H, rg, idg, m2, pre["conics"], op, col, prec, background=bg)
+    r = gs.rasterize_fwd(W, H, rg, idg, m2, pre["conics"], lno, col, prec, background=bg)
     w = np.random.default_rng(seed).normal(0, 1, (3, H, W)).astype(np.float32)
-    g = gs.rasterize_bwd(W, H, rg, idg, m2, pre["conics"], op, col, r.T, r.n_contrib, dev(w), prec,
+    g = gs.rasterize_bwd(W, H, rg, idg, m2, pre["conics"], lno, col, r.T, r.n_contrib, dev(w), prec,
                          background=bg)
     conics = host(pre["conics"]).astype(np.float64)
     ref = oracle.render_backward(W, H, ranges, ids, sc.means2d, conics, sc.opacities, sc.rgb, w, bg=bg)
@@ -64,18 +65,20 @@ def test_autograd_function_and_l1_loss():
     W, H = 128, 96
     sc = scenegen.scene_2d(800, W, H, 21)
     m2, cv = dev(sc.means2d), dev(sc.cov2d)
-    pre = gs.preprocess_2d(m2, cv, W, H)
+    pre = gs.preprocess_2d(m2, cv, dev(sc.opacities), W, H)
+    lno = pre["log_opacities"]
     bs = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H)
     target = torch.rand(3, H, W, device="cuda")
     params = [m2.clone().requires_grad_(), pre["conics"].clone().requires_grad_(),
               dev(sc.opacities).requires_grad_(), dev(sc.rgb).requires_grad_()]
-    img = gs.RasterizeFn.apply(*params, bs.ranges, bs.sorted_ids, W, H, "fp16_g2l_split")
+    img = gs.RasterizeFn.apply(*params, lno, bs.ranges, bs.sorted_ids, W, H, "fp16_g2l_split")
     loss = (img - target).abs().mean()
     loss.backward()
     dimg = (torch.sign(img.detach() - target) / img.numel()).contiguous()
-    r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, *[p.detach() for p in params], "fp16_g2l_split")
-    g = gs.rasterize_bwd(W, H, bs.ranges, bs.sorted_ids, *[p.detach() for p in params], r.T,
-                         r.n_contrib, dimg, "fp16_g2l_split")
+    m, c, _, k = [p.detach() for p in params]
+    r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, m, c, lno, k, "fp16_g2l_split")
+    g = gs.rasterize_bwd(W, H, bs.ranges, bs.sorted_ids, m, c, lno, k, r.T, r.n_contrib, dimg,
+                         "fp16_g2l_split")
     for p, k in zip(params, ("means2d", "conics", "opacities", "rgb")):
         a, b = host(p.grad), host(g[k])
         assert np.allclose(a, b, rtol=1e-4, atol=1e-7 * np.abs(b).max()), k
@@ -92,9 +95,9 @@ def test_backward_fullsize_sampled_tiles():
     cam_np = scenegen.make_camera(cfg)
     cam = gs.make_camera(cam_np.viewmat, cam_np.fx, cam_np.fy, cam_np.cx, cam_np.cy, W, H,
                          campos=cam_np.campos)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh), cam)
     bs = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
-    op = dev(sc.opacities)
+    op = pre["log_opacities"]
     prec = "fp16_g2l_split"
     r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], op, pre["rgb"], prec)
     ranges_g = host(bs.ranges).astype(np.int64)

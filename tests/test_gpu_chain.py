@@ -90,14 +90,15 @@ def test_whole_chain_3d_vs_fp64_chain(W, H, P, seed, pose):
     sc = scenegen.scene_3d(P, seed)
     cam = scenegen.orbit_camera(pose, 8, W, H)
     o, ref = oracle_chain(sc, cam)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), gs_cam(cam))
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh),
+                        gs_cam(cam))
     bs = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
     rad_g = host(pre["radii"])
     vis_g, vis_o = rad_g > 0, o["radii"] > 0
     say(f"  drawn: GPU {vis_g.sum()}, oracle {vis_o.sum()}, differing {np.sum(vis_g != vis_o)}; "
         f"splats GPU {bs.n_splats()}")
     assert np.mean(vis_g == vis_o) > 0.999
-    opac = dev(sc.opacities)
+    opac = pre["log_opacities"]
     for prec in PRECS:
         r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,
                              pre["rgb"], prec)
@@ -132,7 +133,7 @@ def test_near_degenerate_conic_takes_fp64_branch():
     branch = det32 < np.float32(2.0 ** -10) * a * c
     say(f"near-degenerate: {branch.sum()} of {len(a)} take the FP64 branch")
     assert branch[:1500].all() and not branch[1500:].any()
-    pre = gs.preprocess_2d(dev(m2), dev(cov), W, H)
+    pre = gs.preprocess_2d(dev(m2), dev(cov), dev(opac), W, H)
     o = oracle.preprocess_2d(m2, cov, W, H)
     rad = host(pre["radii"])
     same = rad == o["radii"]
@@ -155,8 +156,8 @@ def test_near_degenerate_conic_takes_fp64_branch():
     assert N == len(ids) and np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids)
     results = {}
     for prec in PRECS:
-        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"], dev(opac),
-                             dev(rgb), prec)
+        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"],
+                             pre["log_opacities"], dev(rgb), prec)
         img = host(r.rgb)
         if prec.startswith("fp32"):
             st = fp32_check(W, H, ranges, ids, m2, cg, opac, rgb, img, host(r.T))
@@ -198,9 +199,11 @@ def test_degenerate_inputs_2d():
     cov[7::40, 2] = -1.0          # indefinite
     cov[8::40] = [4.0, 2.0, 1.0]  # singular (det = 0)
     cov[9::40, :] = inf
-    pre = gs.preprocess_2d(dev(m2), dev(cov), W, H)
+    pre = gs.preprocess_2d(dev(m2), dev(cov), dev(opac), W, H)
     o = oracle.preprocess_2d(m2, cov, W, H)
     rad = host(pre["radii"])
+    lno = host(pre["log_opacities"])
+    assert np.all(lno[opac == 0] == -np.inf) and np.all(lno[opac == 1] == 0.0)
     bad = np.zeros(sc.P, bool)
     for k in range(2, 10):
         bad[k::40] = True
@@ -217,8 +220,8 @@ def test_degenerate_inputs_2d():
     cg = host(pre["conics"]).astype(np.float64)
     ref = oracle.render(W, H, ranges, ids, m2, cg, opac, sc.rgb)
     for prec in PRECS:
-        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"], dev(opac),
-                             dev(sc.rgb), prec, count=True)
+        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"],
+                             pre["log_opacities"], dev(sc.rgb), prec, count=True)
         img, T = host(r.rgb), host(r.T)
         assert np.isfinite(img).all() and T.min() >= 1e-4 and T.max() <= 1.0
         if prec.startswith("fp32"):
@@ -231,8 +234,8 @@ def test_degenerate_inputs_2d():
             if prec != "fp16_g2l":
                 assert q["frac_2_255"] >= 0.999
     # a scene of opacity-0 Gaussians only renders the background everywhere
-    z = np.zeros_like(opac)
-    r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"], dev(z), dev(sc.rgb),
+    z = gs.preprocess_2d(dev(m2), dev(cov), dev(np.zeros_like(opac)), W, H)["log_opacities"]
+    r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, dev(m2), pre["conics"], z, dev(sc.rgb),
                          "fp16_g2l_split", background=(0.25, 0.5, 0.75))
     img = host(r.rgb)
     assert np.all(img[0] == 0.25) and np.all(img[1] == 0.5) and np.all(img[2] == 0.75)
@@ -259,13 +262,14 @@ def test_degenerate_inputs_3d():
         bad[k::97] = True
     cam = scenegen.orbit_camera(1, 8, W, H)
     o, ref = oracle_chain(sc, cam)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), gs_cam(cam))
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh),
+                        gs_cam(cam))
     rad = host(pre["radii"])
     assert (rad[bad] == 0).all() and (o["radii"][bad] == 0).all()
     assert np.isfinite(host(pre["means2d"])).all() and np.isfinite(host(pre["conics"])).all()
     assert np.isfinite(host(pre["rgb"])).all()
     bs = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
-    opac = dev(sc.opacities)
+    opac = pre["log_opacities"]
     for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split"):
         r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,
                              pre["rgb"], prec)

@@ -71,7 +71,7 @@ def test_fullsize_sampled(workload, pose, precs):
     cam_np = scenegen.make_camera(cfg, pose)
     cam = gs.make_camera(cam_np.viewmat, cam_np.fx, cam_np.fy, cam_np.cx, cam_np.cy, W, H,
                          campos=cam_np.campos)
-    pre = gs.preprocess(means, scales, quats, sh, cam)
+    pre = gs.preprocess(means, scales, quats, opac, sh, cam)
     probe = gs.BinSorter(sc.P, 0, W, H)
     probe(pre["means2d"], pre["radii"], pre["depths"])
     N = probe.n_splats()
@@ -85,7 +85,8 @@ def test_fullsize_sampled(workload, pose, precs):
     tiles = sample_tiles(ranges_g, gx, gy, seed=pose)
     imgs = {}
     for prec in ["fp32"] + precs:
-        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,
+        r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"],
+                             pre["log_opacities"],
                              pre["rgb"], prec)
         img, T = host(r.rgb), host(r.T)
         assert np.isfinite(img).all() and T.min() >= 1e-4 and T.max() <= 1.0
@@ -163,10 +164,9 @@ def test_tile_sort_block_sizes_agree():
     sc = scenegen.make_scene(cfg)
     c = scenegen.make_camera(cfg)
     cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
-    opac = dev(sc.opacities)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh), cam)
     for precise in (False, True):
-        kw = dict(conics=pre["conics"], opacities=opac, precise=True) if precise else {}
+        kw = dict(conics=pre["conics"], log_opacities=pre["log_opacities"], precise=True) if precise else {}
         small = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, **kw)
         N = small.n_splats()
         big = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, capacity=(24 << 20) + 5,

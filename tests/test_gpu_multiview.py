@@ -67,10 +67,11 @@ def test_bin_sort_multiview_matches_per_view_and_oracle(precise):
     say(f"multi-view bin/sort, precise={precise}")
     sc, cams = small_case()
     gcams = [gs_cam(c) for c in cams]
-    pre = gs.preprocess_multiview(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), gcams)
-    opac = dev(sc.opacities)
+    pre = gs.preprocess_multiview(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities),
+                                  dev(sc.sh), gcams)
+    opac = pre["log_opacities"]
     V, P = len(cams), sc.P
-    kw = lambda v: dict(conics=pre["conics"][v], opacities=opac, precise=True) if precise else {}
+    kw = lambda v: dict(conics=pre["conics"][v], log_opacities=opac, precise=True) if precise else {}
     per = [gs.bin_sort(pre["means2d"][v], pre["radii"][v], pre["depths"][v], c.width, c.height,
                        **kw(v)) for v, c in enumerate(cams)]
     ns = [b.n_splats() for b in per]
@@ -121,7 +122,8 @@ def test_bin_sort_multiview_empty_and_tiny_views():
     cams = cams + [base[k % 8] if k % 5 else away for k in range(gs.GS_MAX_BIN_VIEWS - len(cams))]
     assert len(cams) == gs.GS_MAX_BIN_VIEWS
     gcams = [gs_cam(c) for c in cams]
-    pre = gs.preprocess_multiview(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), gcams)
+    pre = gs.preprocess_multiview(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities),
+                                  dev(sc.sh), gcams)
     ns = []
     per = []
     for v, c in enumerate(cams):
@@ -177,13 +179,15 @@ def test_preprocess_multiview_matches_single_and_oracle():
     sc, cams = small_case(n_views=5, P=20000)
     t = scene_tensors(sc)
     say("preprocess_multiview: 5 views, P=20000")
-    mv = gs.preprocess_multiview(t["means3d"], t["scales"], t["quats"], t["sh"],
+    mv = gs.preprocess_multiview(t["means3d"], t["scales"], t["quats"], t["opacities"], t["sh"],
                                  [gs_cam(c) for c in cams])
     for v, c in enumerate(cams):
-        one = gs.preprocess(t["means3d"], t["scales"], t["quats"], t["sh"], gs_cam(c))
+        one = gs.preprocess(t["means3d"], t["scales"], t["quats"], t["opacities"], t["sh"],
+                            gs_cam(c))
         # the two kernels share the projection code and round identically
         for k in ("radii", "tiles_touched", "means2d", "conics", "depths", "rgb"):
             assert np.array_equal(host(mv[k][v]), host(one[k])), (v, k)
+        assert np.array_equal(host(mv["log_opacities"]), host(one["log_opacities"]))
         o = oracle.preprocess_3d(sc, c)
         rad = host(mv["radii"][v])
         same = rad == o["radii"]
@@ -202,10 +206,11 @@ def test_many_views():
     sc = scenegen.scene_3d(8000, 1018)
     cams = [scenegen.orbit_camera(k, 40, *res[k % len(res)]) for k in range(40)]
     t = scene_tensors(sc)
-    mvp = gs.preprocess_multiview(t["means3d"], t["scales"], t["quats"], t["sh"],
+    mvp = gs.preprocess_multiview(t["means3d"], t["scales"], t["quats"], t["opacities"], t["sh"],
                                   [gs_cam(c) for c in cams])
     for v in (0, 15, 16, 17, 39):
-        one = gs.preprocess(t["means3d"], t["scales"], t["quats"], t["sh"], gs_cam(cams[v]))
+        one = gs.preprocess(t["means3d"], t["scales"], t["quats"], t["opacities"], t["sh"],
+                            gs_cam(cams[v]))
         for k in ("radii", "means2d", "conics", "rgb", "depths"):
             assert np.array_equal(host(mvp[k][v]), host(one[k])), (v, k)
     mv = gs.MultiViewRenderer(t, [gs_cam(c) for c in cams])

@@ -46,7 +46,7 @@ def upload_lists(ranges, ids):
 def test_preprocess_2d_parity(W, H):
     say(f"preprocess_2d {W}x{H}")
     sc, d = scene2d_inputs(W, H, 2000, 1001)
-    g = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    g = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     o = oracle.preprocess_2d(sc.means2d, sc.cov2d, W, H)
     r_g = host(g["radii"])
     same = r_g == o["radii"]
@@ -55,6 +55,9 @@ def test_preprocess_2d_parity(W, H):
     assert np.all(host(g["tiles_touched"])[same] == o["tiles_touched"][same])
     vis = same & (o["radii"] > 0)
     np.testing.assert_allclose(host(g["conics"])[vis], o["conics"][vis], rtol=2e-5, atol=1e-7)
+    # ln o for every Gaussian, to FP32 rounding (opacity crosses as ln o)
+    np.testing.assert_allclose(host(g["log_opacities"]), np.log(sc.opacities.astype(np.float64)),
+                               rtol=3e-7, atol=1e-7)
 
 
 def test_preprocess_3d_parity():
@@ -63,7 +66,7 @@ def test_preprocess_3d_parity():
     cam = scenegen.orbit_camera(1, 7, 640, 360)
     c = gs.make_camera(cam.viewmat, cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height,
                        campos=cam.campos)
-    g = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), c)
+    g = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh), c)
     o = oracle.preprocess_3d(sc, cam)
     r_g = host(g["radii"])
     same = r_g == o["radii"]
@@ -77,6 +80,8 @@ def test_preprocess_3d_parity():
     scale = np.abs(co).max(axis=1, keepdims=True)
     assert np.max(np.abs(cg - co) / scale) < 2e-3
     np.testing.assert_allclose(host(g["rgb"])[vis], o["rgb"][vis], atol=2e-5)
+    np.testing.assert_allclose(host(g["log_opacities"]), np.log(sc.opacities.astype(np.float64)),
+                               rtol=3e-7, atol=1e-7)
 
 
 # ---------------------------------------------------------------- bin / sort
@@ -90,7 +95,7 @@ def test_bin_sort_exact(W, H, P, seed):
     depths[1::97] = -0.0       # -0 equals +0
     depths[2::97] = 0.0
     depths[3::101] = np.nan    # skipped
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     radii = host(pre["radii"])
     bs = gs.bin_sort(d["means2d"], pre["radii"], dev(depths), W, H)
     ranges_o, ids_o = oracle.bin_splats(sc.means2d, radii, depths, W, H)
@@ -104,7 +109,7 @@ def test_bin_sort_overflow_and_empty():
     say("bin_sort overflow / empty")
     W, H = 128, 96
     sc, d = scene2d_inputs(W, H, 500, 3)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     full = gs.bin_sort(d["means2d"], pre["radii"], d["depths"], W, H)
     N = full.n_splats()
     assert N > 10
@@ -133,7 +138,7 @@ def test_bin_sort_first_pass_histogram_both_ways():
     runs a histogram kernel otherwise: both give the oracle's lists."""
     W, H = 96, 64
     sc, d = scene2d_inputs(W, H, 40, 12)  # ~190 splats
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     ranges_o, ids_o = oracle.bin_splats(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     N = len(ids_o)
     say(f"bin_sort first-pass histogram, N={N}")
@@ -152,12 +157,12 @@ def test_bin_sort_first_pass_histogram_both_ways():
 def test_raster_fp32_parity(prec, W, H, P, seed):
     say(f"raster {prec} {W}x{H}")
     sc, d = scene2d_inputs(W, H, P, seed)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     conics = host(pre["conics"]).astype(np.float64)
     ranges, ids = oracle_lists(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     rg, idg = upload_lists(ranges, ids)
     bg = (0.1, 0.2, 0.3)
-    r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], d["opac"], d["rgb"], prec,
+    r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"], prec,
                          background=bg)
     st = fp32_check(W, H, ranges, ids, sc.means2d, conics, sc.opacities, sc.rgb, host(r.rgb),
                     host(r.T), bg=bg)
@@ -172,13 +177,13 @@ def test_raster_counters_match_oracle():
     say("raster counters")
     W, H = 256, 256
     sc, d = scene2d_inputs(W, H, 2000, 1001)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     ranges, ids = oracle_lists(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     rg, idg = upload_lists(ranges, ids)
     ref = oracle.render(W, H, ranges, ids, sc.means2d, host(pre["conics"]), sc.opacities, sc.rgb)
     want = np.array([ref["f_blend"].sum(), ref["f_cull"].sum(), ref["term"].sum()])
     for prec in ["fp32", "fp32_earlycull"] + MFMA_PRECS:
-        r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], d["opac"], d["rgb"], prec,
+        r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"], prec,
                              count=True)
         got = host(r.counters)
         say(f"  {prec}: blend {got[0]} cull {got[1]} term {got[2]} (oracle {want.tolist()})")
@@ -193,10 +198,10 @@ def test_raster_counters_match_oracle():
 def test_raster_mfma_quality(prec, W, H, P, seed):
     say(f"raster {prec} {W}x{H}")
     sc, d = scene2d_inputs(W, H, P, seed)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     ranges, ids = oracle_lists(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     rg, idg = upload_lists(ranges, ids)
-    r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], d["opac"], d["rgb"], prec)
+    r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"], prec)
     ref = oracle.render(W, H, ranges, ids, sc.means2d, host(pre["conics"]), sc.opacities, sc.rgb)
     q = quality(host(r.rgb), ref["rgb"])
     say(f"  PSNR {q['psnr']:.1f} dB  max {q['max_abs']:.2e}  within 2/255 {q['frac_2_255']:.5f}")
@@ -224,10 +229,10 @@ def test_raster_fp16_global_is_negative_control():
     paper's FP16-without-local-coordinates ablation)."""
     W, H = 256, 256
     sc, d = scene2d_inputs(W, H, 2000, 1001)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     ranges, ids = oracle_lists(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     rg, idg = upload_lists(ranges, ids)
-    r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], d["opac"], d["rgb"], "fp16_global")
+    r = gs.rasterize_fwd(W, H, rg, idg, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"], "fp16_global")
     ref = oracle.render(W, H, ranges, ids, sc.means2d, host(pre["conics"]), sc.opacities, sc.rgb)
     p = psnr(host(r.rgb), ref["rgb"])
     say(f"fp16_global PSNR {p:.1f} dB")
@@ -252,7 +257,7 @@ def test_beta_matches_emulation(prec, mode):
     say(f"beta dump {prec}")
     W, H = 256, 256
     sc, d = scene2d_inputs(W, H, 2000, 1001)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     ranges, ids = oracle_lists(sc.means2d, host(pre["radii"]), sc.depths, W, H)
     rg, idg = upload_lists(ranges, ids)
     conics = host(pre["conics"]).astype(np.float64)
@@ -264,7 +269,7 @@ def test_beta_matches_emulation(prec, mode):
         cnt = int(min(e - s, 64))
         if cnt == 0:
             continue
-        B = host(gs.rasterize_beta(W, H, tile, rg, idg, d["means2d"], pre["conics"], d["opac"],
+        B = host(gs.rasterize_beta(W, H, tile, rg, idg, d["means2d"], pre["conics"], pre["log_opacities"],
                                    prec, cnt))
         tx, ty = tile % gx, tile // gx
         tc = np.array([16 * tx + 7.5, 16 * ty + 7.5])
@@ -317,10 +322,10 @@ def test_translation_invariance_g2l():
         imgs = []
         for off in (np.zeros(2), shift):
             m = (mu + off).astype(np.float32)
-            pre = gs.preprocess_2d(dev(m), dev(sc.cov2d), W, H)
+            pre = gs.preprocess_2d(dev(m), dev(sc.cov2d), dev(sc.opacities), W, H)
             ranges, ids = oracle_lists(m, host(pre["radii"]), sc.depths, W, H)
             rg, idg = upload_lists(ranges, ids)
-            r = gs.rasterize_fwd(W, H, rg, idg, dev(m), pre["conics"], dev(sc.opacities), dev(sc.rgb), prec)
+            r = gs.rasterize_fwd(W, H, rg, idg, dev(m), pre["conics"], pre["log_opacities"], dev(sc.rgb), prec)
             imgs.append(host(r.rgb).copy())
         a = imgs[0][:, 0:160, 0:176]
         b = imgs[1][:, 48:208, 64:240]
@@ -333,7 +338,7 @@ def test_translation_invariance_g2l():
 def test_determinism_and_empty_tiles():
     W, H = 250, 190
     sc, d = scene2d_inputs(W, H, 300, 12, s_max=3.0)
-    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], W, H)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
     bs = gs.bin_sort(d["means2d"], pre["radii"], d["depths"], W, H)
     ranges = host(bs.ranges)
     assert (ranges[:, 1] == ranges[:, 0]).any()  # some tiles are empty
@@ -341,7 +346,7 @@ def test_determinism_and_empty_tiles():
         imgs = []
         for _ in range(3):
             r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"],
-                                 d["opac"], d["rgb"], prec, background=(0.5, 0.25, 1.0))
+                                 pre["log_opacities"], d["rgb"], prec, background=(0.5, 0.25, 1.0))
             imgs.append((host(r.rgb).copy(), host(r.T).copy(), host(r.n_contrib).copy()))
         for k in range(3):
             assert np.array_equal(imgs[0][k], imgs[1][k]) and np.array_equal(imgs[0][k], imgs[2][k])
@@ -358,14 +363,14 @@ def test_end_to_end_3d_small():
     sc = scenegen.scene_3d(100_000, 4321)
     cam = scenegen.orbit_camera(0, 1, W, H)
     c = gs.make_camera(cam.viewmat, cam.fx, cam.fy, cam.cx, cam.cy, W, H, campos=cam.campos)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), c)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh), c)
     m2, rad, dep = host(pre["means2d"]), host(pre["radii"]), host(pre["depths"])
     bs = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
     ranges, ids = oracle.bin_splats(m2, rad, dep, W, H)
     N = bs.n_splats()
     assert N == len(ids) and np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids)
     assert np.array_equal(host(bs.ranges).astype(np.uint32), ranges)
-    opac = dev(sc.opacities)
+    opac = pre["log_opacities"]
     conics = host(pre["conics"]).astype(np.float64)
     rgb = host(pre["rgb"])
     r = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, pre["means2d"], pre["conics"], opac,

@@ -74,8 +74,9 @@ def test_precise_lists_match_oracle(W, H, P, seed, smax):
     say(f"precise binning {W}x{H} P={P}")
     sc = scenegen.scene_2d(P, W, H, seed, o_min=0.002, o_max=0.99, s_max=smax)
     m2, cov, op = dev(sc.means2d), dev(sc.cov2d), dev(sc.opacities)
-    pre = gs.preprocess_2d(m2, cov, W, H)
-    bs = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, conics=pre["conics"], opacities=op,
+    pre = gs.preprocess_2d(m2, cov, op, W, H)
+    op = pre["log_opacities"]
+    bs = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, conics=pre["conics"], log_opacities=op,
                      precise=True)
     con = host(pre["conics"]).astype(np.float64)
     r_o, i_o = oracle.bin_splats(sc.means2d, host(pre["radii"]), sc.depths, W, H, conics=con,
@@ -114,19 +115,20 @@ def test_precise_edge_cases():
     # every opacity below 1/255: nothing can reach the culling threshold
     sc = scenegen.scene_2d(300, W, H, 5, o_min=0.001, o_max=0.0035)
     m2 = dev(sc.means2d)
-    pre = gs.preprocess_2d(m2, dev(sc.cov2d), W, H)
+    pre = gs.preprocess_2d(m2, dev(sc.cov2d), dev(sc.opacities), W, H)
     bs = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, capacity=64,
-                     conics=pre["conics"], opacities=dev(sc.opacities), precise=True)
+                     conics=pre["conics"], log_opacities=pre["log_opacities"], precise=True)
     assert bs.n_splats() == 0 and int(host(bs.ranges).max()) == 0
     # overflow: N > capacity leaves every range empty and reports N
     sc = scenegen.scene_2d(300, W, H, 6)
-    m2, op = dev(sc.means2d), dev(sc.opacities)
-    pre = gs.preprocess_2d(m2, dev(sc.cov2d), W, H)
-    ok = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, conics=pre["conics"], opacities=op,
+    m2 = dev(sc.means2d)
+    pre = gs.preprocess_2d(m2, dev(sc.cov2d), dev(sc.opacities), W, H)
+    op = pre["log_opacities"]
+    ok = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, conics=pre["conics"], log_opacities=op,
                      precise=True)
     N = ok.n_splats()
     small = gs.bin_sort(m2, pre["radii"], dev(sc.depths), W, H, capacity=N - 1,
-                        conics=pre["conics"], opacities=op, precise=True)
+                        conics=pre["conics"], log_opacities=op, precise=True)
     assert small.n_splats() == N and int(host(small.ranges).max()) == 0
 
 
@@ -138,11 +140,11 @@ def test_precise_fullsize_sampled():
     sc = scenegen.make_scene(cfg)
     c = scenegen.make_camera(cfg)
     cam = gs.make_camera(c.viewmat, c.fx, c.fy, c.cx, c.cy, W, H, campos=c.campos)
-    op = dev(sc.opacities)
-    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.sh), cam)
+    pre = gs.preprocess(dev(sc.means), dev(sc.scales), dev(sc.quats), dev(sc.opacities), dev(sc.sh), cam)
+    op = pre["log_opacities"]
     full = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H)
     bs = gs.bin_sort(pre["means2d"], pre["radii"], pre["depths"], W, H, conics=pre["conics"],
-                     opacities=op, precise=True)
+                     log_opacities=op, precise=True)
     Np, N3 = bs.n_splats(), full.n_splats()
     say(f"  N precise {Np} vs 3-sigma {N3} ({Np / N3:.3f})")
     assert Np < N3

@@ -41,7 +41,7 @@ def test_noalloc_matches_workspace_call(order):
         cam = scenegen.orbit_camera(1, 8, W, H)
         gcam = gs.make_camera(cam.viewmat, cam.fx, cam.fy, cam.cx, cam.cy, W, H, campos=cam.campos)
         d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-        pre = gs.preprocess(d(sc.means), d(sc.scales), d(sc.quats), d(sc.sh), gcam)
+        pre = gs.preprocess(d(sc.means), d(sc.scales), d(sc.quats), d(sc.opacities), d(sc.sh), gcam)
         probe = gs.BinSorter(P, 0, W, H)
         probe(pre["means2d"], pre["radii"], pre["depths"])
         N = probe.n_splats()
