@@ -285,6 +285,32 @@ gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_r
                            int32_t precision, float *out_rgb, float *out_T, uint32_t *out_ncontrib,
                            uint64_t *d_counters, void *stream);
 
+/* Launch shape of the one-view rasteriser (chosen by an autotuner).
+ *   batch       splats gathered and staged per round by the matrix-core
+ *               kernels: 64, 128 or 256 (the FP32 kernels stage 256)
+ *   chunk_rows  tile rows per XCD chunk: the row-major tiles are cut into
+ *               chunks of about this many rows (1 or 2), chunk k served by
+ *               XCD k mod 8, every XCD the same number of tiles */
+typedef struct {
+    int32_t batch;
+    int32_t chunk_rows;
+} gs_raster_tune;
+
+/*
+ * gs_rasterize_fwd_tuned -- gs_rasterize_fwd with an explicit launch shape
+ * (tune: HOST pointer, NULL = {128, 2}, the shape gs_rasterize_fwd uses).
+ * Every shape renders bit-identical outputs; only the time differs.
+ * Counting launches (d_counters) use batch 128.  Errors: as
+ * gs_rasterize_fwd, plus GS_ERR_INVALID_ARG for a shape outside the listed
+ * values.
+ */
+gs_status gs_rasterize_fwd_tuned(int32_t width, int32_t height, const uint32_t *tile_ranges,
+                                 const uint32_t *sorted_ids, const float *means2d,
+                                 const float *conics, const float *log_opacities, const float *rgb,
+                                 const float *background, int32_t precision,
+                                 const gs_raster_tune *tune, float *out_rgb, float *out_T,
+                                 uint32_t *out_ncontrib, uint64_t *d_counters, void *stream);
+
 /*
  * gs_rasterize_bwd -- gradients of a loss through gs_rasterize_fwd (the
  * backward of Algorithm 1).  Given dL_dimg = dL/dC [3][H][W] (planar, the

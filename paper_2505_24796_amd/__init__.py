@@ -71,6 +71,20 @@ class gs_batch_tune(ctypes.Structure):
         return (self.batch, self.blocks_per_cu, self.xcd_queues)
 
 
+class gs_raster_tune(ctypes.Structure):
+    _fields_ = [("batch", c_int32), ("chunk_rows", c_int32)]
+
+    def as_tuple(self):
+        return (self.batch, self.chunk_rows)
+
+
+def make_raster_tune(batch=128, chunk_rows=2) -> gs_raster_tune:
+    """Launch shape of the one-view rasteriser (gs_rasterize_fwd_tuned)."""
+    t = gs_raster_tune()
+    t.batch, t.chunk_rows = int(batch), int(chunk_rows)
+    return t
+
+
 def make_tune(batch=256, blocks_per_cu=5, xcd_queues=1) -> gs_batch_tune:
     return gs_batch_tune(int(batch), int(blocks_per_cu), int(xcd_queues))
 
@@ -106,6 +120,10 @@ def lib() -> ctypes.CDLL:
         L.gs_rasterize_fwd.restype = ctypes.c_int
         L.gs_rasterize_fwd.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp,
                                        POINTER(c_float), c_int32, vp, vp, vp, vp, vp]
+        L.gs_rasterize_fwd_tuned.restype = ctypes.c_int
+        L.gs_rasterize_fwd_tuned.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp,
+                                             POINTER(c_float), c_int32, POINTER(gs_raster_tune),
+                                             vp, vp, vp, vp, vp]
         L.gs_rasterize_bwd.restype = ctypes.c_int
         L.gs_rasterize_bwd.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp, POINTER(c_float),
                                        c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -410,17 +428,20 @@ def bin_sort_noalloc(means2d, radii, depths, width: int, height: int, sorted_ids
 
 
 class Rasterizer:
-    """Owns the output buffers of gs_rasterize_fwd for one image size."""
+    """Owns the output buffers of gs_rasterize_fwd for one image size.
+    ``tune`` (a gs_raster_tune, e.g. from autotune.tune_raster) selects the
+    launch shape; None is the library default."""
 
-    def __init__(self, width: int, height: int, device="cuda"):
+    def __init__(self, width: int, height: int, device="cuda", tune: "gs_raster_tune | None" = None):
         self.width, self.height = width, height
+        self.tune = tune
         self.rgb = torch.empty(3, height, width, dtype=torch.float32, device=device)
         self.T = torch.empty(height, width, dtype=torch.float32, device=device)
         self.n_contrib = torch.empty(height, width, dtype=torch.int32, device=device)
         self.counters = torch.zeros(4, dtype=torch.int64, device=device)
 
     def __call__(self, ranges, sorted_ids, means2d, conics, log_opacities, rgb, precision="fp32",
-                 background=(0.0, 0.0, 0.0), count: bool = False):
+                 background=(0.0, 0.0, 0.0), count: bool = False, tune=None):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         for n, t, dt in (("ranges", ranges, torch.int32), ("sorted_ids", sorted_ids, torch.int32),
                          ("means2d", means2d, torch.float32), ("conics", conics, torch.float32),
@@ -430,11 +451,23 @@ class Rasterizer:
         bg = (c_float * 3)(*[float(b) for b in background])
         if count:
             self.counters.zero_()
-        st = lib().gs_rasterize_fwd(self.width, self.height, _ptr(ranges), _ptr(sorted_ids),
-                                    _ptr(means2d), _ptr(conics), _ptr(log_opacities), _ptr(rgb), bg,
-                                    prec, _ptr(self.rgb), _ptr(self.T), _ptr(self.n_contrib),
-                                    _ptr(self.counters) if count else c_void_p(0), _stream())
-        _check("gs_rasterize_fwd", st)
+        tune = self.tune if tune is None else tune
+        if tune is None:
+            st = lib().gs_rasterize_fwd(self.width, self.height, _ptr(ranges), _ptr(sorted_ids),
+                                        _ptr(means2d), _ptr(conics), _ptr(log_opacities), _ptr(rgb),
+                                        bg, prec, _ptr(self.rgb), _ptr(self.T),
+                                        _ptr(self.n_contrib),
+                                        _ptr(self.counters) if count else c_void_p(0), _stream())
+            _check("gs_rasterize_fwd", st)
+        else:
+            st = lib().gs_rasterize_fwd_tuned(self.width, self.height, _ptr(ranges),
+                                              _ptr(sorted_ids), _ptr(means2d), _ptr(conics),
+                                              _ptr(log_opacities), _ptr(rgb), bg, prec,
+                                              ctypes.byref(tune), _ptr(self.rgb), _ptr(self.T),
+                                              _ptr(self.n_contrib),
+                                              _ptr(self.counters) if count else c_void_p(0),
+                                              _stream())
+            _check("gs_rasterize_fwd_tuned", st)
         return self.rgb, self.T, self.n_contrib
 
 

@@ -58,27 +58,28 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 // Tile visited by workgroup `b` of a launch over the gx x gy tiles.
 // Workgroups are dispatched to the 8 XCDs round-robin (b -> XCD b mod 8),
 // and each XCD has its own L2.  The row-major tile sequence is cut into
-// 8 m chunks of c consecutive tiles (about two tile rows each: m =
-// ceil(ceil(gy / 2) / 8) rounds of 8), and chunk k is served by XCD k mod 8.
+// 8 m chunks of c consecutive tiles (about `rows` tile rows each, 1 or 2:
+// m = ceil(ceil(gy / rows) / 8) rounds of 8), and chunk k is served by XCD
+// k mod 8.
 // A Gaussian that spans neighbouring tiles is then mostly fetched into one
 // XCD's L2, every XCD gets a spread of light and heavy image regions, and
 // every XCD gets the same number of tiles (whole two-row bands would give
 // some XCDs a band more than others: 1200 against 960 tiles at 1920x1080).
 // Returns -1 for padding workgroups.
-__host__ __device__ inline void xcd_chunks(int gx, int gy, int &m, int &c) {
-    const int nbands = (gy + 1) / 2;
+__host__ __device__ inline void xcd_chunks(int gx, int gy, int rows, int &m, int &c) {
+    const int nbands = (gy + rows - 1) / rows;
     m = (nbands + 7) / 8;
     const int ntiles = gx * gy;
     c = (ntiles + 8 * m - 1) / (8 * m);
 }
-__host__ __device__ inline int xcd_grid_blocks(int gx, int gy) {
+__host__ __device__ inline int xcd_grid_blocks(int gx, int gy, int rows = 2) {
     int m, c;
-    xcd_chunks(gx, gy, m, c);
+    xcd_chunks(gx, gy, rows, m, c);
     return 8 * m * c;
 }
-__device__ __forceinline__ int xcd_tile(int b, int gx, int gy) {
+__device__ __forceinline__ int xcd_tile(int b, int gx, int gy, int rows = 2) {
     int m, c;
-    xcd_chunks(gx, gy, m, c);
+    xcd_chunks(gx, gy, rows, m, c);
     const int xcd = b & 7, j = b >> 3;
     const int t = ((j / c) * 8 + xcd) * c + j % c;
     return t < gx * gy ? t : -1;

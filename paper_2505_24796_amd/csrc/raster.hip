@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
     __shared__ float2 s_mu[BATCH];
     __shared__ float4 s_co[BATCH];  // s11, s12, s22, o (ln o with EARLY)
     __shared__ float4 s_rgb[BATCH];
-    int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
+    int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy, a.chunk_rows);
     if (tile < 0) return;
     int tx = tile % a.gx, ty = tile / a.gx;
     int px = tx * GS_TILE + (threadIdx.x & 15), py = ty * GS_TILE + (threadIdx.x >> 4);
@@ -121,17 +121,17 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
 
 // At least 5 resident waves per SIMD (the compiler then fits the kernel in
 // <= 80 VGPRs, i.e. 6 waves): the blend's exp / LDS / gather latencies are
-// hidden by other waves rather than by instruction-level parallelism.
-#ifndef MFMA_BATCH
-#define MFMA_BATCH 128
-#endif
-template <int VAR, bool COUNT>
+// hidden by other waves rather than by instruction-level parallelism.  NB
+// splats are gathered and staged per round (64, 128 or 256; the default
+// launch takes 128, the tuned one what an autotuner picked).
+constexpr int DEFAULT_NB = 128;
+template <int VAR, bool COUNT, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_mfma(RasterArgs a) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR, MFMA_BATCH>::BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR, NB>::BYTES];
     __shared__ TileShared sh;
-    const int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy);
+    const int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy, a.chunk_rows);
     if (tile < 0) return;
-    raster_tile_mfma<VAR, COUNT, MFMA_BATCH>(a, tile, stage, sh);
+    raster_tile_mfma<VAR, COUNT, NB>(a, tile, stage, sh);
 }
 
 // Diagnostic: exponents of the first `count` splats of one tile.
@@ -178,27 +178,39 @@ __global__ __launch_bounds__(256) void k_beta_dump(RasterArgs a, int tile, int c
     }
 }
 
+// Counting launches (diagnostics) always take the default batch.
 template <int VAR>
-void launch_mfma(const RasterArgs &a, int blocks, bool count, hipStream_t s) {
-    if (count)
-        hipLaunchKernelGGL((k_raster_mfma<VAR, true>), dim3(blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_raster_mfma<VAR, false>), dim3(blocks), dim3(256), 0, s, a);
+void launch_mfma(const RasterArgs &a, int blocks, bool count, int nb, hipStream_t s) {
+    if (count) {
+        hipLaunchKernelGGL((k_raster_mfma<VAR, true, DEFAULT_NB>), dim3(blocks), dim3(256), 0, s, a);
+        return;
+    }
+    switch (nb) {
+    case 64: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 64>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 256>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 128>), dim3(blocks), dim3(256), 0, s, a); break;
+    }
 }
 
 }  // namespace
 
-extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
-                                      const uint32_t *sorted_ids, const float *means2d,
-                                      const float *conics, const float *log_opacities,
-                                      const float *rgb, const float *background, int32_t precision,
-                                      float *out_rgb, float *out_T, uint32_t *out_ncontrib,
-                                      uint64_t *d_counters, void *stream) {
+extern "C" gs_status gs_rasterize_fwd_tuned(int32_t width, int32_t height,
+                                            const uint32_t *tile_ranges, const uint32_t *sorted_ids,
+                                            const float *means2d, const float *conics,
+                                            const float *log_opacities, const float *rgb,
+                                            const float *background, int32_t precision,
+                                            const gs_raster_tune *tune, float *out_rgb,
+                                            float *out_T, uint32_t *out_ncontrib,
+                                            uint64_t *d_counters, void *stream) {
     const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, log_opacities, rgb, out_rgb, out_T, out_ncontrib};
     if (!valid_inputs(width, height, ptrs, 9) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     if (d_counters && !gs::aligned(d_counters, 8)) return GS_ERR_INVALID_ARG;
     if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
+    const int nb = tune ? tune->batch : DEFAULT_NB;
+    const int rows = tune ? tune->chunk_rows : 2;
+    if (!(nb == 64 || nb == 128 || nb == 256) || !(rows == 1 || rows == 2)) return GS_ERR_INVALID_ARG;
     RasterArgs a;
+    a.chunk_rows = rows;
     a.W = width;
     a.H = height;
     a.gx = gs::grid_x(width);
@@ -217,7 +229,7 @@ extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint3
     a.out_nc = out_ncontrib;
     a.counters = (unsigned long long *)d_counters;
     hipStream_t s = (hipStream_t)stream;
-    int blocks = gs::xcd_grid_blocks(a.gx, a.gy);
+    int blocks = gs::xcd_grid_blocks(a.gx, a.gy, rows);
     bool cnt = d_counters != nullptr;
     switch (precision) {
     case GS_PREC_FP32:
@@ -228,12 +240,23 @@ extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint3
         if (cnt) hipLaunchKernelGGL((k_raster_fp32<true, true>), dim3(blocks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_raster_fp32<true, false>), dim3(blocks), dim3(256), 0, s, a);
         break;
-    case GS_PREC_FP16_GLOBAL: launch_mfma<VAR_F16_GLOBAL>(a, blocks, cnt, s); break;
-    case GS_PREC_FP16_G2L: launch_mfma<VAR_F16_G2L>(a, blocks, cnt, s); break;
-    case GS_PREC_FP16_G2L_SPLIT: launch_mfma<VAR_F16_SPLIT>(a, blocks, cnt, s); break;
-    case GS_PREC_BF16_G2L_SPLIT: launch_mfma<VAR_BF16_SPLIT>(a, blocks, cnt, s); break;
+    case GS_PREC_FP16_GLOBAL: launch_mfma<VAR_F16_GLOBAL>(a, blocks, cnt, nb, s); break;
+    case GS_PREC_FP16_G2L: launch_mfma<VAR_F16_G2L>(a, blocks, cnt, nb, s); break;
+    case GS_PREC_FP16_G2L_SPLIT: launch_mfma<VAR_F16_SPLIT>(a, blocks, cnt, nb, s); break;
+    case GS_PREC_BF16_G2L_SPLIT: launch_mfma<VAR_BF16_SPLIT>(a, blocks, cnt, nb, s); break;
     }
     return gs::launch_status();
+}
+
+extern "C" gs_status gs_rasterize_fwd(int32_t width, int32_t height, const uint32_t *tile_ranges,
+                                      const uint32_t *sorted_ids, const float *means2d,
+                                      const float *conics, const float *log_opacities,
+                                      const float *rgb, const float *background, int32_t precision,
+                                      float *out_rgb, float *out_T, uint32_t *out_ncontrib,
+                                      uint64_t *d_counters, void *stream) {
+    return gs_rasterize_fwd_tuned(width, height, tile_ranges, sorted_ids, means2d, conics,
+                                  log_opacities, rgb, background, precision, nullptr, out_rgb,
+                                  out_T, out_ncontrib, d_counters, stream);
 }
 
 extern "C" gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t tile,
@@ -247,6 +270,7 @@ extern "C" gs_status gs_rasterize_beta(int32_t width, int32_t height, int32_t ti
     if (tile < 0 || tile >= ntiles || count <= 0) return GS_ERR_INVALID_ARG;
     if (precision < GS_PREC_FP16_GLOBAL || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
     RasterArgs a{};
+    a.chunk_rows = 2;
     a.W = width;
     a.H = height;
     a.gx = gs::grid_x(width);

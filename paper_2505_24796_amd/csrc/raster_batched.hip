@@ -181,6 +181,7 @@ extern "C" gs_status gs_batch_plan_write(int32_t nviews, const gs_view *views, v
         if (!valid_inputs(g.width, g.height, ptrs, 9) || !gs::aligned(g.means2d, 8))
             return GS_ERR_INVALID_ARG;
         RasterArgs &a = pv[v].a;
+        a.chunk_rows = 2;
         a.W = g.width;
         a.H = g.height;
         a.gx = gs::grid_x(g.width);

@@ -370,6 +370,7 @@ extern "C" gs_status gs_rasterize_bwd(int32_t width, int32_t height, const uint3
     if (!valid_inputs(width, height, ptrs, 13) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
     BwdArgs a{};
+    a.f.chunk_rows = 2;
     a.f.W = width;
     a.f.H = height;
     a.f.gx = gs::grid_x(width);

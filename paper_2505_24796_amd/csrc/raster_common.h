@@ -26,6 +26,7 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 struct RasterArgs {
     int W, H, gx, gy;
+    int chunk_rows;  // tile rows per XCD chunk (1 or 2), see gs::xcd_tile
     const uint32_t *ranges;
     const uint32_t *ids;
     const float2 *means2d;

@@ -129,18 +129,23 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
                     const float4 col = cols[g];
                     const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(beta));
                     const float test = fmaf(-alpha, T, T);
-                    const bool term = test < T_MIN;
-                    const bool blend = sv && !term;
-                    const float w = blend ? alpha * T : 0.0f;
+                    // one compare decides both outcomes (test is finite)
+                    const bool live = test >= T_MIN;
+                    const bool blend = sv && live, stop = sv && !live;
+                    // the weight alpha T as the drop in transmittance: zero
+                    // for lanes that do not blend, and the weights and the
+                    // final T sum to exactly 1
+                    const float Tn = blend ? test : T;
+                    const float w = T - Tn;
                     C0 = fmaf(col.x, w, C0);
                     C1 = fmaf(col.y, w, C1);
                     C2 = fmaf(col.z, w, C2);
-                    T = blend ? test : T;
+                    T = Tn;
                     last = blend ? __float_as_uint(col.w) : last;
-                    thr = (sv && term) ? __builtin_inff() : thr;
+                    thr = stop ? __builtin_inff() : thr;
                     if (COUNT) {
                         nb += blend ? 1u : 0u;
-                        nt += (sv && term) ? 1u : 0u;
+                        nt += stop ? 1u : 0u;
                     }
                 }
             }

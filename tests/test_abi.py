@@ -94,6 +94,12 @@ def test_invalid_arguments_rejected_on_host(gslib):
     assert gslib.gs_rasterize_fwd(*args, 9, v(16), v(16), v(16), v(0), v(0)) == 1
     # null output image
     assert gslib.gs_rasterize_fwd(*args, 0, v(0), v(16), v(16), v(0), v(0)) == 1
+    # tuned launch: batch must be 64/128/256, chunk rows 1 or 2
+    import paper_2505_24796_amd as gsm
+    for bad in ((96, 2), (128, 3), (0, 1)):
+        t = gsm.make_raster_tune(*bad)
+        assert gslib.gs_rasterize_fwd_tuned(*args, 4, ctypes.byref(t), v(16), v(16), v(16), v(0),
+                                            v(0)) == 1
     # beta dump: tile out of range, FP32 precision not allowed
     assert gslib.gs_rasterize_beta(64, 64, 16, v(16), v(16), v(16), v(16), v(16), 4, 32, v(16),
                                    v(0)) == 1

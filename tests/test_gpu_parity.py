@@ -384,3 +384,26 @@ def test_end_to_end_3d_small():
         q = quality(host(r.rgb), ref["rgb"])
         say(f"  {prec}: PSNR {q['psnr']:.1f} dB within 2/255 {q['frac_2_255']:.5f}")
         check_mfma_quality(prec, q, host(r.rgb), W, H, ranges, ids, m2, conics, sc.opacities, rgb)
+
+
+def test_tuned_launch_shapes_bit_identical():
+    """Every one-view launch shape (splats per round 64/128/256, one- or
+    two-row XCD chunks) renders bit-identical outputs, for the FP32 and the
+    matrix-core kernels; the autotuner checks the same and installs the
+    fastest."""
+    from paper_2505_24796_amd import autotune
+    W, H = 250, 190
+    sc, d = scene2d_inputs(W, H, 3000, 7)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
+    bs = gs.bin_sort(d["means2d"], pre["radii"], d["depths"], W, H)
+    for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split"):
+        base = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"],
+                                pre["log_opacities"], d["rgb"], prec)
+        ref = (host(base.rgb), host(base.T), host(base.n_contrib))
+        rz = gs.Rasterizer(W, H)
+        res = autotune.tune_raster(rz, bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"],
+                                   pre["log_opacities"], d["rgb"], prec, reps=2, warmup=1)
+        say(f"tuned {prec}: {res['best']}")
+        rz(bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"], prec)
+        got = (host(rz.rgb), host(rz.T), host(rz.n_contrib))
+        assert all(np.array_equal(a, b) for a, b in zip(ref, got)), prec
