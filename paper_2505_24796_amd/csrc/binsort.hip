@@ -279,16 +279,38 @@ __device__ __forceinline__ bool seg_block(const SegTable &st, uint32_t b, int &s
     return false;
 }
 
+// Logical block of workgroup b of a radix launch: the launch's active blocks
+// (the concatenated segments') are cut into 8 contiguous runs, run x served
+// by XCD x (workgroups reach the 8 XCDs round-robin), so blocks whose
+// output ranges neighbour each other (a digit's keys of block k are written
+// just before those of block k + 1) share an L2 and their partial cache
+// lines merge there.  False for padding workgroups.
+template <int TILE>
+__device__ __forceinline__ bool xcd_block(const SegTable &st, uint32_t b, uint32_t &lb) {
+    uint32_t total = 0;
+    for (int q = 0; q < st.nseg; ++q) {
+        uint32_t base, n;
+        st.get(q, base, n);
+        total += (n + TILE - 1) / TILE;
+    }
+    const uint32_t per = (total + 7) / 8, j = b >> 3, x = b & 7;
+    if (j >= per) return false;
+    lb = x * per + j;
+    return lb < total;
+}
+
 template <int ITEMS, int BITS, bool DROP, int NT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                              SegTable st, int shift,
-                                                             uint32_t *__restrict__ hist) {
+                                                             uint32_t *__restrict__ hist,
+                                                             uint32_t ncols) {
     constexpr int NDIG = 1 << BITS;
     constexpr int TILE = NT * ITEMS;
     __shared__ uint32_t h[NDIG];
     int sg;
-    uint32_t lb, base, n, col0;
-    if (!seg_block<TILE>(st, blockIdx.x, sg, lb, base, n, col0)) return;  // idle: uniform exit
+    uint32_t lb, base, n, col0, L;
+    if (!xcd_block<TILE>(st, blockIdx.x, L)) return;  // idle: uniform exit
+    if (!seg_block<TILE>(st, L, sg, lb, base, n, col0)) return;
     const uint32_t kb = st.key_base(sg);
     const size_t b0 = (size_t)lb * TILE;
     // every load issued before the first count (a block that is not idle has
@@ -308,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t *__restrict__ 
             atomicAdd(&h[((kv[k] - kb) >> shift) & (NDIG - 1)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < NDIG) hist[(size_t)threadIdx.x * ncols + L] = h[threadIdx.x];
 }
 
 // Exclusive scan over columns [0, nb) of get(i) into out[i], ROW_RPT
@@ -372,7 +394,7 @@ template <int ITEMS, int BITS, bool DROP, int NT>
 __global__ __launch_bounds__(NT) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, SegTable st, int shift, const uint32_t *__restrict__ hist_scan,
-    const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept) {
+    const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept, uint32_t ncols) {
     constexpr int NDIG = 1 << BITS;
     __shared__ uint32_t wcnt[(NT / 64)][NDIG];
     __shared__ uint32_t gbase[NDIG];   // segment position of this block's first key of digit d
@@ -383,8 +405,9 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     __shared__ uint32_t sval[TILE];
     __shared__ uint32_t lds_scan[(NT / 64)];
     int sg;
-    uint32_t lb, sbase, n, col0;
-    if (!seg_block<TILE>(st, blockIdx.x, sg, lb, sbase, n, col0)) return;  // idle: uniform exit
+    uint32_t lb, sbase, n, col0, L;
+    if (!xcd_block<TILE>(st, blockIdx.x, L)) return;  // idle: uniform exit
+    if (!seg_block<TILE>(st, L, sg, lb, sbase, n, col0)) return;
     const uint32_t kb = st.key_base(sg);
     const size_t base = (size_t)lb * TILE;  // within the segment
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -398,7 +421,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         const uint32_t kept = block_excl_scan<uint32_t>(t, ex, lds_scan);
         if (DROP && lb == 0 && threadIdx.x == 0) n_kept[sg] = kept;
         if (threadIdx.x < NDIG)
-            gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+            gbase[threadIdx.x] = ex + hist_scan[(size_t)threadIdx.x * ncols + L];
     }
     __syncthreads();
 
@@ -498,10 +521,10 @@ void scatter_launch(SortBufs b, int cur, const SegTable &st, int shift, uint32_t
                     uint32_t *hist, uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
     constexpr int IT = ITEMS * SORT_THREADS / SCATTER_THREADS;
     static_assert(IT >= 1 && IT * SCATTER_THREADS == ITEMS * SORT_THREADS, "same block of keys");
-    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS>), dim3(ncols),
+    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS>), dim3((ncols + 7) / 8 * 8),
                        dim3(SCATTER_THREADS), 0, s,
                        b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], st, shift, hist, totals,
-                       n_kept);
+                       n_kept, ncols);
 }
 
 template <int ITEMS, int BITS, bool DROP>
@@ -509,8 +532,8 @@ void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t nco
                 uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
     constexpr int TILE = SORT_THREADS * ITEMS;
     constexpr int IT = TILE / SCATTER_THREADS;  // the histogram takes the same wide workgroups
-    hipLaunchKernelGGL((k_radix_hist<IT, BITS, DROP, SCATTER_THREADS>), dim3(ncols),
-                       dim3(SCATTER_THREADS), 0, s, b.k[cur], st, shift, hist);
+    hipLaunchKernelGGL((k_radix_hist<IT, BITS, DROP, SCATTER_THREADS>), dim3((ncols + 7) / 8 * 8),
+                       dim3(SCATTER_THREADS), 0, s, b.k[cur], st, shift, hist, ncols);
     hipLaunchKernelGGL(k_hist_rows<TILE>, dim3(1 << BITS, st.nseg), dim3(SORT_THREADS), 0, s, hist,
                        st, ncols, totals);
     scatter_launch<ITEMS, BITS, DROP>(b, cur, st, shift, ncols, hist, totals, n_kept, s);
