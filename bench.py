@@ -55,16 +55,19 @@ RASTER_SOURCES = ["paper_2505_24796_amd/csrc/raster.hip", "paper_2505_24796_amd/
                   "paper_2505_24796_amd/csrc/raster_common.h", "paper_2505_24796_amd/csrc/common.h"]
 
 
-def read_traffic(precision: str):
+def read_traffic(precision: str, shape=None):
     """HBM traffic of the raster kernel measured by rocprofv3 counters
     (profiles/raster_traffic_<precision>.json), only if the kernel source is
-    unchanged since the counters were taken."""
+    unchanged since the counters were taken and the launch shape is the one
+    they were taken at."""
     p = os.path.join(ROOT, "profiles", f"raster_traffic_fwd_1080p_1M_{precision}.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash(RASTER_SOURCES):
+        return None
+    if shape is not None and rec.get("launch_shape") != shape:
         return None
     return rec
 
@@ -510,6 +513,9 @@ def main():
                     help="only time the 1080p/1M bin/sort (3-sigma and precise), for traces")
     ap.add_argument("--train-only", action="store_true",
                     help="only time the 1600x1064/1M training step (forward + backward), for traces")
+    ap.add_argument("--raster-shape", default=None,
+                    help="BATCH,ROWS: use this one-view launch shape for the headline precision "
+                         "instead of tuning (profiling runs; the FP32 path then takes the default)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -567,7 +573,11 @@ def main():
     # matrix-core path and the FP32 path alike (images compared bit for bit)
     from paper_2505_24796_amd import autotune
     tunes = {}
-    for prec in (args.precision, "fp32"):
+    if args.raster_shape:
+        nb_, cr_ = (int(x) for x in args.raster_shape.split(","))
+        tunes[args.precision] = {"best": {"batch": nb_, "chunk_rows": cr_}, "table": [],
+                                 "given": True}
+    for prec in ((args.precision, "fp32") if not args.raster_shape else ()):
         r_t = gs.Rasterizer(W, H)
         tunes[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
                                            pre["conics"], pre["log_opacities"], pre["rgb"], prec,
@@ -707,7 +717,8 @@ def main():
     # 12-flop exponent is an FP16 contraction on the matrix cores.
     valu_flop = FLOP_TEST * pairs + FLOP_PER_SURVIVOR * survivors
     achieved = valu_flop / raster_s / 1e12
-    counters = read_traffic(args.precision)
+    hb = tunes[args.precision]["best"]
+    counters = read_traffic(args.precision, {"batch": hb["batch"], "chunk_rows": hb["chunk_rows"]})
     traffic = counters.get("bytes_per_launch") if counters else None
     log("[bench] peak-rate probes")
     peaks = {"exp_per_s": gs.peak_probe("exp", 4000, 2048),
