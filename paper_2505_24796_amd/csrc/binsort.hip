@@ -1061,41 +1061,44 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__
     }
 }
 
-// Workgroup d: digit d's counts of the first tile pass per block of BLK
-// keys (the sum of the counts of the block's G = BLK / WIN
-// emission windows of WIN slots, from hist2 as k_emit<false, true> wrote
-// it: one row of RADIX counts per window), scanned exclusively over the blocks into
-// hist[d * ncols + block]; the total goes to totals[d].  One segment (one
-// view).
+// The first tile pass's digit counts per block of BLK keys, from the counts
+// k_emit<false, true> wrote per emission window of WIN slots (one row of
+// RADIX counts per window): a block's counts are the sum of its G = BLK /
+// WIN windows' rows.  Workgroup j takes blocks 16 j .. 16 j + 15: thread d
+// reads digit d of each window (the rows are read whole, 256 threads at a
+// time; threads past the pass's digits idle) and writes digit d's 16 block counts side by side into
+// hist[d * ncols + block], the layout the row scan (k_hist_rows) and the
+// scatter read.  One segment (one view).
+constexpr int WIN_BLOCKS = 16;
 template <int WIN, int BLK>
-__global__ __launch_bounds__(SORT_THREADS) void k_hist_rows_windows(const uint32_t *__restrict__ hist2,
-                                                                    SegTable st,
-                                                                    uint32_t ncols,
-                                                                    uint32_t *__restrict__ hist,
-                                                                    uint32_t *__restrict__ totals) {
+__global__ __launch_bounds__(SORT_THREADS) void k_windows_to_blocks(const uint32_t *__restrict__ hist2,
+                                                                    SegTable st, uint32_t ncols,
+                                                                    uint32_t ndig,
+                                                                    uint32_t *__restrict__ hist) {
     constexpr uint32_t G = BLK / WIN;
-    static_assert(BLK % WIN == 0, "whole windows per block");
-    __shared__ uint32_t lds[WAVES];
+    static_assert(BLK % WIN == 0 && RADIX == SORT_THREADS, "whole windows; one digit per thread");
     uint32_t base, n;
     st.get(0, base, n);
-    const uint32_t nb = (n + BLK - 1u) / BLK;
-    const uint32_t nw = (n + WIN - 1u) / WIN;
-    const uint32_t *src = hist2 + blockIdx.x;  // digit d of window w: src[w * RADIX]
-    uint32_t *row = hist + (size_t)blockIdx.x * ncols;
-    // block i's count: its windows G i .. G i + G - 1 that hold splats
-    // (nw >= 1 whenever nb >= 1)
-    auto block_count = [&](uint32_t i) {
-        uint32_t v = 0u;
+    const uint32_t nb = (n + BLK - 1u) / BLK, nw = (n + WIN - 1u) / WIN;
+    const uint32_t b0 = blockIdx.x * WIN_BLOCKS;
+    if (b0 >= nb) return;  // uniform
+    const uint32_t d = threadIdx.x;
+    if (d >= ndig) return;  // digits the pass does not use (whole waves)
+    uint32_t v[WIN_BLOCKS];
+#pragma unroll
+    for (int i = 0; i < WIN_BLOCKS; ++i) {
+        uint32_t acc = 0u;
 #pragma unroll
         for (uint32_t g = 0; g < G; ++g) {
-            const uint32_t w = G * i + g;
-            const uint32_t x = src[(size_t)(w < nw ? w : nw - 1u) * RADIX];
-            v += w < nw ? x : 0u;
+            const uint32_t w = (b0 + i) * G + g;
+            const uint32_t x = hist2[(size_t)(w < nw ? w : nw - 1u) * RADIX + d];
+            acc += w < nw ? x : 0u;
         }
-        return v;
-    };
-    const uint32_t carry = scan_columns(block_count, row, nb, lds);
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+        v[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < WIN_BLOCKS; ++i)
+        if (b0 + i < nb) hist[(size_t)d * ncols + b0 + i] = v[i];
 }
 
 // Exclusive prefix sum of a[0, n) in place (n <= NT * 8); returns the total.
@@ -1420,8 +1423,11 @@ int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool e
               hipStream_t s) {
     if (emit_hist) {
         const int w0 = radix_width(tbits, 0);
-        hipLaunchKernelGGL((k_hist_rows_windows<EMIT_TILE, SORT_THREADS * ITEMS>), dim3(1 << w0),
-                           dim3(SORT_THREADS), 0, s, hist2, st, ncols, hist, totals);
+        hipLaunchKernelGGL((k_windows_to_blocks<EMIT_TILE, SORT_THREADS * ITEMS>),
+                           dim3((ncols + WIN_BLOCKS - 1) / WIN_BLOCKS), dim3(SORT_THREADS), 0, s,
+                           hist2, st, ncols, 1u << w0, hist);
+        hipLaunchKernelGGL(k_hist_rows<SORT_THREADS * ITEMS>, dim3(1 << w0, 1), dim3(SORT_THREADS),
+                           0, s, hist, st, ncols, totals);
         switch (w0) {
         case 4: scatter_launch<ITEMS, 4, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
         case 5: scatter_launch<ITEMS, 5, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
