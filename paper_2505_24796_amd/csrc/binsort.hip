@@ -57,19 +57,6 @@ constexpr int RCAP = 1280;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Number of valid elements of a pass: static, or the device splat count
-// (zero when it exceeds the capacity, so an overflowing frame does nothing).
-struct Count {
-    uint32_t n_static;
-    const uint32_t *n_dev;
-    uint32_t cap;
-    __device__ __forceinline__ uint32_t get() const {
-        if (!n_dev) return n_static;
-        uint32_t n = *n_dev;
-        return n > cap ? 0u : n;
-    }
-};
-
 // ---------------------------------------------------------------------------
 // Block-level scans
 // ---------------------------------------------------------------------------
@@ -390,11 +377,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
 
 // With DROP, the first block of each segment also writes the number of keys
 // the segment keeps to n_kept[s].  NT threads of ITEMS keys per block.
-template <int ITEMS, int BITS, bool DROP, int NT>
+//
+// With RANGES (the last pass of the tile sort, whose keys are the final
+// tile order), the sorted keys are not written: the pass records where each
+// tile starts, in ranges[2 t], instead.  A block's keys of one digit land
+// side by side in the output, in key order, so inside such a run a key that
+// differs from the one before starts a tile exactly and is stored as is.
+// At a run's first key the key before belongs to another block: there the
+// position is folded in with an atomic min, whose result the exact store,
+// where a tile has one, equals.  The starts hold ~0 before the pass;
+// k_ranges_finish derives the ends.
+template <int ITEMS, int BITS, bool DROP, int NT, bool RANGES>
 __global__ __launch_bounds__(NT) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, SegTable st, int shift, const uint32_t *__restrict__ hist_scan,
-    const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept, uint32_t ncols) {
+    const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept, uint32_t ncols,
+    uint32_t *__restrict__ ranges, uint32_t ntiles) {
+    static_assert(!(RANGES && DROP), "ranges come from the tile sort");
     constexpr int NDIG = 1 << BITS;
     __shared__ uint32_t wcnt[(NT / 64)][NDIG];
     __shared__ uint32_t gbase[NDIG];   // segment position of this block's first key of digit d
@@ -502,8 +501,74 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         uint32_t k = skey[lp];
         uint32_t d = ((k - kb) >> shift) & (NDIG - 1);
         uint32_t dst = sbase + gbase[d] + (lp - lstart[d]);
-        kout[dst] = k;
+        if (!RANGES) kout[dst] = k;
         vout[dst] = sval[lp];
+        if (RANGES) {
+            // the key before in the block's staged order
+            const uint32_t kp = lp > 0 ? skey[lp - 1] : ~0u;
+            const bool first = lp == 0 || (((kp - kb) >> shift) & (NDIG - 1)) != d;
+            if (k < ntiles) {  // always, for keys built here; keeps the writes in bounds
+                if (first) atomicMin(&ranges[2 * k], dst);
+                else if (kp != k) ranges[2 * k] = dst;
+            }
+        }
+    }
+}
+
+// Tile ends from the starts the tile sort's last pass recorded: the output
+// is in tile order, so a tile ends where the next tile with keys starts, or
+// at the number of sorted keys; tiles without keys (start still ~0) become
+// (0, 0).  One tile per thread: the next start inside the workgroup's 256
+// tiles is a suffix minimum over them (starts grow with the tile index);
+// past them the workgroup looks ahead 256 tiles at a time for the first
+// tile with keys.  Nothing was sorted when the splats overflowed the
+// capacity.
+constexpr int FINISH_THREADS = 256;
+__global__ __launch_bounds__(FINISH_THREADS) void k_ranges_finish(uint32_t *__restrict__ ranges,
+                                                                  uint32_t ntiles,
+                                                                  const uint32_t *__restrict__ d_total,
+                                                                  uint32_t cap) {
+    __shared__ uint32_t sw[FINISH_THREADS / 64];
+    __shared__ uint32_t s_after;
+    const uint32_t N = *d_total;
+    const uint32_t t = blockIdx.x * FINISH_THREADS + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t st = t < ntiles ? ranges[2 * t] : ~0u;
+    // inclusive suffix minimum within the wave, then over the waves above
+    uint32_t m = st;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_down((int)m, o, 64);
+        m = lane + o < 64 ? min(m, v) : m;
+    }
+    if (lane == 0) sw[w] = m;
+    // the first start past the workgroup's tiles
+    uint32_t after = ~0u;
+    for (uint32_t base = (blockIdx.x + 1) * FINISH_THREADS; base < ntiles; base += FINISH_THREADS) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t v = i < ntiles ? ranges[2 * i] : ~0u;
+        for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+        __syncthreads();
+        if (threadIdx.x == 0) s_after = ~0u;
+        __syncthreads();
+        if (lane == 0) atomicMin(&s_after, v);
+        __syncthreads();
+        after = s_after;
+        if (after != ~0u) break;  // uniform
+    }
+    __syncthreads();
+    // next start after tile t: the rest of the wave, the waves above, then past the workgroup
+    uint32_t next = (uint32_t)__shfl_down((int)m, 1, 64);
+    if (lane == 63) next = ~0u;
+    for (int i = w + 1; i < FINISH_THREADS / 64; ++i) next = min(next, sw[i]);
+    next = min(next, after);
+    if (next == ~0u) next = N;
+    if (t < ntiles) {
+        if (st == ~0u || N > cap) {
+            ranges[2 * t] = 0u;
+            ranges[2 * t + 1] = 0u;
+        } else {
+            ranges[2 * t + 1] = next;
+        }
     }
 }
 
@@ -516,27 +581,40 @@ struct SortBufs {
 // scatter takes each with SCATTER_THREADS threads (wider workgroups: more
 // waves per CU hide the latency of its ranking and staging steps).
 constexpr int SCATTER_THREADS = 512;
+// (ranges: the tile sort's last pass records the tile ranges there, see
+// k_radix_scatter; nullptr otherwise)
 template <int ITEMS, int BITS, bool DROP>
 void scatter_launch(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols,
-                    uint32_t *hist, uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
+                    uint32_t *hist, uint32_t *totals, uint32_t *n_kept, uint32_t *ranges,
+                    uint32_t ntiles, hipStream_t s) {
     constexpr int IT = ITEMS * SORT_THREADS / SCATTER_THREADS;
     static_assert(IT >= 1 && IT * SCATTER_THREADS == ITEMS * SORT_THREADS, "same block of keys");
-    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS>), dim3((ncols + 7) / 8 * 8),
-                       dim3(SCATTER_THREADS), 0, s,
-                       b.k[cur], b.v[cur], b.k[cur ^ 1], b.v[cur ^ 1], st, shift, hist, totals,
-                       n_kept, ncols);
+    const dim3 grid((ncols + 7) / 8 * 8);
+    if constexpr (!DROP) {
+        if (ranges) {
+            hipLaunchKernelGGL((k_radix_scatter<IT, BITS, false, SCATTER_THREADS, true>), grid,
+                               dim3(SCATTER_THREADS), 0, s, b.k[cur], b.v[cur], b.k[cur ^ 1],
+                               b.v[cur ^ 1], st, shift, hist, totals, n_kept, ncols, ranges, ntiles);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS, false>), grid,
+                       dim3(SCATTER_THREADS), 0, s, b.k[cur], b.v[cur], b.k[cur ^ 1],
+                       b.v[cur ^ 1], st, shift, hist, totals, n_kept, ncols, (uint32_t *)nullptr, 0u);
 }
 
 template <int ITEMS, int BITS, bool DROP>
 void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols, uint32_t *hist,
-                uint32_t *totals, uint32_t *n_kept, hipStream_t s) {
+                uint32_t *totals, uint32_t *n_kept, uint32_t *ranges, uint32_t ntiles,
+                hipStream_t s) {
     constexpr int TILE = SORT_THREADS * ITEMS;
     constexpr int IT = TILE / SCATTER_THREADS;  // the histogram takes the same wide workgroups
     hipLaunchKernelGGL((k_radix_hist<IT, BITS, DROP, SCATTER_THREADS>), dim3((ncols + 7) / 8 * 8),
                        dim3(SCATTER_THREADS), 0, s, b.k[cur], st, shift, hist, ncols);
     hipLaunchKernelGGL(k_hist_rows<TILE>, dim3(1 << BITS, st.nseg), dim3(SORT_THREADS), 0, s, hist,
                        st, ncols, totals);
-    scatter_launch<ITEMS, BITS, DROP>(b, cur, st, shift, ncols, hist, totals, n_kept, s);
+    scatter_launch<ITEMS, BITS, DROP>(b, cur, st, shift, ncols, hist, totals, n_kept, ranges, ntiles,
+                                      s);
 }
 
 // Digit widths of a sort on `bits` key bits: ceil(bits / 8) passes of
@@ -558,28 +636,30 @@ inline int radix_width(int bits, int pass) {
 // is in buffer pair p0 % 2.
 template <int ITEMS>
 int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist,
-               uint32_t *totals, uint32_t *n_kept, hipStream_t s, int p0 = 0) {
+               uint32_t *totals, uint32_t *n_kept, hipStream_t s, int p0 = 0,
+               uint32_t *ranges = nullptr, uint32_t ntiles = 0) {
     if (ncols == 0) ncols = 1;
     int cur = p0 & 1, shift = 0;
     for (int p = 0; p < p0; ++p) shift += radix_width(bits, p);
     for (int p = p0; p < radix_passes(bits); ++p) {
         const int w = radix_width(bits, p);
+        uint32_t *rg = p + 1 == radix_passes(bits) ? ranges : nullptr;  // the last pass
         if (p == 0 && n_kept) {
             switch (w) {
-            case 4: radix_pass<ITEMS, 4, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
-            case 5: radix_pass<ITEMS, 5, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
-            case 6: radix_pass<ITEMS, 6, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
-            case 7: radix_pass<ITEMS, 7, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
-            default: radix_pass<ITEMS, 8, true>(b, cur, st, shift, ncols, hist, totals, n_kept, s); break;
+            case 4: radix_pass<ITEMS, 4, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
+            case 5: radix_pass<ITEMS, 5, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
+            case 6: radix_pass<ITEMS, 6, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
+            case 7: radix_pass<ITEMS, 7, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
+            default: radix_pass<ITEMS, 8, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
             }
             st.n_dev = n_kept;
         } else {
             switch (w) {
-            case 4: radix_pass<ITEMS, 4, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
-            case 5: radix_pass<ITEMS, 5, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
-            case 6: radix_pass<ITEMS, 6, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
-            case 7: radix_pass<ITEMS, 7, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
-            default: radix_pass<ITEMS, 8, false>(b, cur, st, shift, ncols, hist, totals, nullptr, s); break;
+            case 4: radix_pass<ITEMS, 4, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+            case 5: radix_pass<ITEMS, 5, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+            case 6: radix_pass<ITEMS, 6, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+            case 7: radix_pass<ITEMS, 7, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+            default: radix_pass<ITEMS, 8, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
             }
         }
         shift += w;
@@ -753,7 +833,9 @@ __global__ __launch_bounds__(256) void k_depth_keys(int P, const float2 *__restr
                                                     PGauss *__restrict__ pg,
                                                     uint32_t *__restrict__ ranges, int n2) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n2) ranges[i] = 0u;
+    // (~0, 0) per tile for the tile sort's last pass to fold starts into;
+    // (0, 0) when there are no Gaussians (no sort follows)
+    if (i < n2) ranges[i] = (i & 1) || P == 0 ? 0u : ~0u;
     // (with PRECISE every lane of a wave takes part in the row loop, so
     // lanes past P stay, as Gaussians without tiles)
     if (!PRECISE && i >= P) return;
@@ -1255,43 +1337,6 @@ __global__ __launch_bounds__(EMIT_THREADS_P) void k_emit_precise(
     }
 }
 
-// Tile ranges from the tile-sorted keys: 4 keys per thread (one 16-byte
-// load; the neighbours come from the adjacent lanes).
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tkey, Count cnt,
-                                                uint32_t ntiles, uint32_t *__restrict__ ranges) {
-    const uint32_t n = cnt.get();
-    const uint32_t i0 = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
-    const int lane = threadIdx.x & 63;
-    uint32_t k[6];
-    if (i0 + 3 < n) {
-        uint4 q = *(const uint4 *)(tkey + i0);
-        k[1] = q.x;
-        k[2] = q.y;
-        k[3] = q.z;
-        k[4] = q.w;
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) k[j + 1] = (i0 + j < n) ? tkey[i0 + j] : 0xFFFFFFFFu;
-    }
-    // previous key: last key of the lane below; next key: first key of the lane above
-    uint32_t prev = __shfl_up(k[4], 1, 64), next = __shfl_down(k[1], 1, 64);
-    if (lane == 0) prev = (i0 > 0 && i0 - 1 < n) ? tkey[i0 - 1] : 0xFFFFFFFFu;
-    if (lane == 63) next = (i0 + 4 < n) ? tkey[i0 + 4] : 0xFFFFFFFFu;
-    if (i0 + 4 >= n) next = 0xFFFFFFFFu;
-    k[0] = i0 > 0 ? prev : 0xFFFFFFFFu;
-    k[5] = next;
-    if (i0 >= n) return;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        uint32_t i = i0 + j;
-        if (i >= n) break;
-        uint32_t t = k[j + 1];
-        if (t >= ntiles) continue;  // cannot happen for keys built here; keeps writes in bounds
-        if (k[j] != t) ranges[2 * t] = i;
-        if (k[j + 2] != t) ranges[2 * t + 1] = i + 1;
-    }
-}
-
 // Workspace carve-up (every region 256-byte aligned) for n = V * P
 // instances and room for `cap` splats.
 struct Layout {
@@ -1419,24 +1464,26 @@ namespace {
 // result.
 template <int ITEMS>
 int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool emit_hist,
-              const uint32_t *hist2, uint32_t *hist, uint32_t *totals,
-              hipStream_t s) {
+              const uint32_t *hist2, uint32_t *hist, uint32_t *totals, uint32_t *ranges,
+              uint32_t ntiles, hipStream_t s) {
     if (emit_hist) {
         const int w0 = radix_width(tbits, 0);
+        uint32_t *rg = radix_passes(tbits) == 1 ? ranges : nullptr;  // a one-pass sort
         hipLaunchKernelGGL((k_windows_to_blocks<EMIT_TILE, SORT_THREADS * ITEMS>),
                            dim3((ncols + WIN_BLOCKS - 1) / WIN_BLOCKS), dim3(SORT_THREADS), 0, s,
                            hist2, st, ncols, 1u << w0, hist);
         hipLaunchKernelGGL(k_hist_rows<SORT_THREADS * ITEMS>, dim3(1 << w0, 1), dim3(SORT_THREADS),
                            0, s, hist, st, ncols, totals);
         switch (w0) {
-        case 4: scatter_launch<ITEMS, 4, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
-        case 5: scatter_launch<ITEMS, 5, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
-        case 6: scatter_launch<ITEMS, 6, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
-        case 7: scatter_launch<ITEMS, 7, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
-        default: scatter_launch<ITEMS, 8, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, s); break;
+        case 4: scatter_launch<ITEMS, 4, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+        case 5: scatter_launch<ITEMS, 5, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+        case 6: scatter_launch<ITEMS, 6, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+        case 7: scatter_launch<ITEMS, 7, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, rg, ntiles, s); break;
+        default: scatter_launch<ITEMS, 8, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, rg, ntiles, s); break;
         }
     }
-    return radix_sort<ITEMS>(tb, st, ncols, tbits, hist, totals, nullptr, s, emit_hist ? 1 : 0);
+    return radix_sort<ITEMS>(tb, st, ncols, tbits, hist, totals, nullptr, s, emit_hist ? 1 : 0,
+                             ranges, ntiles);
 }
 
 gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t *heights,
@@ -1573,14 +1620,16 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     // within the view)
     int tcur = tile_items((uint32_t)nv, capacity) == TILE_ITEMS_BIG
                    ? tile_sort<TILE_ITEMS_BIG>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
-                                               U(L.hist), U(L.totals), s)
+                                               U(L.hist), U(L.totals), tile_ranges,
+                                               (uint32_t)ntiles, s)
                    : tile_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
-                                           U(L.hist), U(L.totals), s);
-    // 4. ranges (tile indices are unique across views)
-    Count nc{0u, d_num_splats, capacity};
-    uint32_t rblocks = (capacity / 4 + 255) / 256 + 1;
-    hipLaunchKernelGGL(k_ranges, dim3(rblocks), dim3(256), 0, s, tb.k[tcur], nc, (uint32_t)ntiles,
-                       tile_ranges);
+                                           U(L.hist), U(L.totals), tile_ranges, (uint32_t)ntiles, s);
+    (void)tcur;
+    // 4. the last tile pass wrote the starts of the tiles it met (tile
+    // indices are unique across views); the ends follow from them
+    hipLaunchKernelGGL(k_ranges_finish, dim3((ntiles + FINISH_THREADS - 1) / FINISH_THREADS),
+                       dim3(FINISH_THREADS), 0, s, tile_ranges, (uint32_t)ntiles,
+                       (const uint32_t *)d_num_splats, capacity);
     return gs::launch_status();
 }
 
