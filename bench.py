@@ -759,11 +759,12 @@ def main():
                                          "source": "SQ_INSTS_MFMA x 32768 flop (counters)"}
         other["raster_valu_issue_frac"] = counters.get("valu_issue_utilisation")
     # preprocess: 240 B read + 48 B written per Gaussian; bin/sort: per
-    # Gaussian 4 x 16 B (depth passes) + 40 B, per splat 40 B (8 written by
-    # the expansion, 16 by the first tile pass, 4 read by the second pass's
-    # histogram, 8 read and 4 written, the ids, by its scatter)
+    # Gaussian 4 x 16 B (depth passes) + 40 B, per splat 30 B with 16-bit
+    # tile keys (6 written by the expansion, 12 moved by the first tile
+    # pass, 2 read by the second pass's histogram, 6 read and 4 written, the
+    # ids, by its scatter)
     pre_bytes = 288.0 * P
-    bin_bytes = P * (4 * 16 + 40) + 40.0 * N
+    bin_bytes = P * (4 * 16 + 40) + 30.0 * N
     other["preprocess_hbm"] = {"achieved": pre_bytes / (mean[0] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": pre_bytes / (mean[0] / 1e3) / 1e9 / HBM_PEAK_GBS}
     other["bin_sort_hbm"] = {"achieved": bin_bytes / (mean[1] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,

@@ -286,8 +286,8 @@ __device__ __forceinline__ bool xcd_block(const SegTable &st, uint32_t b, uint32
     return lb < total;
 }
 
-template <int ITEMS, int BITS, bool DROP, int NT>
-__global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t *__restrict__ keys,
+template <int ITEMS, int BITS, bool DROP, int NT, typename K = uint32_t>
+__global__ __launch_bounds__(NT) void k_radix_hist(const K *__restrict__ keys,
                                                              SegTable st, int shift,
                                                              uint32_t *__restrict__ hist,
                                                              uint32_t ncols) {
@@ -387,9 +387,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_hist_rows(uint32_t *__restrict
 // position is folded in with an atomic min, whose result the exact store,
 // where a tile has one, equals.  The starts hold ~0 before the pass;
 // k_ranges_finish derives the ends.
-template <int ITEMS, int BITS, bool DROP, int NT, bool RANGES>
+template <int ITEMS, int BITS, bool DROP, int NT, bool RANGES, typename K = uint32_t>
 __global__ __launch_bounds__(NT) void k_radix_scatter(
-    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    const K *__restrict__ kin, const uint32_t *__restrict__ vin, K *__restrict__ kout,
     uint32_t *__restrict__ vout, SegTable st, int shift, const uint32_t *__restrict__ hist_scan,
     const uint32_t *__restrict__ totals, uint32_t *__restrict__ n_kept, uint32_t ncols,
     uint32_t *__restrict__ ranges, uint32_t ntiles) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     __shared__ uint32_t lstart[NDIG];  // local position of this block's first key of digit d
     constexpr int TILE = NT * ITEMS;
     constexpr int W_ITEMS = TILE / (NT / 64), W_CHUNKS = W_ITEMS / 64;
-    __shared__ uint32_t skey[TILE];
+    __shared__ K skey[TILE];
     __shared__ uint32_t sval[TILE];
     __shared__ uint32_t lds_scan[(NT / 64)];
     int sg;
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         if (i < n && (!DROP || key[c] != DROP_KEY)) {
             uint32_t d = ((key[c] - kb) >> shift) & (NDIG - 1);
             uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
-            skey[lp] = key[c];
+            skey[lp] = (K)key[c];
             sval[lp] = val[c];
         }
     }
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         uint32_t k = skey[lp];
         uint32_t d = ((k - kb) >> shift) & (NDIG - 1);
         uint32_t dst = sbase + gbase[d] + (lp - lstart[d]);
-        if (!RANGES) kout[dst] = k;
+        if (!RANGES) kout[dst] = (K)k;
         vout[dst] = sval[lp];
         if (RANGES) {
             // the key before in the block's staged order
@@ -572,9 +572,14 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_ranges_finish(uint32_t *__re
     }
 }
 
-struct SortBufs {
-    uint32_t *k[2], *v[2];
+// Key and id buffer pairs of a sort.  The tile sort of one view with at
+// most 65536 tiles carries 16-bit keys (a quarter fewer bytes per splat).
+template <typename K>
+struct SortBufsT {
+    K *k[2];
+    uint32_t *v[2];
 };
+using SortBufs = SortBufsT<uint32_t>;
 
 // The scatter of a pass from buffer pair cur into cur ^ 1 (hist and totals
 // already scanned).  A pass's blocks hold SORT_THREADS * ITEMS keys; the
@@ -583,8 +588,8 @@ struct SortBufs {
 constexpr int SCATTER_THREADS = 512;
 // (ranges: the tile sort's last pass records the tile ranges there, see
 // k_radix_scatter; nullptr otherwise)
-template <int ITEMS, int BITS, bool DROP>
-void scatter_launch(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols,
+template <int ITEMS, int BITS, bool DROP, typename K>
+void scatter_launch(SortBufsT<K> b, int cur, const SegTable &st, int shift, uint32_t ncols,
                     uint32_t *hist, uint32_t *totals, uint32_t *n_kept, uint32_t *ranges,
                     uint32_t ntiles, hipStream_t s) {
     constexpr int IT = ITEMS * SORT_THREADS / SCATTER_THREADS;
@@ -592,24 +597,24 @@ void scatter_launch(SortBufs b, int cur, const SegTable &st, int shift, uint32_t
     const dim3 grid((ncols + 7) / 8 * 8);
     if constexpr (!DROP) {
         if (ranges) {
-            hipLaunchKernelGGL((k_radix_scatter<IT, BITS, false, SCATTER_THREADS, true>), grid,
+            hipLaunchKernelGGL((k_radix_scatter<IT, BITS, false, SCATTER_THREADS, true, K>), grid,
                                dim3(SCATTER_THREADS), 0, s, b.k[cur], b.v[cur], b.k[cur ^ 1],
                                b.v[cur ^ 1], st, shift, hist, totals, n_kept, ncols, ranges, ntiles);
             return;
         }
     }
-    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS, false>), grid,
+    hipLaunchKernelGGL((k_radix_scatter<IT, BITS, DROP, SCATTER_THREADS, false, K>), grid,
                        dim3(SCATTER_THREADS), 0, s, b.k[cur], b.v[cur], b.k[cur ^ 1],
                        b.v[cur ^ 1], st, shift, hist, totals, n_kept, ncols, (uint32_t *)nullptr, 0u);
 }
 
-template <int ITEMS, int BITS, bool DROP>
-void radix_pass(SortBufs b, int cur, const SegTable &st, int shift, uint32_t ncols, uint32_t *hist,
+template <int ITEMS, int BITS, bool DROP, typename K>
+void radix_pass(SortBufsT<K> b, int cur, const SegTable &st, int shift, uint32_t ncols, uint32_t *hist,
                 uint32_t *totals, uint32_t *n_kept, uint32_t *ranges, uint32_t ntiles,
                 hipStream_t s) {
     constexpr int TILE = SORT_THREADS * ITEMS;
     constexpr int IT = TILE / SCATTER_THREADS;  // the histogram takes the same wide workgroups
-    hipLaunchKernelGGL((k_radix_hist<IT, BITS, DROP, SCATTER_THREADS>), dim3((ncols + 7) / 8 * 8),
+    hipLaunchKernelGGL((k_radix_hist<IT, BITS, DROP, SCATTER_THREADS, K>), dim3((ncols + 7) / 8 * 8),
                        dim3(SCATTER_THREADS), 0, s, b.k[cur], st, shift, hist, ncols);
     hipLaunchKernelGGL(k_hist_rows<TILE>, dim3(1 << BITS, st.nseg), dim3(SORT_THREADS), 0, s, hist,
                        st, ncols, totals);
@@ -634,8 +639,8 @@ inline int radix_width(int bits, int pass) {
 // and writes how many each segment kept there; later passes sort that many.
 // With p0 > 0 the first p0 passes have been done elsewhere and their result
 // is in buffer pair p0 % 2.
-template <int ITEMS>
-int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist,
+template <int ITEMS, typename K = uint32_t>
+int radix_sort(SortBufsT<K> b, SegTable st, uint32_t ncols, int bits, uint32_t *hist,
                uint32_t *totals, uint32_t *n_kept, hipStream_t s, int p0 = 0,
                uint32_t *ranges = nullptr, uint32_t ntiles = 0) {
     if (ncols == 0) ncols = 1;
@@ -644,7 +649,9 @@ int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist
     for (int p = p0; p < radix_passes(bits); ++p) {
         const int w = radix_width(bits, p);
         uint32_t *rg = p + 1 == radix_passes(bits) ? ranges : nullptr;  // the last pass
-        if (p == 0 && n_kept) {
+        bool dropped = false;  // the depth sort's first pass (32-bit keys only)
+        if constexpr (sizeof(K) == 4) {
+          if (p == 0 && n_kept) {
             switch (w) {
             case 4: radix_pass<ITEMS, 4, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
             case 5: radix_pass<ITEMS, 5, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
@@ -653,7 +660,10 @@ int radix_sort(SortBufs b, SegTable st, uint32_t ncols, int bits, uint32_t *hist
             default: radix_pass<ITEMS, 8, true>(b, cur, st, shift, ncols, hist, totals, n_kept, nullptr, 0, s); break;
             }
             st.n_dev = n_kept;
-        } else {
+            dropped = true;
+          }
+        }
+        if (!dropped) {
             switch (w) {
             case 4: radix_pass<ITEMS, 4, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
             case 5: radix_pass<ITEMS, 5, false>(b, cur, st, shift, ncols, hist, totals, nullptr, rg, ntiles, s); break;
@@ -1044,10 +1054,10 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t *a, uint32_t n, uint3
 // walked in row-major order; written from registers with one 16-byte store
 // per array (consecutive threads, consecutive 16-byte pieces).  With HIST,
 // each key's lowest digit (key & dmask) is also counted in hcount (LDS).
-template <bool MULTI, bool HIST>
+template <bool MULTI, bool HIST, typename K>
 __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uint32_t *s_off,
                                            const uint2 *s_rect, const uint32_t *s_id, uint32_t m,
-                                           const ViewRef &vt, uint32_t *__restrict__ tkey,
+                                           const ViewRef &vt, K *__restrict__ tkey,
                                            uint32_t *__restrict__ tid, uint32_t dmask,
                                            uint32_t *hcount) {
     uint32_t tk[EMIT_ITEMS], tg[EMIT_ITEMS];
@@ -1079,15 +1089,19 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
             }
         }
     }
-    const bool vec = s0 + EMIT_ITEMS <= oend && gs::aligned(tkey + s0, 16) && gs::aligned(tid + s0, 16);
+    const bool vec = s0 + EMIT_ITEMS <= oend && gs::aligned(tkey + s0, EMIT_ITEMS * sizeof(K)) &&
+                     gs::aligned(tid + s0, 16);
     if (vec) {
-        *(uint4 *)(tkey + s0) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+        if constexpr (sizeof(K) == 4)
+            *(uint4 *)(tkey + s0) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
+        else  // four 16-bit keys in one 8-byte store
+            *(uint2 *)(tkey + s0) = make_uint2(tk[0] | tk[1] << 16, tk[2] | tk[3] << 16);
         *(uint4 *)(tid + s0) = make_uint4(tg[0], tg[1], tg[2], tg[3]);
     } else {
 #pragma unroll
         for (int i = 0; i < EMIT_ITEMS; ++i) {
             if (s0 + (uint32_t)i < oend) {
-                tkey[s0 + i] = tk[i];
+                tkey[s0 + i] = (K)tk[i];
                 tid[s0 + i] = tg[i];
             }
         }
@@ -1106,7 +1120,7 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
 // dmask, at most RADIX digits) for the first tile pass and writes the counts
 // to hist2[window * RADIX + d], so that pass needs no histogram kernel of its
 // own; windows past the splats write nothing.
-template <bool MULTI, bool HIST>
+template <bool MULTI, bool HIST, typename K = uint32_t>
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ offs,
                                                        const uint2 *__restrict__ rects_sorted,
@@ -1114,7 +1128,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__
                                                        uint32_t nwin, ViewRef vt,
                                                        const uint32_t *__restrict__ n_vis,
                                                        const uint32_t *__restrict__ n_splats,
-                                                       uint32_t cap, uint32_t *__restrict__ tkey,
+                                                       uint32_t cap, K *__restrict__ tkey,
                                                        uint32_t *__restrict__ tid, uint32_t dmask,
                                                        uint32_t *__restrict__ hist2) {
     static_assert(EMIT_ITEMS == 4, "one 16-byte store per thread and array");
@@ -1135,7 +1149,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__
     const uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
     const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
     if (s0 < oend)
-        emit_slots<MULTI, HIST>(s0, oend, s_off, s_rect, s_id, m, vt, tkey, tid, dmask, hcount);
+        emit_slots<MULTI, HIST, K>(s0, oend, s_off, s_rect, s_id, m, vt, tkey, tid, dmask, hcount);
     if (HIST) {
         __syncthreads();
         if (threadIdx.x <= dmask)  // one contiguous row of counts per window
@@ -1209,13 +1223,13 @@ __device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t n, ui
 // thread then finds the run holding its first slot by binary search and
 // writes its EMIT_ITEMS_P tiles directly.  A window with more than RCAP
 // pairs (several very tall Gaussians) walks the rows per thread instead.
-template <bool MULTI>
+template <bool MULTI, typename K = uint32_t>
 __global__ __launch_bounds__(EMIT_THREADS_P) void k_emit_precise(
     int P, const uint32_t *__restrict__ order, const uint32_t *__restrict__ offs,
     const uint2 *__restrict__ rects_sorted, const PGauss *__restrict__ pg,
     const uint32_t *__restrict__ win_start, uint32_t nwin, ViewRef vt,
     const uint32_t *__restrict__ n_vis, const uint32_t *__restrict__ n_splats, uint32_t cap,
-    uint32_t *__restrict__ tkey,
+    K *__restrict__ tkey,
     uint32_t *__restrict__ tid) {
     constexpr int WIN = EMIT_TILE_P;
     __shared__ uint32_t s_off[WIN + 1];
@@ -1332,7 +1346,7 @@ __global__ __launch_bounds__(EMIT_THREADS_P) void k_emit_precise(
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < oend - o0; i += EMIT_THREADS_P) {
-        tkey[o0 + i] = s_tk[i];
+        tkey[o0 + i] = (K)s_tk[i];
         tid[o0 + i] = s_tg[i];
     }
 }
@@ -1462,8 +1476,8 @@ namespace {
 // expansion has counted the first pass's digits per window into hist2: the
 // pass then only scans and scatters.  Returns the buffer pair holding the
 // result.
-template <int ITEMS>
-int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool emit_hist,
+template <int ITEMS, typename K>
+int tile_sort(SortBufsT<K> tb, const SegTable &st, uint32_t ncols, int tbits, bool emit_hist,
               const uint32_t *hist2, uint32_t *hist, uint32_t *totals, uint32_t *ranges,
               uint32_t ntiles, hipStream_t s) {
     if (emit_hist) {
@@ -1482,8 +1496,8 @@ int tile_sort(SortBufs tb, const SegTable &st, uint32_t ncols, int tbits, bool e
         default: scatter_launch<ITEMS, 8, false>(tb, 0, st, 0, ncols, hist, totals, nullptr, rg, ntiles, s); break;
         }
     }
-    return radix_sort<ITEMS>(tb, st, ncols, tbits, hist, totals, nullptr, s, emit_hist ? 1 : 0,
-                             ranges, ntiles);
+    return radix_sort<ITEMS, K>(tb, st, ncols, tbits, hist, totals, nullptr, s, emit_hist ? 1 : 0,
+                                ranges, ntiles);
 }
 
 gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t *heights,
@@ -1585,7 +1599,6 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     uint32_t *other_ids = (npass % 2 == 0) ? U(L.tid) : sorted_ids;
     if (capacity == 0) emit_ids = other_ids = U(L.tid);  // nothing fits
     uint32_t eblocks = (capacity + win - 1) / win;
-    SortBufs tb{{U(L.tkey0), U(L.tkey1)}, {emit_ids, other_ids}};
     SegTable st{};
     st.nseg = nv;
     st.bounds = bounds;
@@ -1600,31 +1613,42 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
     const bool emit_hist = nv == 1 && !precise && eblocks > 0 &&
                            (uint64_t)RADIX * eblocks <= (uint64_t)capacity;
     const int w0 = radix_width(tbits, 0);
-    if (eblocks > 0) {
-        if (precise) {
-            hipLaunchKernelGGL(nv > 1 ? k_emit_precise<true> : k_emit_precise<false>, dim3(eblocks),
-                               dim3(EMIT_THREADS_P), 0, s, n, order,
-                               U(L.offs), (const uint2 *)(ws + L.rects_sorted), (const PGauss *)pg,
-                               U(L.win), L.nwin, vt, (const uint32_t *)n_vis, d_num_splats,
-                               capacity, U(L.tkey0), emit_ids);
-        } else {
-            auto ke = emit_hist ? k_emit<false, true>
-                                : (nv > 1 ? k_emit<true, false> : k_emit<false, false>);
-            hipLaunchKernelGGL(ke, dim3(eblocks), dim3(EMIT_THREADS), 0, s, n, order, U(L.offs),
-                               (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
-                               (const uint32_t *)n_vis, d_num_splats, capacity, U(L.tkey0),
-                               emit_ids, (1u << w0) - 1u, U(L.tkey1));
+    // expansion, then 3. stable sort of each view's splats by tile (digits
+    // of the tile index within the view), with K-bit tile keys
+    auto emit_and_sort = [&](auto key_tag) {
+        using K = decltype(key_tag);
+        SortBufsT<K> tb{{(K *)(ws + L.tkey0), (K *)(ws + L.tkey1)}, {emit_ids, other_ids}};
+        if (eblocks > 0) {
+            if (precise) {
+                auto kp = k_emit_precise<false, K>;
+                if constexpr (sizeof(K) == 4)
+                    if (nv > 1) kp = k_emit_precise<true, K>;
+                hipLaunchKernelGGL(kp, dim3(eblocks), dim3(EMIT_THREADS_P), 0, s, n, order,
+                                   U(L.offs), (const uint2 *)(ws + L.rects_sorted),
+                                   (const PGauss *)pg, U(L.win), L.nwin, vt,
+                                   (const uint32_t *)n_vis, d_num_splats, capacity, tb.k[0],
+                                   emit_ids);
+            } else {
+                auto ke = emit_hist ? k_emit<false, true, K> : k_emit<false, false, K>;
+                if constexpr (sizeof(K) == 4)
+                    if (nv > 1) ke = k_emit<true, false, K>;
+                hipLaunchKernelGGL(ke, dim3(eblocks), dim3(EMIT_THREADS), 0, s, n, order, U(L.offs),
+                                   (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
+                                   (const uint32_t *)n_vis, d_num_splats, capacity, tb.k[0],
+                                   emit_ids, (1u << w0) - 1u, U(L.tkey1));
+            }
         }
-    }
-    // 3. stable sort of each view's splats by tile (digits of the tile index
-    // within the view)
-    int tcur = tile_items((uint32_t)nv, capacity) == TILE_ITEMS_BIG
-                   ? tile_sort<TILE_ITEMS_BIG>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
-                                               U(L.hist), U(L.totals), tile_ranges,
-                                               (uint32_t)ntiles, s)
-                   : tile_sort<TILE_ITEMS>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
-                                           U(L.hist), U(L.totals), tile_ranges, (uint32_t)ntiles, s);
-    (void)tcur;
+        if (tile_items((uint32_t)nv, capacity) == TILE_ITEMS_BIG)
+            tile_sort<TILE_ITEMS_BIG, K>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1),
+                                         U(L.hist), U(L.totals), tile_ranges, (uint32_t)ntiles, s);
+        else
+            tile_sort<TILE_ITEMS, K>(tb, st, L.ncols_tile, tbits, emit_hist, U(L.tkey1), U(L.hist),
+                                     U(L.totals), tile_ranges, (uint32_t)ntiles, s);
+    };
+    if (nv == 1 && ntiles <= 65536)
+        emit_and_sort(uint16_t{});
+    else
+        emit_and_sort(uint32_t{});
     // 4. the last tile pass wrote the starts of the tiles it met (tile
     // indices are unique across views); the ends follow from them
     hipLaunchKernelGGL(k_ranges_finish, dim3((ntiles + FINISH_THREADS - 1) / FINISH_THREADS),
