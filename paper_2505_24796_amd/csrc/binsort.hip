@@ -396,8 +396,10 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     static_assert(!(RANGES && DROP), "ranges come from the tile sort");
     constexpr int NDIG = 1 << BITS;
     __shared__ uint32_t wcnt[(NT / 64)][NDIG];
-    __shared__ uint32_t gbase[NDIG];   // segment position of this block's first key of digit d
-    __shared__ uint32_t lstart[NDIG];  // local position of this block's first key of digit d
+    // gbase[d]: first the segment position of this block's first key of
+    // digit d, then that minus the key's local position (staged key lp of
+    // digit d goes to sbase + gbase[d] + lp)
+    __shared__ uint32_t gbase[NDIG];
     constexpr int TILE = NT * ITEMS;
     constexpr int W_ITEMS = TILE / (NT / 64), W_CHUNKS = W_ITEMS / 64;
     __shared__ K skey[TILE];
@@ -437,10 +439,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     // within a chunk of 64 from the lanes below with the same digit (one
     // ballot per digit bit); across chunks from a per-wave digit counter
     // that the chunk's lowest lane of each digit advances with an LDS
-    // atomic returning the count so far.  LDS operations of one wave
-    // execute in issue order, so the atomics of all chunks are issued back
-    // to back and still see the chunks in order; one wait, then each lane
-    // takes its digit's base from that lowest lane.
+    // atomic returning the count so far (the chunks' atomics run in chunk
+    // order); each lane then takes its digit's base from that lowest lane.
     uint32_t lead[W_CHUNKS];
     uint32_t nloc_kept;  // keys of this block that are written
 #pragma unroll
@@ -448,13 +448,21 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         size_t i = wbase + (size_t)c * 64 + lane;
         bool ok = i < n && (!DROP || key[c] != DROP_KEY);
         uint32_t d = ((key[c] - kb) >> shift) & (NDIG - 1);
-        uint64_t peers = __ballot(ok);
+        const uint64_t okm = __ballot(ok);
+        uint32_t plo = (uint32_t)okm, phi = (uint32_t)(okm >> 32);
 #pragma unroll
         for (int bb = 0; bb < BITS; ++bb) {
-            bool bit = (d >> bb) & 1u;
-            uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            // clear: ~0 where this lane's bit is 0, else 0.  The lanes that
+            // agree with it on the bit are ballot(bit) ^ clear, so each half
+            // of the update peers &= ballot(bit) ^ clear is one three-input
+            // bitwise operation (truth table a & (b ^ c) = 0x60)
+            uint32_t clear = (uint32_t)((int32_t)(~d << (31 - bb)) >> 31);
+            asm volatile("" : "+v"(clear));  // compare this value, not a re-derived shift
+            const uint64_t m = __ballot(clear == 0u);
+            plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)m, clear, (uint8_t)0x60);
+            phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(m >> 32), clear, (uint8_t)0x60);
         }
+        const uint64_t peers = (uint64_t)phi << 32 | plo;
         uint32_t rank = gs::lanes_below(peers);
         pos[c] = rank;
         lead[c] = ok ? (uint32_t)__builtin_ctzll(peers) : (uint32_t)lane;
@@ -468,19 +476,25 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     }
     __syncthreads();
     {
-        // per digit: prefix over waves, and the block's digit-major local start
+        // per digit: the counts over the waves, the block's digit-major
+        // local start, then each wave's staging base for the digit
         uint32_t d = threadIdx.x, off = 0;
         if (d < NDIG) {
 #pragma unroll
-            for (int i = 0; i < (NT / 64); ++i) {
-                uint32_t t = wcnt[i][d];
-                wcnt[i][d] = off;
-                off += t;
-            }
+            for (int i = 0; i < (NT / 64); ++i) off += wcnt[i][d];
         }
         uint32_t ex;
         nloc_kept = block_excl_scan<uint32_t>(off, ex, lds_scan);
-        if (d < NDIG) lstart[d] = ex;
+        if (d < NDIG) {
+            uint32_t run = ex;
+#pragma unroll
+            for (int i = 0; i < (NT / 64); ++i) {
+                const uint32_t t = wcnt[i][d];
+                wcnt[i][d] = run;
+                run += t;
+            }
+            gbase[d] -= ex;
+        }
     }
     __syncthreads();
     // stage in LDS in (digit, original order) order ...
@@ -489,7 +503,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
         size_t i = wbase + (size_t)c * 64 + lane;
         if (i < n && (!DROP || key[c] != DROP_KEY)) {
             uint32_t d = ((key[c] - kb) >> shift) & (NDIG - 1);
-            uint32_t lp = lstart[d] + wcnt[w][d] + pos[c];
+            uint32_t lp = wcnt[w][d] + pos[c];
             skey[lp] = (K)key[c];
             sval[lp] = val[c];
         }
@@ -497,12 +511,11 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     __syncthreads();
     // ... and write runs of equal digits to consecutive global addresses
     const uint32_t nloc = nloc_kept;
-    for (uint32_t lp = threadIdx.x; lp < nloc; lp += NT) {
-        uint32_t k = skey[lp];
-        uint32_t d = ((k - kb) >> shift) & (NDIG - 1);
-        uint32_t dst = sbase + gbase[d] + (lp - lstart[d]);
+    auto put = [&](uint32_t lp, uint32_t k, uint32_t v) {
+        const uint32_t d = ((k - kb) >> shift) & (NDIG - 1);
+        const uint32_t dst = sbase + gbase[d] + lp;
         if (!RANGES) kout[dst] = (K)k;
-        vout[dst] = sval[lp];
+        vout[dst] = v;
         if (RANGES) {
             // the key before in the block's staged order
             const uint32_t kp = lp > 0 ? skey[lp - 1] : ~0u;
@@ -512,7 +525,15 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
                 else if (kp != k) ranges[2 * k] = dst;
             }
         }
+    };
+    uint32_t lp = threadIdx.x;
+    for (; lp + NT < nloc; lp += 2 * NT) {
+        const uint32_t k0 = skey[lp], k1 = skey[lp + NT];
+        const uint32_t v0 = sval[lp], v1 = sval[lp + NT];
+        put(lp, k0, v0);
+        put(lp + NT, k1, v1);
     }
+    if (lp < nloc) put(lp, skey[lp], sval[lp]);
 }
 
 // Tile ends from the starts the tile sort's last pass recorded: the output
