@@ -290,19 +290,42 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
             "raster_ms": float(np.median([e[1].elapsed_time(e[2]) for e in evs[warmup:]]))}
         row["speedup_frame_fp16_precise_vs_fp32"] = (row["fp32"]["ms_per_frame"]
                                                      / row["fp16_g2l_split_precise"]["ms_per_frame"])
+        # the FP32 path on the same precise lists: both frames under one rule
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(warmup + steps)]
+        for e in evs:
+            e[0].record()
+            p = gs.preprocess(means, scales, quats, opac, sh, cam)
+            bsp(p["means2d"], p["radii"], p["depths"], p["conics"], p["log_opacities"])
+            e[1].record()
+            rz(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], "fp32",
+               tune=tune_obj["fp32"])
+            e[2].record()
+        torch.cuda.synchronize()
+        row["fp32_precise"] = {
+            "ms_per_frame": float(np.median([e[0].elapsed_time(e[2]) for e in evs[warmup:]])),
+            "raster_ms": float(np.median([e[1].elapsed_time(e[2]) for e in evs[warmup:]]))}
+        row["speedup_frame_fp16_vs_fp32_precise_rule"] = (row["fp32_precise"]["ms_per_frame"]
+                                                          / row["fp16_g2l_split_precise"]["ms_per_frame"])
         del bsp, probe_p
         rows.append(row)
         log(f"[bench] 4K pose {pose}: N={N} fp32 {row['fp32']['ms_per_frame']:.2f} ms, "
             f"fp16 {row['fp16_g2l_split']['ms_per_frame']:.2f} ms, bf16 {row['bf16_g2l_split']['ms_per_frame']:.2f} ms, "
-            f"fp16+precise {row['fp16_g2l_split_precise']['ms_per_frame']:.2f} ms (N={Np})")
+            f"fp16+precise {row['fp16_g2l_split_precise']['ms_per_frame']:.2f} ms, "
+            f"fp32+precise {row['fp32_precise']['ms_per_frame']:.2f} ms (N={Np})")
         del bs, probe, pre
     summ_precise = {"ms_per_frame_mean": float(np.mean([r["fp16_g2l_split_precise"]["ms_per_frame"]
-                                                        for r in rows]))}
+                                                        for r in rows])),
+                    "fp32_ms_per_frame_mean": float(np.mean([r["fp32_precise"]["ms_per_frame"]
+                                                             for r in rows]))}
+    summ_precise["speedup_frame_fp16_vs_fp32"] = (summ_precise["fp32_ms_per_frame_mean"]
+                                                  / summ_precise["ms_per_frame_mean"])
     summ = {prec: {"ms_per_frame_mean": float(np.mean([r[prec]["ms_per_frame"] for r in rows])),
                    "roofline_frac_mean": float(np.mean([r[prec]["roofline_frac"] for r in rows])),
                    "psnr_vs_fp32_min_db": float(np.min([r[prec]["psnr_vs_fp32_db"] for r in rows]))}
             for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split")}
     summ["fp16_g2l_split_precise"] = summ_precise
+    summ["speedup_frame_fp16_vs_fp32_3sigma"] = (summ["fp32"]["ms_per_frame_mean"]
+                                                 / summ["fp16_g2l_split"]["ms_per_frame_mean"])
     return {"workload": "fwd_4k_6M", "gaussians": P, "width": W, "height": H, "poses": rows,
             "raster_tune": tuned, "summary": summ}
 

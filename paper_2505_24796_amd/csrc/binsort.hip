@@ -1075,13 +1075,14 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t *a, uint32_t n, uint3
 // walked in row-major order; written from registers with one 16-byte store
 // per array (consecutive threads, consecutive 16-byte pieces).  With HIST,
 // each key's lowest digit (key & dmask) is also counted in hcount (LDS).
-template <bool MULTI, bool HIST, typename K>
+template <bool MULTI, bool HIST, typename K, int IT = EMIT_ITEMS>
 __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uint32_t *s_off,
                                            const uint2 *s_rect, const uint32_t *s_id, uint32_t m,
                                            const ViewRef &vt, K *__restrict__ tkey,
                                            uint32_t *__restrict__ tid, uint32_t dmask,
                                            uint32_t *hcount) {
-    uint32_t tk[EMIT_ITEMS], tg[EMIT_ITEMS];
+    static_assert(IT == 4 || IT == 8, "whole 16-byte stores");
+    uint32_t tk[IT], tg[IT];
     {
         uint32_t k = last_le(s_off, m, s0);
         const uint32_t l = s0 - s_off[k];
@@ -1092,7 +1093,7 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
         int v = vt.view_of<MULTI>(s_id[k]);
         uint32_t gid = s_id[k] - (uint32_t)v * vt.P;
 #pragma unroll
-        for (int i = 0; i < EMIT_ITEMS; ++i) {
+        for (int i = 0; i < IT; ++i) {
             const uint32_t tx = (r.x & 0xFFFFu) + col, ty = (r.x >> 16) + row;
             tk[i] = vt.tbase<MULTI>(v) + ty * vt.gx<MULTI>(v) + tx;
             tg[i] = gid;
@@ -1110,17 +1111,25 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
             }
         }
     }
-    const bool vec = s0 + EMIT_ITEMS <= oend && gs::aligned(tkey + s0, EMIT_ITEMS * sizeof(K)) &&
+    const bool vec = s0 + IT <= oend && gs::aligned(tkey + s0, IT * sizeof(K)) &&
                      gs::aligned(tid + s0, 16);
     if (vec) {
-        if constexpr (sizeof(K) == 4)
-            *(uint4 *)(tkey + s0) = make_uint4(tk[0], tk[1], tk[2], tk[3]);
-        else  // four 16-bit keys in one 8-byte store
+        if constexpr (sizeof(K) == 4) {
+#pragma unroll
+            for (int i = 0; i < IT; i += 4)
+                *(uint4 *)(tkey + s0 + i) = make_uint4(tk[i], tk[i + 1], tk[i + 2], tk[i + 3]);
+        } else if constexpr (IT == 4) {  // four 16-bit keys in one 8-byte store
             *(uint2 *)(tkey + s0) = make_uint2(tk[0] | tk[1] << 16, tk[2] | tk[3] << 16);
-        *(uint4 *)(tid + s0) = make_uint4(tg[0], tg[1], tg[2], tg[3]);
+        } else {  // eight in one 16-byte store
+            *(uint4 *)(tkey + s0) = make_uint4(tk[0] | tk[1] << 16, tk[2] | tk[3] << 16,
+                                               tk[4] | tk[5] << 16, tk[6] | tk[7] << 16);
+        }
+#pragma unroll
+        for (int i = 0; i < IT; i += 4)
+            *(uint4 *)(tid + s0 + i) = make_uint4(tg[i], tg[i + 1], tg[i + 2], tg[i + 3]);
     } else {
 #pragma unroll
-        for (int i = 0; i < EMIT_ITEMS; ++i) {
+        for (int i = 0; i < IT; ++i) {
             if (s0 + (uint32_t)i < oend) {
                 tkey[s0 + i] = (K)tk[i];
                 tid[s0 + i] = tg[i];
@@ -1129,7 +1138,7 @@ __device__ __forceinline__ void emit_slots(uint32_t s0, uint32_t oend, const uin
     }
     if (HIST) {
 #pragma unroll
-        for (int i = 0; i < EMIT_ITEMS; ++i)
+        for (int i = 0; i < IT; ++i)
             if (s0 + (uint32_t)i < oend) atomicAdd(&hcount[tk[i] & dmask], 1u);
     }
 }
@@ -1171,6 +1180,65 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(int P, const uint32_t *__
     const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT_ITEMS;
     if (s0 < oend)
         emit_slots<MULTI, HIST, K>(s0, oend, s_off, s_rect, s_id, m, vt, tkey, tid, dmask, hcount);
+    if (HIST) {
+        __syncthreads();
+        if (threadIdx.x <= dmask)  // one contiguous row of counts per window
+            hist2[(size_t)blockIdx.x * RADIX + threadIdx.x] = hcount[threadIdx.x];
+    }
+}
+
+// One view, 3-sigma rule: window blockIdx.x (EMIT_TILE slots) with 256
+// threads of 8 slots, so twice as many windows fit on a CU as with k_emit
+// (one window is a chain of dependent steps: staging loads, search, walk,
+// stores).  Up to EMIT1_CAP + 1 Gaussians are staged in LDS (16 KB); a
+// window with more (its Gaussians average under two slots) searches and
+// walks the global arrays instead.  HIST as for k_emit.
+constexpr int EMIT1_THREADS = 256;
+constexpr int EMIT1_ITEMS = EMIT_TILE / EMIT1_THREADS;
+constexpr uint32_t EMIT1_CAP = 1024;
+template <bool HIST, typename K>
+__global__ __launch_bounds__(EMIT1_THREADS) void k_emit1(int P, const uint32_t *__restrict__ order,
+                                                         const uint32_t *__restrict__ offs,
+                                                         const uint2 *__restrict__ rects_sorted,
+                                                         const uint32_t *__restrict__ win_start,
+                                                         uint32_t nwin, ViewRef vt,
+                                                         const uint32_t *__restrict__ n_splats,
+                                                         uint32_t cap, K *__restrict__ tkey,
+                                                         uint32_t *__restrict__ tid, uint32_t dmask,
+                                                         uint32_t *__restrict__ hist2) {
+    static_assert(EMIT1_THREADS >= RADIX, "one thread per digit count");
+    __shared__ uint32_t s_off[EMIT1_CAP + 1];
+    __shared__ uint2 s_rect[EMIT1_CAP + 1];
+    __shared__ uint32_t s_id[EMIT1_CAP + 1];
+    __shared__ uint32_t hcount[HIST ? RADIX : 1];
+    const uint32_t N = *n_splats;
+    const uint32_t o0 = blockIdx.x * (uint32_t)EMIT_TILE;
+    if (N > cap || o0 >= N || blockIdx.x + 1 >= nwin) return;  // block-uniform
+    const uint32_t j0 = win_start[blockIdx.x];
+    const uint32_t j1 = win_start[blockIdx.x + 1];
+    if (j0 >= (uint32_t)P || j1 >= (uint32_t)P || j1 < j0) return;  // cannot happen when the scan ran
+    // every instance in [j0, j1] owns a slot (one view)
+    const uint32_t m = j1 - j0 + 1u;
+    const bool staged = m <= EMIT1_CAP + 1u;
+    if (staged) {
+        for (uint32_t k = threadIdx.x; k < m; k += EMIT1_THREADS) {
+            s_off[k] = offs[j0 + k];
+            s_rect[k] = rects_sorted[j0 + k];
+            s_id[k] = order[j0 + k];
+        }
+    }
+    if (HIST && threadIdx.x <= dmask) hcount[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t oend = min(o0 + (uint32_t)EMIT_TILE, N);
+    const uint32_t s0 = o0 + (uint32_t)threadIdx.x * EMIT1_ITEMS;
+    if (s0 < oend) {
+        if (staged)
+            emit_slots<false, HIST, K, EMIT1_ITEMS>(s0, oend, s_off, s_rect, s_id, m, vt, tkey, tid,
+                                                    dmask, hcount);
+        else
+            emit_slots<false, HIST, K, EMIT1_ITEMS>(s0, oend, offs + j0, rects_sorted + j0,
+                                                    order + j0, m, vt, tkey, tid, dmask, hcount);
+    }
     if (HIST) {
         __syncthreads();
         if (threadIdx.x <= dmask)  // one contiguous row of counts per window
@@ -1650,13 +1718,24 @@ gs_status bin_sort_views(int nv, int32_t P, const int32_t *widths, const int32_t
                                    (const uint32_t *)n_vis, d_num_splats, capacity, tb.k[0],
                                    emit_ids);
             } else {
-                auto ke = emit_hist ? k_emit<false, true, K> : k_emit<false, false, K>;
-                if constexpr (sizeof(K) == 4)
-                    if (nv > 1) ke = k_emit<true, false, K>;
-                hipLaunchKernelGGL(ke, dim3(eblocks), dim3(EMIT_THREADS), 0, s, n, order, U(L.offs),
-                                   (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin, vt,
-                                   (const uint32_t *)n_vis, d_num_splats, capacity, tb.k[0],
-                                   emit_ids, (1u << w0) - 1u, U(L.tkey1));
+                bool done = false;
+                if constexpr (sizeof(K) == 4) {
+                    if (nv > 1) {
+                        hipLaunchKernelGGL((k_emit<true, false, K>), dim3(eblocks), dim3(EMIT_THREADS),
+                                           0, s, n, order, U(L.offs),
+                                           (const uint2 *)(ws + L.rects_sorted), U(L.win), L.nwin,
+                                           vt, (const uint32_t *)n_vis, d_num_splats, capacity,
+                                           tb.k[0], emit_ids, (1u << w0) - 1u, U(L.tkey1));
+                        done = true;
+                    }
+                }
+                if (!done) {
+                    auto ke = emit_hist ? k_emit1<true, K> : k_emit1<false, K>;
+                    hipLaunchKernelGGL(ke, dim3(eblocks), dim3(EMIT1_THREADS), 0, s, n, order,
+                                       U(L.offs), (const uint2 *)(ws + L.rects_sorted), U(L.win),
+                                       L.nwin, vt, d_num_splats, capacity, tb.k[0], emit_ids,
+                                       (1u << w0) - 1u, U(L.tkey1));
+                }
             }
         }
         if (tile_items((uint32_t)nv, capacity) == TILE_ITEMS_BIG)

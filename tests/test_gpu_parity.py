@@ -151,6 +151,41 @@ def test_bin_sort_first_pass_histogram_both_ways():
         assert np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids_o), cap
 
 
+def test_bin_sort_expansion_staged_and_unstaged_windows():
+    """The one-view expansion stages up to 1025 Gaussians of a 2048-slot
+    window in LDS and reads the global arrays for windows with more (their
+    Gaussians average under two splats).  Near tiny Gaussians (one or two
+    tiles each) before far large ones in depth order give windows of both
+    kinds; both must give the oracle's lists."""
+    W, H = 512, 512
+    tiny = scenegen.scene_2d(12000, W, H, 31, s_min=0.1, s_max=0.4)
+    big = scenegen.scene_2d(1500, W, H, 32, s_min=4.0, s_max=30.0)
+    m2 = np.concatenate([tiny.means2d, big.means2d])
+    cov = np.concatenate([tiny.cov2d, big.cov2d])
+    opac = np.concatenate([tiny.opacities, big.opacities])
+    depths = np.concatenate([1.0 + 9.0 * (tiny.depths - 1.0) / 99.0,
+                             50.0 + 50.0 * (big.depths - 1.0) / 99.0]).astype(np.float32)
+    P = len(depths)
+    pre = gs.preprocess_2d(dev(m2), dev(cov), dev(opac), W, H)
+    radii = host(pre["radii"])
+    ranges_o, ids_o = oracle.bin_splats(m2, radii, depths, W, H)
+    # Gaussians per 2048-slot window in the emission (depth) order
+    cnt = np.bincount(ids_o.astype(np.int64), minlength=P)
+    order = [g for g in np.lexsort((np.arange(P), depths)) if cnt[g] > 0]
+    ends = np.cumsum(cnt[order])
+    starts = ends - cnt[order]
+    nwin = (int(ends[-1]) + 2047) // 2048
+    per_win = [int(np.sum((starts < 2048 * (w + 1)) & (ends > 2048 * w))) for w in range(nwin)]
+    say(f"bin_sort staged/unstaged windows: N={len(ids_o)}, Gaussians per window "
+        f"{min(per_win)}..{max(per_win)}")
+    assert min(per_win) <= 1025 < max(per_win)
+    bs = gs.bin_sort(dev(m2), pre["radii"], dev(depths), W, H)
+    N = bs.n_splats()
+    assert N == len(ids_o)
+    assert np.array_equal(host(bs.ranges).astype(np.uint32), ranges_o)
+    assert np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids_o)
+
+
 # ---------------------------------------------------------------- raster FP32
 @pytest.mark.parametrize("prec", ["fp32", "fp32_earlycull"])
 @pytest.mark.parametrize("W,H,P,seed", [(256, 256, 2000, 1001), (250, 190, 3000, 7)])
