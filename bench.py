@@ -526,6 +526,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="fwd_1080p_1M")
     ap.add_argument("--precision", default="fp16_g2l_split")
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="frames in flight for the serving-throughput figure, each on its own "
+                         "stream with its own buffers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
@@ -619,46 +622,68 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration {nb} bytes x3")
 
-    def frame(prec, ev=None):
-        if ev is not None:
-            ev[0].record()
-        p = gs.preprocess(means, scales, quats, opac, sh, cam)
-        if ev is not None:
-            ev[1].record()
-        bs(p["means2d"], p["radii"], p["depths"])
-        if ev is not None:
-            ev[2].record()
-        rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec,
-           tune=tune_obj.get(prec))
-        if ev is not None:
-            ev[3].record()
+    # The step time is one frame after another on one stream.  Beside it, a
+    # serving figure: frames are independent of each other, so up to
+    # args.inflight of them can run at once, each on a stream of its own
+    # with its own lists and image; one frame's latency-bound preprocess and
+    # binning kernels then fill CUs that another frame's raster leaves idle.
+    nflight = max(1, args.inflight)
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(nflight - 1)]
+    sets = [(bs, rz)] + [(gs.BinSorter(P, capacity, W, H), gs.Rasterizer(W, H))
+                         for _ in range(nflight - 1)]
+
+    def frame(prec, k, ev=None, one_stream=False):
+        j = 0 if one_stream else k % nflight
+        b, r = sets[j]
+        with torch.cuda.stream(streams[j]):
+            if ev is not None:
+                ev[0].record()
+            p = gs.preprocess(means, scales, quats, opac, sh, cam)
+            if ev is not None:
+                ev[1].record()
+            b(p["means2d"], p["radii"], p["depths"])
+            if ev is not None:
+                ev[2].record()
+            r(b.ranges, b.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec,
+              tune=tune_obj.get(prec))
+            if ev is not None:
+                ev[3].record()
 
     def timed(prec):
-        # K frames back to back between two synchronisations (the step time;
-        # no events inside the frames, each of which costs the GPU a few
-        # microseconds), then K more with HIP events between the stages on
-        # the frame's stream (stage times, the raster's duration)
-        for _ in range(args.warmup):
-            frame(prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            frame(prec)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) * 1e3 / args.steps
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-        for k in range(args.steps):
-            frame(prec, evs[k])
-        torch.cuda.synchronize()
-        st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
-                        e[0].elapsed_time(e[3])] for e in evs])
-        return wall, np.median(st, axis=0), st.mean(axis=0), st
+        # per mode (frames in flight, one stream): K frames back to back
+        # between two synchronisations (the step time; no events inside the
+        # frames, each of which costs the GPU a few microseconds), then K
+        # more with HIP events between the stages on each frame's stream
+        # (stage times, the raster's duration)
+        res = {}
+        for one in (False, True):
+            for k in range(args.warmup):
+                frame(prec, k, one_stream=one)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                frame(prec, k, one_stream=one)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3 / args.steps
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+            for k in range(args.steps):
+                frame(prec, k, evs[k], one_stream=one)
+            torch.cuda.synchronize()
+            st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                            e[0].elapsed_time(e[3])] for e in evs])
+            res["one_stream" if one else "inflight"] = (wall, np.median(st, axis=0), st.mean(axis=0), st)
+        return res
 
-    log(f"[bench] timing {args.precision} ({args.warmup} warmup + {args.steps} steps)")
-    wall, med, mean, st_all = timed(args.precision)
+    log(f"[bench] timing {args.precision} ({args.warmup} warmup + {args.steps} steps, "
+        f"{nflight} frames in flight, then one stream)")
+    tm = timed(args.precision)
+    wall, med, mean, st_all = tm["one_stream"]
+    wall_f, _, mean_f, st_f = tm["inflight"]
     img = rz.rgb.clone()
     log(f"[bench] timing fp32 baseline")
-    wall32, med32, mean32, _ = timed("fp32")
+    tm32 = timed("fp32")
+    wall32, med32, mean32, _ = tm32["one_stream"]
+    wall32_f, _, mean32_f, _ = tm32["inflight"]
     torch.cuda.synchronize()
 
     # precision sweep (the paper's EarlyCull / precision ablations): raster
@@ -831,6 +856,15 @@ def main():
                       / (mean32[2] / 1e3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS},
         "speedup_frame_vs_fp32": wall32 / wall,
         "speedup_raster_vs_fp32": mean32[2] / mean[2],
+        "frames_in_flight": {
+            "frames": nflight,
+            "ms_per_frame": wall_f, "pairs_per_s": pairs / (wall_f / 1e3),
+            "fp32_ms_per_frame": wall32_f, "speedup_vs_fp32": wall32_f / wall_f,
+            "frame_latency_ms_p50": float(np.percentile(st_f[:, 3], 50)),
+            "stages_ms": {"preprocess": mean_f[0], "bin_sort": mean_f[1], "raster": mean_f[2]},
+            "note": "serving throughput: frames launched back to back over this many streams, "
+                    "each with its own lists and image; each stage's time overlaps the other "
+                    "frames' stages"},
         "psnr_vs_fp32_db": psnr,
         "raster_pairs_per_s": pairs / raster_s,
         "raster_tune": {k: v for k, v in tunes.items()},
