@@ -242,7 +242,7 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
                 r_t = gs.Rasterizer(W, H)
                 tuned[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
                                                    pre["conics"], pre["log_opacities"], pre["rgb"],
-                                                   prec, reps=3, warmup=1)["best"]
+                                                   prec, reps=3, warmup=1, ncontrib=False)["best"]
                 del r_t
             tune_obj = {k: gs.make_raster_tune(v["batch"], v["chunk_rows"]) for k, v in tuned.items()}
             log(f"[bench] 4K tuned shapes {tuned}")
@@ -253,7 +253,7 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
                 bs(p["means2d"], p["radii"], p["depths"])
                 ev[1].record()
                 rz(bs.ranges, bs.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec,
-                   tune=tune_obj[prec])
+                   tune=tune_obj[prec], ncontrib=False)
                 ev[2].record()
             evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(warmup + steps)]
             for e in evs:
@@ -282,7 +282,7 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
             bsp(p["means2d"], p["radii"], p["depths"], p["conics"], p["log_opacities"])
             e[1].record()
             rz(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], "fp16_g2l_split",
-               tune=tune_obj["fp16_g2l_split"])
+               tune=tune_obj["fp16_g2l_split"], ncontrib=False)
             e[2].record()
         torch.cuda.synchronize()
         row["fp16_g2l_split_precise"] = {
@@ -298,7 +298,7 @@ def large_scene(args, poses=range(10), steps=20, warmup=3):
             bsp(p["means2d"], p["radii"], p["depths"], p["conics"], p["log_opacities"])
             e[1].record()
             rz(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], "fp32",
-               tune=tune_obj["fp32"])
+               tune=tune_obj["fp32"], ncontrib=False)
             e[2].record()
         torch.cuda.synchronize()
         row["fp32_precise"] = {
@@ -607,7 +607,7 @@ def main():
         r_t = gs.Rasterizer(W, H)
         tunes[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
                                            pre["conics"], pre["log_opacities"], pre["rgb"], prec,
-                                           reps=5, warmup=2)
+                                           reps=5, warmup=2, ncontrib=False)
         log(f"[bench] tuned {prec}: {tunes[prec]['best']}")
         del r_t
     tune_obj = {k: gs.make_raster_tune(v["best"]["batch"], v["best"]["chunk_rows"])
@@ -645,7 +645,7 @@ def main():
             if ev is not None:
                 ev[2].record()
             r(b.ranges, b.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"], prec,
-              tune=tune_obj.get(prec))
+              tune=tune_obj.get(prec), ncontrib=False)
             if ev is not None:
                 ev[3].record()
 
@@ -694,12 +694,14 @@ def main():
         bs(p2["means2d"], p2["radii"], p2["depths"])
         for prec in gs.PRECISIONS:
             for _ in range(3):
-                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], p2["log_opacities"], p2["rgb"], prec)
+                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], p2["log_opacities"], p2["rgb"], prec,
+                   ncontrib=False)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ts = []
             for _ in range(10):
                 ev0.record()
-                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], p2["log_opacities"], p2["rgb"], prec)
+                rz(bs.ranges, bs.sorted_ids, p2["means2d"], p2["conics"], p2["log_opacities"], p2["rgb"], prec,
+                   ncontrib=False)
                 ev1.record()
                 torch.cuda.synchronize()
                 ts.append(ev0.elapsed_time(ev1))
@@ -728,7 +730,7 @@ def main():
             if ev is not None:
                 ev[2].record()
             rzp(bsp.ranges, bsp.sorted_ids, p["means2d"], p["conics"], p["log_opacities"], p["rgb"],
-                args.precision)
+                args.precision, ncontrib=False)
             if ev is not None:
                 ev[3].record()
 

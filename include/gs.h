@@ -273,7 +273,9 @@ gs_status gs_bin_sort_multiview(int32_t nviews, int32_t P, const int32_t *widths
  *   background  HOST pointer to 3 floats composited as C + T * bg (NULL = 0)
  *   out_rgb [3][H][W] planar colour; out_T [H][W] final transmittance;
  *   out_ncontrib [H][W] 1-based position in the tile list of the last
- *   composited splat (0 if none).
+ *   composited splat (0 if none); NULL = not written, and the kernels then
+ *   skip that bookkeeping (gs_rasterize_bwd needs it: pass it when the
+ *   frame will be differentiated).
  *   d_counters  NULL, or device uint64[4] that the call ADDS fragment counts
  *   to: {blended, culled, terminating, pairs = the three summed}; counting
  *   slows the kernel and is meant for diagnostics only.

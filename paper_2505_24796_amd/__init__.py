@@ -441,7 +441,10 @@ class Rasterizer:
         self.counters = torch.zeros(4, dtype=torch.int64, device=device)
 
     def __call__(self, ranges, sorted_ids, means2d, conics, log_opacities, rgb, precision="fp32",
-                 background=(0.0, 0.0, 0.0), count: bool = False, tune=None):
+                 background=(0.0, 0.0, 0.0), count: bool = False, tune=None,
+                 ncontrib: bool = True):
+        """ncontrib=False: n_contrib is not written (the kernels skip that
+        bookkeeping; the backward needs it)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         for n, t, dt in (("ranges", ranges, torch.int32), ("sorted_ids", sorted_ids, torch.int32),
                          ("means2d", means2d, torch.float32), ("conics", conics, torch.float32),
@@ -456,7 +459,7 @@ class Rasterizer:
             st = lib().gs_rasterize_fwd(self.width, self.height, _ptr(ranges), _ptr(sorted_ids),
                                         _ptr(means2d), _ptr(conics), _ptr(log_opacities), _ptr(rgb),
                                         bg, prec, _ptr(self.rgb), _ptr(self.T),
-                                        _ptr(self.n_contrib),
+                                        _ptr(self.n_contrib) if ncontrib else c_void_p(0),
                                         _ptr(self.counters) if count else c_void_p(0), _stream())
             _check("gs_rasterize_fwd", st)
         else:
@@ -464,7 +467,7 @@ class Rasterizer:
                                               _ptr(sorted_ids), _ptr(means2d), _ptr(conics),
                                               _ptr(log_opacities), _ptr(rgb), bg, prec,
                                               ctypes.byref(tune), _ptr(self.rgb), _ptr(self.T),
-                                              _ptr(self.n_contrib),
+                                              _ptr(self.n_contrib) if ncontrib else c_void_p(0),
                                               _ptr(self.counters) if count else c_void_p(0),
                                               _stream())
             _check("gs_rasterize_fwd_tuned", st)

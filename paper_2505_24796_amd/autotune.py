@@ -83,12 +83,13 @@ def tune_batched(renderer, space: dict | None = None, reps: int = 5, warmup: int
 
 def tune_raster(rasterizer: Rasterizer, ranges, sorted_ids, means2d, conics, log_opacities, rgb,
                 precision="fp16_g2l_split", space: dict | None = None, reps: int = 5,
-                warmup: int = 1, check: bool = True) -> dict:
+                warmup: int = 1, check: bool = True, ncontrib: bool = True) -> dict:
     """Times every launch shape of ``space`` for one-view rasterisation of
     the given lists and installs the fastest as ``rasterizer.tune``.  The
     FP32 kernels stage a fixed 256 splats, so only the chunk height is tried
     for them.  Returns {"best": {batch, chunk_rows, ms_median, ms_min},
-    "table": [...]}."""
+    "table": [...]}.  ncontrib as for Rasterizer: tune the launches that
+    write n_contrib, or those that skip it."""
     space = dict(RASTER_SPACE, **(space or {}))
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     batches = space["batch"] if prec >= PRECISIONS["fp16_global"] else (128,)
@@ -96,9 +97,10 @@ def tune_raster(rasterizer: Rasterizer, ranges, sorted_ids, means2d, conics, log
     for nb, cr in itertools.product(batches, space["chunk_rows"]):
         t = make_raster_tune(nb, cr)
         ts = time_ms(lambda: rasterizer(ranges, sorted_ids, means2d, conics, log_opacities, rgb,
-                                        precision, tune=t), reps, warmup)
+                                        precision, tune=t, ncontrib=ncontrib), reps, warmup)
         if check:
-            snap = (rasterizer.rgb.clone(), rasterizer.T.clone(), rasterizer.n_contrib.clone())
+            snap = (rasterizer.rgb.clone(), rasterizer.T.clone()) + (
+                (rasterizer.n_contrib.clone(),) if ncontrib else ())
             if ref is None:
                 ref = snap
             elif not all(torch.equal(x, y) for x, y in zip(ref, snap)):

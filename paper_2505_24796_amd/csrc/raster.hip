@@ -17,7 +17,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // Plain FP32 kernel
 // ---------------------------------------------------------------------------
-template <bool EARLY, bool COUNT>
+// Without NC the last composited position is not tracked (out_ncontrib NULL).
+template <bool EARLY, bool COUNT, bool NC = true>
 __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
     __shared__ float2 s_mu[BATCH];
     __shared__ float4 s_co[BATCH];  // s11, s12, s22, o (ln o with EARLY)
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
                     C1 = fmaf(col.y, w, C1);
                     C2 = fmaf(col.z, w, C2);
                     T = test;
-                    last = b0 - start + (uint32_t)j + 1u;
+                    if (NC) last = b0 - start + (uint32_t)j + 1u;
                     if (COUNT) ++nb;
                 }
             }
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
                 C1 = fmaf(col.y, w, C1);
                 C2 = fmaf(col.z, w, C2);
                 T = test;
-                last = b0 - start + (uint32_t)j + 1u;
+                if (NC) last = b0 - start + (uint32_t)j + 1u;
                 if (COUNT) ++nb;
             }
         }
@@ -125,13 +126,13 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
 // splats are gathered and staged per round (64, 128 or 256; the default
 // launch takes 128, the tuned one what an autotuner picked).
 constexpr int DEFAULT_NB = 128;
-template <int VAR, bool COUNT, int NB>
+template <int VAR, bool COUNT, int NB, bool NC = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_mfma(RasterArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR, NB>::BYTES];
     __shared__ TileShared sh;
     const int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy, a.chunk_rows);
     if (tile < 0) return;
-    raster_tile_mfma<VAR, COUNT, NB>(a, tile, stage, sh);
+    raster_tile_mfma<VAR, COUNT, NB, NC>(a, tile, stage, sh);
 }
 
 // Diagnostic: exponents of the first `count` splats of one tile.
@@ -178,18 +179,24 @@ __global__ __launch_bounds__(256) void k_beta_dump(RasterArgs a, int tile, int c
     }
 }
 
-// Counting launches (diagnostics) always take the default batch.
+// Counting launches (diagnostics) always take the default batch and track
+// the last composited position.
+template <int VAR, bool NC>
+void launch_mfma_nb(const RasterArgs &a, int blocks, int nb, hipStream_t s) {
+    switch (nb) {
+    case 64: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 64, NC>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 256, NC>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 128, NC>), dim3(blocks), dim3(256), 0, s, a); break;
+    }
+}
 template <int VAR>
 void launch_mfma(const RasterArgs &a, int blocks, bool count, int nb, hipStream_t s) {
-    if (count) {
+    if (count)
         hipLaunchKernelGGL((k_raster_mfma<VAR, true, DEFAULT_NB>), dim3(blocks), dim3(256), 0, s, a);
-        return;
-    }
-    switch (nb) {
-    case 64: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 64>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 256>), dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 128>), dim3(blocks), dim3(256), 0, s, a); break;
-    }
+    else if (a.out_nc)
+        launch_mfma_nb<VAR, true>(a, blocks, nb, s);
+    else
+        launch_mfma_nb<VAR, false>(a, blocks, nb, s);
 }
 
 }  // namespace
@@ -202,8 +209,9 @@ extern "C" gs_status gs_rasterize_fwd_tuned(int32_t width, int32_t height,
                                             const gs_raster_tune *tune, float *out_rgb,
                                             float *out_T, uint32_t *out_ncontrib,
                                             uint64_t *d_counters, void *stream) {
-    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, log_opacities, rgb, out_rgb, out_T, out_ncontrib};
-    if (!valid_inputs(width, height, ptrs, 9) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
+    const void *ptrs[] = {tile_ranges, sorted_ids, means2d, conics, log_opacities, rgb, out_rgb, out_T};
+    if (!valid_inputs(width, height, ptrs, 8) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
+    if (out_ncontrib && !gs::aligned(out_ncontrib, 4)) return GS_ERR_INVALID_ARG;
     if (d_counters && !gs::aligned(d_counters, 8)) return GS_ERR_INVALID_ARG;
     if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
     const int nb = tune ? tune->batch : DEFAULT_NB;
@@ -234,11 +242,13 @@ extern "C" gs_status gs_rasterize_fwd_tuned(int32_t width, int32_t height,
     switch (precision) {
     case GS_PREC_FP32:
         if (cnt) hipLaunchKernelGGL((k_raster_fp32<false, true>), dim3(blocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_raster_fp32<false, false>), dim3(blocks), dim3(256), 0, s, a);
+        else if (out_ncontrib) hipLaunchKernelGGL((k_raster_fp32<false, false>), dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_raster_fp32<false, false, false>), dim3(blocks), dim3(256), 0, s, a);
         break;
     case GS_PREC_FP32_EARLYCULL:
         if (cnt) hipLaunchKernelGGL((k_raster_fp32<true, true>), dim3(blocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_raster_fp32<true, false>), dim3(blocks), dim3(256), 0, s, a);
+        else if (out_ncontrib) hipLaunchKernelGGL((k_raster_fp32<true, false>), dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_raster_fp32<true, false, false>), dim3(blocks), dim3(256), 0, s, a);
         break;
     case GS_PREC_FP16_GLOBAL: launch_mfma<VAR_F16_GLOBAL>(a, blocks, cnt, nb, s); break;
     case GS_PREC_FP16_G2L: launch_mfma<VAR_F16_G2L>(a, blocks, cnt, nb, s); break;

@@ -66,7 +66,7 @@ __device__ __forceinline__ void write_pixel(const RasterArgs &a, int px, int py,
         a.out_rgb[hw + pi] = fmaf(T, a.bg1, C1);
         a.out_rgb[2 * hw + pi] = fmaf(T, a.bg2, C2);
         a.out_T[pi] = T;
-        a.out_nc[pi] = last;
+        if (a.out_nc) a.out_nc[pi] = last;
     }
 }
 

@@ -32,7 +32,10 @@ struct TileShared {
 // NB splats (64, 128 or 256) are gathered and staged per round; every thread
 // of the workgroup must call this with the same arguments.  Touches only
 // `stage` and `sh` in LDS; the caller separates two calls with a barrier.
-template <int VAR, bool COUNT, int NB>
+// Without NC the position of each pixel's last composited splat is not
+// tracked (one vector instruction less per visited splat; for callers that
+// do not ask for it).
+template <int VAR, bool COUNT, int NB, bool NC = true>
 __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, uint8_t *stage,
                                                  TileShared &sh) {
     static_assert(NB == 64 || NB == 128 || NB == 256, "batch of 64, 128 or 256 splats");
@@ -141,7 +144,7 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
                     C1 = fmaf(col.y, w, C1);
                     C2 = fmaf(col.z, w, C2);
                     T = Tn;
-                    last = blend ? __float_as_uint(col.w) : last;
+                    if (NC) last = blend ? __float_as_uint(col.w) : last;
                     thr = stop ? __builtin_inff() : thr;
                     if (COUNT) {
                         nb += blend ? 1u : 0u;

@@ -442,3 +442,29 @@ def test_tuned_launch_shapes_bit_identical():
         rz(bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"], prec)
         got = (host(rz.rgb), host(rz.T), host(rz.n_contrib))
         assert all(np.array_equal(a, b) for a, b in zip(ref, got)), prec
+
+
+def test_forward_without_ncontrib_bit_identical():
+    """gs_rasterize_fwd with out_ncontrib NULL runs kernel instances that do
+    not track the last composited splat: colour and transmittance are bit
+    for bit those of the full call, for every precision and launch shape,
+    and the n_contrib buffer is left alone."""
+    W, H = 250, 190
+    sc, d = scene2d_inputs(W, H, 3000, 7)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
+    bs = gs.bin_sort(d["means2d"], pre["radii"], d["depths"], W, H)
+    for prec in gs.PRECISIONS:
+        for tune in (None, gs.make_raster_tune(64, 1), gs.make_raster_tune(256, 2)):
+            rz = gs.Rasterizer(W, H)
+            rz(bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"],
+               prec, tune=tune)
+            ref = (host(rz.rgb), host(rz.T))
+            rz.n_contrib.fill_(-7)
+            rz.rgb.fill_(float("nan"))
+            rz.T.fill_(float("nan"))
+            rz(bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"],
+               prec, tune=tune, ncontrib=False)
+            assert np.array_equal(host(rz.rgb), ref[0]), (prec, tune)
+            assert np.array_equal(host(rz.T), ref[1]), (prec, tune)
+            assert int(host(rz.n_contrib).max()) == -7 and int(host(rz.n_contrib).min()) == -7
+        say(f"forward without n_contrib: {prec} bit-identical")
