@@ -87,7 +87,8 @@ typedef struct {
 /* Returns a static, human-readable name for a gs_status value. */
 const char *gs_status_string(int status);
 
-/* Library ABI version (major * 100 + minor); 200 = opacity as ln o. */
+/* Library ABI version (major * 100 + minor); 200 = opacity as ln o; 201 =
+ * gs_rasterize_fwd(_tuned) also accepts out_ncontrib = NULL. */
 int gs_version(void);
 
 /*

@@ -313,4 +313,4 @@ extern "C" const char *gs_status_string(int status) {
     }
 }
 
-extern "C" int gs_version(void) { return 200; }
+extern "C" int gs_version(void) { return 201; }
