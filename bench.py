@@ -592,6 +592,7 @@ def main():
     torch.cuda.synchronize()
     cnt = rz.counters.cpu().numpy()
     pairs, survivors = int(cnt[3]), int(cnt[0] + cnt[2])
+    drawn = int((pre["radii"] > 0).sum())  # Gaussians whose SH the preprocess reads
     ref_img = rz.rgb.clone()
     log(f"[bench] pairs {pairs} (blend {cnt[0]} cull {cnt[1]} term {cnt[2]}), gross {256 * N}")
 
@@ -808,12 +809,13 @@ def main():
                                          "unit": "TFLOP/s", "frac": mfma_exec / FP16_MFMA_PEAK_TFLOPS,
                                          "source": "SQ_INSTS_MFMA x 32768 flop (counters)"}
         other["raster_valu_issue_frac"] = counters.get("valu_issue_utilisation")
-    # preprocess: 240 B read + 48 B written per Gaussian; bin/sort: per
+    # preprocess: 44 B read + 48 B written per Gaussian, and the 192 B of SH
+    # coefficients of each drawn one; bin/sort: per
     # Gaussian 4 x 16 B (depth passes) + 40 B, per splat 30 B with 16-bit
     # tile keys (6 written by the expansion, 12 moved by the first tile
     # pass, 2 read by the second pass's histogram, 6 read and 4 written, the
     # ids, by its scatter)
-    pre_bytes = 288.0 * P
+    pre_bytes = 92.0 * P + 192.0 * drawn
     bin_bytes = P * (4 * 16 + 40) + 30.0 * N
     other["preprocess_hbm"] = {"achieved": pre_bytes / (mean[0] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": pre_bytes / (mean[0] / 1e3) / 1e9 / HBM_PEAK_GBS}
