@@ -151,6 +151,23 @@ def test_bin_sort_first_pass_histogram_both_ways():
         assert np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids_o), cap
 
 
+@pytest.mark.parametrize("W", [4096, 4160])
+def test_bin_sort_tile_key_width(W):
+    """A one-view call carries tile keys as 16-bit words up to 65536 tiles
+    (4096 x 4096 is exactly 65536, the largest key 65535) and as 32-bit
+    words beyond (4160 x 4160: 67600 tiles); both give the oracle's lists."""
+    sc, d = scene2d_inputs(W, W, 20000, 41, s_min=0.5, s_max=6.0)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, W)
+    radii = host(pre["radii"])
+    ranges_o, ids_o = oracle.bin_splats(sc.means2d, radii, sc.depths, W, W)
+    say(f"bin_sort {W}x{W}: {(W // 16) ** 2} tiles, N={len(ids_o)}")
+    bs = gs.bin_sort(d["means2d"], pre["radii"], d["depths"], W, W)
+    N = bs.n_splats()
+    assert N == len(ids_o)
+    assert np.array_equal(host(bs.ranges).astype(np.uint32), ranges_o)
+    assert np.array_equal(host(bs.sorted_ids)[:N].astype(np.uint32), ids_o)
+
+
 def test_bin_sort_expansion_staged_and_unstaged_windows():
     """The one-view expansion stages up to 1025 Gaussians of a 2048-slot
     window in LDS and reads the global arrays for windows with more (their
