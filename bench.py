@@ -709,6 +709,17 @@ def main():
             m = float(torch.mean((rz.rgb - ref_img) ** 2))
             sweep[prec] = {"raster_ms": float(np.median(ts)),
                            "psnr_vs_fp32_db": 10 * np.log10(1.0 / m) if m > 0 else float("inf")}
+        # the paper's EarlyCull x Frag2Mat ablation (Sec. 5.3, Table 5) on
+        # these lists: neither, EarlyCull only (FP32 path with the cull on
+        # beta before exp), Frag2Mat with G2L only (FP16 split, every splat
+        # visited), both (the FP16 split as benched)
+        cells = {"neither": "fp32", "earlycull": "fp32_earlycull",
+                 "frag2mat_g2l": "fp16_g2l_split_nocull", "both": "fp16_g2l_split"}
+        if all(v in sweep for v in cells.values()):
+            t0 = sweep["fp32"]["raster_ms"]
+            sweep["ablation_earlycull_x_frag2mat"] = {
+                k: {"precision": v, "raster_ms": sweep[v]["raster_ms"],
+                    "speedup_vs_neither": t0 / sweep[v]["raster_ms"]} for k, v in cells.items()}
         log(f"[bench] sweep {sweep}")
     # the same frame with precise Gaussian-tile intersection in the binning
     # (fewer splats; same image up to near-threshold fragments)

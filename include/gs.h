@@ -63,14 +63,22 @@ typedef enum {
  *   FP16_G2L_SPLIT  as FP16_G2L, with each coefficient split into FP16 high
  *                   and low parts in the spare K slots (K = 16).
  *   BF16_G2L_SPLIT  BF16 with a three-way high/mid/low split (K = 24 of 32).
- * All matrix-core variants accumulate in FP32 and apply EarlyCull. */
+ *   FP16_G2L_SPLIT_NOCULL  ablation only (Sec. 5.3, Table 5: Frag2Mat with
+ *                   G2L, EarlyCull off): FP16_G2L_SPLIT's exponents, but
+ *                   every listed splat is staged (no per-tile cull) and the
+ *                   exp and blend run for every one of them.  The image is
+ *                   that of FP16_G2L_SPLIT's counting launch (d_counters set),
+ *                   which also keeps every splat.  gs_rasterize_fwd(_tuned)
+ *                   only; the backward and the batched rasteriser reject it.
+ * All other matrix-core variants accumulate in FP32 and apply EarlyCull. */
 typedef enum {
     GS_PREC_FP32 = 0,
     GS_PREC_FP32_EARLYCULL = 1,
     GS_PREC_FP16_GLOBAL = 2,
     GS_PREC_FP16_G2L = 3,
     GS_PREC_FP16_G2L_SPLIT = 4,
-    GS_PREC_BF16_G2L_SPLIT = 5
+    GS_PREC_BF16_G2L_SPLIT = 5,
+    GS_PREC_FP16_G2L_SPLIT_NOCULL = 6
 } gs_precision;
 
 /* Pinhole camera (OpenCV axes: x right, y down, z forward). */
@@ -88,7 +96,8 @@ typedef struct {
 const char *gs_status_string(int status);
 
 /* Library ABI version (major * 100 + minor); 200 = opacity as ln o; 201 =
- * gs_rasterize_fwd(_tuned) also accepts out_ncontrib = NULL. */
+ * gs_rasterize_fwd(_tuned) also accepts out_ncontrib = NULL; 202 = the
+ * GS_PREC_FP16_G2L_SPLIT_NOCULL ablation variant. */
 int gs_version(void);
 
 /*

@@ -39,6 +39,8 @@ PRECISIONS = {
     "fp16_g2l": 3,
     "fp16_g2l_split": 4,
     "bf16_g2l_split": 5,
+    # ablation only (one-view forward): the FP16 split without EarlyCull
+    "fp16_g2l_split_nocull": 6,
 }
 
 STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARG", 2: "GS_ERR_UNSUPPORTED", 3: "GS_ERR_HIP",

@@ -126,13 +126,13 @@ __global__ __launch_bounds__(256) void k_raster_fp32(RasterArgs a) {
 // splats are gathered and staged per round (64, 128 or 256; the default
 // launch takes 128, the tuned one what an autotuner picked).
 constexpr int DEFAULT_NB = 128;
-template <int VAR, bool COUNT, int NB, bool NC = true>
+template <int VAR, bool COUNT, int NB, bool NC = true, bool CULL = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_raster_mfma(RasterArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[Stage<VAR, NB>::BYTES];
     __shared__ TileShared sh;
     const int tile = gs::xcd_tile(blockIdx.x, a.gx, a.gy, a.chunk_rows);
     if (tile < 0) return;
-    raster_tile_mfma<VAR, COUNT, NB, NC>(a, tile, stage, sh);
+    raster_tile_mfma<VAR, COUNT, NB, NC, CULL>(a, tile, stage, sh);
 }
 
 // Diagnostic: exponents of the first `count` splats of one tile.
@@ -180,23 +180,24 @@ __global__ __launch_bounds__(256) void k_beta_dump(RasterArgs a, int tile, int c
 }
 
 // Counting launches (diagnostics) always take the default batch and track
-// the last composited position.
-template <int VAR, bool NC>
+// the last composited position; they already stage and visit every listed
+// splat (to count its fragments), so CULL does not apply to them.
+template <int VAR, bool NC, bool CULL>
 void launch_mfma_nb(const RasterArgs &a, int blocks, int nb, hipStream_t s) {
     switch (nb) {
-    case 64: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 64, NC>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 256, NC>), dim3(blocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 128, NC>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 64, NC, CULL>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 256, NC, CULL>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_raster_mfma<VAR, false, 128, NC, CULL>), dim3(blocks), dim3(256), 0, s, a); break;
     }
 }
-template <int VAR>
+template <int VAR, bool CULL = true>
 void launch_mfma(const RasterArgs &a, int blocks, bool count, int nb, hipStream_t s) {
     if (count)
         hipLaunchKernelGGL((k_raster_mfma<VAR, true, DEFAULT_NB>), dim3(blocks), dim3(256), 0, s, a);
     else if (a.out_nc)
-        launch_mfma_nb<VAR, true>(a, blocks, nb, s);
+        launch_mfma_nb<VAR, true, CULL>(a, blocks, nb, s);
     else
-        launch_mfma_nb<VAR, false>(a, blocks, nb, s);
+        launch_mfma_nb<VAR, false, CULL>(a, blocks, nb, s);
 }
 
 }  // namespace
@@ -213,7 +214,7 @@ extern "C" gs_status gs_rasterize_fwd_tuned(int32_t width, int32_t height,
     if (!valid_inputs(width, height, ptrs, 8) || !gs::aligned(means2d, 8)) return GS_ERR_INVALID_ARG;
     if (out_ncontrib && !gs::aligned(out_ncontrib, 4)) return GS_ERR_INVALID_ARG;
     if (d_counters && !gs::aligned(d_counters, 8)) return GS_ERR_INVALID_ARG;
-    if (precision < GS_PREC_FP32 || precision > GS_PREC_BF16_G2L_SPLIT) return GS_ERR_INVALID_ARG;
+    if (precision < GS_PREC_FP32 || precision > GS_PREC_FP16_G2L_SPLIT_NOCULL) return GS_ERR_INVALID_ARG;
     const int nb = tune ? tune->batch : DEFAULT_NB;
     const int rows = tune ? tune->chunk_rows : 2;
     if (!(nb == 64 || nb == 128 || nb == 256) || !(rows == 1 || rows == 2)) return GS_ERR_INVALID_ARG;
@@ -254,6 +255,7 @@ extern "C" gs_status gs_rasterize_fwd_tuned(int32_t width, int32_t height,
     case GS_PREC_FP16_G2L: launch_mfma<VAR_F16_G2L>(a, blocks, cnt, nb, s); break;
     case GS_PREC_FP16_G2L_SPLIT: launch_mfma<VAR_F16_SPLIT>(a, blocks, cnt, nb, s); break;
     case GS_PREC_BF16_G2L_SPLIT: launch_mfma<VAR_BF16_SPLIT>(a, blocks, cnt, nb, s); break;
+    case GS_PREC_FP16_G2L_SPLIT_NOCULL: launch_mfma<VAR_F16_SPLIT, false>(a, blocks, cnt, nb, s); break;
     }
     return gs::launch_status();
 }
@@ -313,4 +315,4 @@ extern "C" const char *gs_status_string(int status) {
     }
 }
 
-extern "C" int gs_version(void) { return 201; }
+extern "C" int gs_version(void) { return 202; }

@@ -34,8 +34,11 @@ struct TileShared {
 // `stage` and `sh` in LDS; the caller separates two calls with a barrier.
 // Without NC the position of each pixel's last composited splat is not
 // tracked (one vector instruction less per visited splat; for callers that
-// do not ask for it).
-template <int VAR, bool COUNT, int NB, bool NC = true>
+// do not ask for it).  Without CULL (the EarlyCull-off cell of the paper's
+// EarlyCull x Frag2Mat ablation, Sec. 5.3, Table 5) every listed splat is
+// staged and visited: no per-tile cull, and the exp and blend run for every
+// splat; the per-lane threshold still decides what each pixel composites.
+template <int VAR, bool COUNT, int NB, bool NC = true, bool CULL = true>
 __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, uint8_t *stage,
                                                  TileShared &sh) {
     static_assert(NB == 64 || NB == 128 || NB == 256, "batch of 64, 128 or 256 splats");
@@ -78,7 +81,7 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
         // 1. which splats of the batch can contribute to this tile at all
         // (counting mode keeps every splat so culled fragments are counted
         // per pixel in list order)
-        const bool keep = COUNT ? cur.valid : tile_alive(cur, bx0, by0);
+        const bool keep = COUNT || !CULL ? cur.valid : tile_alive(cur, bx0, by0);
         const uint64_t kmask = __ballot(keep);
         const bool wave_done = __ballot(thr != __builtin_inff()) == 0ull;
         if (lane == 0) {
@@ -128,7 +131,7 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
                 const float beta = g < 16 ? lo[g] : hi[g - 16];
                 const bool sv = beta >= thr;
                 if (COUNT) ncl += (thr != __builtin_inff() && !sv) ? 1u : 0u;
-                if (COUNT || __ballot(sv) != 0ull) {
+                if (COUNT || !CULL || __ballot(sv) != 0ull) {
                     const float4 col = cols[g];
                     const float alpha = fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(beta));
                     const float test = fmaf(-alpha, T, T);

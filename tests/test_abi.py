@@ -54,7 +54,7 @@ def test_status_strings(gslib):
     assert gslib.gs_status_string(0) == b"GS_OK"
     assert gslib.gs_status_string(4) == b"GS_ERR_CAPACITY"
     assert gslib.gs_status_string(99) == b"GS_ERR_UNKNOWN"
-    assert gslib.gs_version() == 201  # ln o across the boundary; out_ncontrib may be NULL
+    assert gslib.gs_version() == 202  # ln o across the boundary; out_ncontrib may be NULL; NOCULL ablation
 
 
 def test_invalid_arguments_rejected_on_host(gslib):
@@ -92,6 +92,11 @@ def test_invalid_arguments_rejected_on_host(gslib):
     bg = (ctypes.c_float * 3)(0, 0, 0)
     args = [64, 64, v(16), v(16), v(16), v(16), v(16), v(16), bg]
     assert gslib.gs_rasterize_fwd(*args, 9, v(16), v(16), v(16), v(0), v(0)) == 1
+    assert gslib.gs_rasterize_fwd(*args, 7, v(16), v(16), v(16), v(0), v(0)) == 1
+    # the EarlyCull-off ablation variant is forward-only
+    assert gslib.gs_rasterize_bwd(*args, 6, *([v(16)] * 7), v(0)) == 1
+    assert gslib.gs_rasterize_beta(64, 64, 0, v(16), v(16), v(16), v(16), v(16), 6, 32, v(16),
+                                   v(0)) == 1
     # null output image
     assert gslib.gs_rasterize_fwd(*args, 0, v(0), v(16), v(16), v(0), v(0)) == 1
     # tuned launch: batch must be 64/128/256, chunk rows 1 or 2
@@ -133,6 +138,7 @@ def test_batched_and_precise_arguments_rejected_on_host(gslib):
     assert gslib.gs_rasterize_fwd_batched(0, v(256), 4, t, v(256), 1024, v(0), v(0)) == 1
     assert gslib.gs_rasterize_fwd_batched(1, v(256), 4, t, v(256), 4, v(0), v(0)) == 4
     assert gslib.gs_rasterize_fwd_batched(1, v(256), 1, t, v(256), 1024, v(0), v(0)) == 2
+    assert gslib.gs_rasterize_fwd_batched(1, v(256), 6, t, v(256), 1024, v(0), v(0)) == 1
     assert gslib.gs_rasterize_fwd_batched(1, v(256), 4, gs.make_tune(96, 5, 1), v(256), 1024,
                                           v(0), v(0)) == 1
     assert gslib.gs_rasterize_fwd_batched(1, v(256), 4, gs.make_tune(64, 0, 1), v(256), 1024,

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():  # collected on CPU machines too, but never ru
 import paper_2505_24796_amd as gs  # noqa: E402
 from gpu_helpers import dev, fp32_check, host, psnr, quality  # noqa: E402
 
-MFMA_PRECS = ["fp16_g2l", "fp16_g2l_split", "bf16_g2l_split"]
+MFMA_PRECS = ["fp16_g2l", "fp16_g2l_split", "bf16_g2l_split", "fp16_g2l_split_nocull"]
 
 
 def say(*a):
@@ -274,6 +274,28 @@ def check_mfma_quality(prec, q, img, W, H, ranges, ids, means2d, conics, opac, r
         assert qe["psnr"] >= 60.0 and qe["frac_2_255"] >= 0.999
     else:
         assert q["frac_2_255"] >= 0.999
+
+
+def test_raster_without_earlycull_equals_counting_launch():
+    """The EarlyCull-off ablation variant stages and visits every listed
+    splat, as the FP16 split's counting launch does to count fragments, so
+    the two composite exactly the same fragments: colour, transmittance and
+    n_contrib bit for bit, at every launch shape."""
+    W, H = 250, 190
+    sc, d = scene2d_inputs(W, H, 3000, 7)
+    pre = gs.preprocess_2d(d["means2d"], d["cov2d"], d["opac"], W, H)
+    bs = gs.bin_sort(d["means2d"], pre["radii"], d["depths"], W, H)
+    ref = gs.rasterize_fwd(W, H, bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"],
+                           pre["log_opacities"], d["rgb"], "fp16_g2l_split", count=True)
+    want = (host(ref.rgb), host(ref.T), host(ref.n_contrib))
+    for tune in (None, gs.make_raster_tune(64, 1), gs.make_raster_tune(256, 2)):
+        rz = gs.Rasterizer(W, H)
+        rz(bs.ranges, bs.sorted_ids, d["means2d"], pre["conics"], pre["log_opacities"], d["rgb"],
+           "fp16_g2l_split_nocull", tune=tune)
+        got = (host(rz.rgb), host(rz.T), host(rz.n_contrib))
+        for k in range(3):
+            assert np.array_equal(got[k], want[k]), (tune, k)
+    say("fp16_g2l_split_nocull equals the counting launch")
 
 
 def test_raster_fp16_global_is_negative_control():
