@@ -309,7 +309,8 @@ __device__ __forceinline__ void stage_splat(uint8_t *stage, int j, const SplatRe
 // Can the splat reach the 1/255 threshold anywhere in the pixel box
 // [x0, x0 + 15] x [y0, y0 + 15]?  Exact minimum of the convex form
 // q/2 = 1/2 d^T S d over the box (zero if the centre is inside, otherwise the
-// smallest of the four edge minima, each a clamped 1D minimisation), compared
+// smaller of the minima along the vertical and the horizontal edge on the
+// centre's side, each a clamped 1D minimisation), compared
 // with ln o + ln 255 with a margin that covers FP32 rounding of the bound.
 // A splat that fails the test is culled at every pixel of the tile, so
 // dropping it changes no output of the exact computation.
@@ -326,14 +327,21 @@ __device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y
         // is evaluated, and at the minimum the form is flat, so its 1-ulp
         // error moves f by far less than the margin below.
         const float nb_c = -b * __builtin_amdgcn_rcpf(c), nb_a = -b * __builtin_amdgcn_rcpf(a);
+        // The form is convex with its minimum at the mean, outside the box,
+        // so its minimum over the box lies on an edge whose half-plane the
+        // mean violates: from a boundary point on no such edge, a step
+        // toward the mean stays in the box and lowers the form.  One
+        // vertical and one horizontal edge, each the one on the mean's side,
+        // hold every such edge (an edge the mean does not violate only adds
+        // a value above the minimum).
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 2; ++e) {
             float dx, dy;
-            if (e < 2) {
-                dx = (e == 0 ? x0 : x1) - mx;
+            if (e == 0) {
+                dx = (mx < x0 ? x0 : x1) - mx;
                 dy = fminf(fmaxf(nb_c * dx, y0 - my), y1 - my);
             } else {
-                dy = (e == 2 ? y0 : y1) - my;
+                dy = (my < y0 ? y0 : y1) - my;
                 dx = fminf(fmaxf(nb_a * dy, x0 - mx), x1 - mx);
             }
             float t0 = a * dx * dx, t1 = 2.0f * b * dx * dy, t2 = c * dy * dy;
