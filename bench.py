@@ -55,19 +55,25 @@ RASTER_SOURCES = ["paper_2505_24796_amd/csrc/raster.hip", "paper_2505_24796_amd/
                   "paper_2505_24796_amd/csrc/raster_common.h", "paper_2505_24796_amd/csrc/common.h"]
 
 
-def read_traffic(precision: str, shape=None):
-    """HBM traffic of the raster kernel measured by rocprofv3 counters
-    (profiles/raster_traffic_<precision>.json), only if the kernel source is
-    unchanged since the counters were taken and the launch shape is the one
-    they were taken at."""
-    p = os.path.join(ROOT, "profiles", f"raster_traffic_fwd_1080p_1M_{precision}.json")
+def traffic_path(precision: str, shape: dict) -> str:
+    """Counter record of one raster launch shape at 1080p/1M."""
+    return os.path.join(ROOT, "profiles", f"raster_traffic_fwd_1080p_1M_{precision}"
+                                          f"_b{shape['batch']}_c{shape['chunk_rows']}.json")
+
+
+def read_traffic(precision: str, shape: dict):
+    """HBM traffic of the raster kernel measured by rocprofv3 counters at the
+    launch shape the autotuner picked (one record per shape under
+    profiles/), only if the kernel source is unchanged since the counters
+    were taken."""
+    p = traffic_path(precision, shape)
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash(RASTER_SOURCES):
         return None
-    if shape is not None and rec.get("launch_shape") != shape:
+    if rec.get("launch_shape") != shape:
         return None
     return rec
 
