@@ -203,7 +203,7 @@ def train_step(args):
                       "opacity logits + N(0, 0.5), SH + N(0, 0.05)"}
 
 
-def large_scene(args, poses=range(10), steps=20, warmup=3):
+def large_scene(args, poses=range(10), steps=50, warmup=5):
     """6M Gaussians at 3840x2160, the 10 orbit poses: per pose and precision
     (FP32 path, FP16 and BF16 hi/lo split) the frame time, the raster time,
     the raster's vector-ALU roofline fraction (as the headline's) and, for
@@ -528,8 +528,8 @@ def binsort_only(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="fwd_1080p_1M")
     ap.add_argument("--precision", default="fp16_g2l_split")
     ap.add_argument("--inflight", type=int, default=3,
