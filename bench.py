@@ -244,11 +244,21 @@ def large_scene(args, poses=range(10), steps=50, warmup=5):
             # launch shapes tuned on the first pose, kept for the others
             from paper_2505_24796_amd import autotune
             tuned = {}
+
+            def frame_prefix():
+                # the frame's preprocess and bin/sort ahead of each timed
+                # raster call (the same values into the same buffers)
+                p2 = gs.preprocess(means, scales, quats, opac, sh, cam)
+                for k in ("means2d", "radii", "depths", "conics", "log_opacities", "rgb"):
+                    pre[k].copy_(p2[k])
+                bs(pre["means2d"], pre["radii"], pre["depths"])
+
             for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split"):
                 r_t = gs.Rasterizer(W, H)
                 tuned[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
                                                    pre["conics"], pre["log_opacities"], pre["rgb"],
-                                                   prec, reps=3, warmup=1, ncontrib=False)["best"]
+                                                   prec, reps=8, warmup=2, ncontrib=False,
+                                                   before=frame_prefix)["best"]
                 del r_t
             tune_obj = {k: gs.make_raster_tune(v["batch"], v["chunk_rows"]) for k, v in tuned.items()}
             log(f"[bench] 4K tuned shapes {tuned}")
@@ -610,11 +620,20 @@ def main():
         nb_, cr_ = (int(x) for x in args.raster_shape.split(","))
         tunes[args.precision] = {"best": {"batch": nb_, "chunk_rows": cr_}, "table": [],
                                  "given": True}
+    def frame_prefix():
+        # the frame's preprocess and bin/sort ahead of each timed raster call
+        # (same inputs, so the same values land in the same buffers): each
+        # shape is timed in the state a frame leaves the GPU in
+        p2 = gs.preprocess(means, scales, quats, opac, sh, cam)
+        for k in ("means2d", "radii", "depths", "conics", "log_opacities", "rgb"):
+            pre[k].copy_(p2[k])
+        bs(pre["means2d"], pre["radii"], pre["depths"])
+
     for prec in ((args.precision, "fp32") if not args.raster_shape else ()):
         r_t = gs.Rasterizer(W, H)
         tunes[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
                                            pre["conics"], pre["log_opacities"], pre["rgb"], prec,
-                                           reps=5, warmup=2, ncontrib=False)
+                                           reps=15, warmup=3, ncontrib=False, before=frame_prefix)
         log(f"[bench] tuned {prec}: {tunes[prec]['best']}")
         del r_t
     tune_obj = {k: gs.make_raster_tune(v["best"]["batch"], v["best"]["chunk_rows"])

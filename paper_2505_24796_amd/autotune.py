@@ -30,14 +30,19 @@ DEFAULT_SPACE = {"batch": (64, 128, 256), "blocks_per_cu": (2, 3, 4, 5), "xcd_qu
 RASTER_SPACE = {"batch": (64, 128, 256), "chunk_rows": (1, 2)}
 
 
-def time_ms(fn, reps: int = 5, warmup: int = 1) -> list:
+def time_ms(fn, reps: int = 5, warmup: int = 1, before=None) -> list:
     """Per-call times of fn() in ms (HIP events around each call on the
-    current stream)."""
+    current stream).  before(), if given, runs ahead of every call, outside
+    the events."""
     for _ in range(warmup):
+        if before is not None:
+            before()
         fn()
     out = []
     st = torch.cuda.current_stream()
     for _ in range(reps):
+        if before is not None:
+            before()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(st)
         fn()
@@ -83,13 +88,16 @@ def tune_batched(renderer, space: dict | None = None, reps: int = 5, warmup: int
 
 def tune_raster(rasterizer: Rasterizer, ranges, sorted_ids, means2d, conics, log_opacities, rgb,
                 precision="fp16_g2l_split", space: dict | None = None, reps: int = 5,
-                warmup: int = 1, check: bool = True, ncontrib: bool = True) -> dict:
+                warmup: int = 1, check: bool = True, ncontrib: bool = True, before=None) -> dict:
     """Times every launch shape of ``space`` for one-view rasterisation of
     the given lists and installs the fastest as ``rasterizer.tune``.  The
     FP32 kernels stage a fixed 256 splats, so only the chunk height is tried
     for them.  Returns {"best": {batch, chunk_rows, ms_median, ms_min},
     "table": [...]}.  ncontrib as for Rasterizer: tune the launches that
-    write n_contrib, or those that skip it."""
+    write n_contrib, or those that skip it.  before(), if given, runs ahead
+    of every timed call (e.g. the frame's preprocess and bin/sort, which must
+    leave the lists unchanged), so each shape is timed in the state a frame
+    leaves the GPU in."""
     space = dict(RASTER_SPACE, **(space or {}))
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     batches = space["batch"] if prec >= PRECISIONS["fp16_global"] else (128,)
@@ -97,7 +105,8 @@ def tune_raster(rasterizer: Rasterizer, ranges, sorted_ids, means2d, conics, log
     for nb, cr in itertools.product(batches, space["chunk_rows"]):
         t = make_raster_tune(nb, cr)
         ts = time_ms(lambda: rasterizer(ranges, sorted_ids, means2d, conics, log_opacities, rgb,
-                                        precision, tune=t, ncontrib=ncontrib), reps, warmup)
+                                        precision, tune=t, ncontrib=ncontrib), reps, warmup,
+                     before)
         if check:
             snap = (rasterizer.rgb.clone(), rasterizer.T.clone()) + (
                 (rasterizer.n_contrib.clone(),) if ncontrib else ())
