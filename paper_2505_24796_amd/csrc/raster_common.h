@@ -330,10 +330,11 @@ __device__ __forceinline__ bool tile_alive(const SplatRegs &s, float x0, float y
         // The form is convex with its minimum at the mean, outside the box,
         // so its minimum over the box lies on an edge whose half-plane the
         // mean violates: from a boundary point on no such edge, a step
-        // toward the mean stays in the box and lowers the form.  One
-        // vertical and one horizontal edge, each the one on the mean's side,
-        // hold every such edge (an edge the mean does not violate only adds
-        // a value above the minimum).
+        // toward the mean stays in the box and lowers the form.  The mean
+        // violates at most one vertical and one horizontal edge, those on
+        // its side, so those two are evaluated; where the mean lies within
+        // the box's x (or y) span, the edge taken there is not violated and
+        // only adds a value above the minimum.
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             float dx, dy;
