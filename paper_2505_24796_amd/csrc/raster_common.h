@@ -261,6 +261,7 @@ struct SplatRegs {
     float2 mu;
     float s11, s12, s22, lno, r, g, b;
     bool valid;
+    uint32_t id;
 };
 
 // Three consecutive floats read with one 12-byte load (the arrays are only
@@ -271,9 +272,13 @@ struct __attribute__((aligned(4))) Float3 {
 
 // One splat's parameters: four loads (mean, conic, ln o, colour) rather
 // than one per float, so a wave's gather touches each array's lines once.
+// Without RGB the colour is left to load_rgb, so that a caller can fetch it
+// only for the splats its per-tile cull keeps.
+template <bool RGB = true>
 __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bool valid) {
     SplatRegs s;
     s.valid = valid;
+    s.id = id;
     if (valid) {
         s.mu = a.means2d[id];
         const Float3 c = *(const Float3 *)(a.conics + 3 * (size_t)id);
@@ -281,10 +286,14 @@ __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bo
         s.s12 = c.y;
         s.s22 = c.z;
         s.lno = a.lno[id];
-        const Float3 k = *(const Float3 *)(a.rgb + 3 * (size_t)id);
-        s.r = k.x;
-        s.g = k.y;
-        s.b = k.z;
+        if (RGB) {
+            const Float3 k = *(const Float3 *)(a.rgb + 3 * (size_t)id);
+            s.r = k.x;
+            s.g = k.y;
+            s.b = k.z;
+        } else {
+            s.r = s.g = s.b = 0.f;
+        }
     } else {
         s.mu = make_float2(0.f, 0.f);
         s.s11 = s.s12 = s.s22 = 0.f;
@@ -292,6 +301,14 @@ __device__ __forceinline__ SplatRegs gather(const RasterArgs &a, uint32_t id, bo
         s.r = s.g = s.b = 0.f;
     }
     return s;
+}
+
+// The colour of a splat gathered without it (gather<false>).
+__device__ __forceinline__ void load_rgb(const RasterArgs &a, SplatRegs &s) {
+    const Float3 k = *(const Float3 *)(a.rgb + 3 * (size_t)s.id);
+    s.r = k.x;
+    s.g = k.y;
+    s.b = k.z;
 }
 
 template <int VAR, int NB = BATCH>

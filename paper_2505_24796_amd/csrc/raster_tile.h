@@ -69,11 +69,12 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
     // threads beyond NB take no splat
     const bool gatherer = NB == 256 || (int)threadIdx.x < NB;
 
-    // software pipeline: data of batch b+1 and the id of batch b+2 are in
-    // flight while batch b is blended
+    // software pipeline: the geometry (mean, conic, ln o) of batch b+1 and
+    // the id of batch b+2 are in flight while batch b is blended; a splat's
+    // colour is fetched only once the per-tile cull has kept it
     uint32_t k0 = start + threadIdx.x;
     uint32_t id_cur = gatherer && k0 < end ? a.ids[k0] : 0u;
-    SplatRegs cur = gather(a, id_cur, gatherer && k0 < end);
+    SplatRegs cur = gather<false>(a, id_cur, gatherer && k0 < end);
     uint32_t k1 = k0 + NB;
     uint32_t id_next = gatherer && k1 < end ? a.ids[k1] : 0u;
 
@@ -82,6 +83,9 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
         // (counting mode keeps every splat so culled fragments are counted
         // per pixel in list order)
         const bool keep = COUNT || !CULL ? cur.valid : tile_alive(cur, bx0, by0);
+        // the colours of the kept splats only (most listed splats are culled
+        // here); the loads are in flight across the barrier below
+        if (keep) load_rgb(a, cur);
         const uint64_t kmask = __ballot(keep);
         const bool wave_done = __ballot(thr != __builtin_inff()) == 0ull;
         if (lane == 0) {
@@ -103,7 +107,7 @@ __device__ __forceinline__ void raster_tile_mfma(const RasterArgs &a, int tile, 
                                  b * NB + threadIdx.x);
         {
             uint32_t kn = start + (b + 1) * NB + threadIdx.x;
-            cur = gather(a, id_next, gatherer && kn < end);
+            cur = gather<false>(a, id_next, gatherer && kn < end);
             uint32_t kn2 = kn + NB;
             id_next = gatherer && kn2 < end ? a.ids[kn2] : 0u;
         }
