@@ -55,18 +55,18 @@ RASTER_SOURCES = ["paper_2505_24796_amd/csrc/raster.hip", "paper_2505_24796_amd/
                   "paper_2505_24796_amd/csrc/raster_common.h", "paper_2505_24796_amd/csrc/common.h"]
 
 
-def traffic_path(precision: str, shape: dict) -> str:
-    """Counter record of one raster launch shape at 1080p/1M."""
-    return os.path.join(ROOT, "profiles", f"raster_traffic_fwd_1080p_1M_{precision}"
+def traffic_path(precision: str, shape: dict, workload: str = "fwd_1080p_1M") -> str:
+    """Counter record of one raster launch shape on one workload."""
+    return os.path.join(ROOT, "profiles", f"raster_traffic_{workload}_{precision}"
                                           f"_b{shape['batch']}_c{shape['chunk_rows']}.json")
 
 
-def read_traffic(precision: str, shape: dict):
-    """HBM traffic of the raster kernel measured by rocprofv3 counters at the
-    launch shape the autotuner picked (one record per shape under
-    profiles/), only if the kernel source is unchanged since the counters
-    were taken."""
-    p = traffic_path(precision, shape)
+def read_traffic(precision: str, shape: dict, workload: str = "fwd_1080p_1M"):
+    """HBM traffic of the raster kernel measured by rocprofv3 counters on
+    this workload at the launch shape the autotuner picked (one record per
+    workload and shape under profiles/), only if the kernel source is
+    unchanged since the counters were taken."""
+    p = traffic_path(precision, shape, workload)
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -805,7 +805,8 @@ def main():
     valu_flop = FLOP_TEST * pairs + FLOP_PER_SURVIVOR * survivors
     achieved = valu_flop / raster_s / 1e12
     hb = tunes[args.precision]["best"]
-    counters = read_traffic(args.precision, {"batch": hb["batch"], "chunk_rows": hb["chunk_rows"]})
+    counters = read_traffic(args.precision, {"batch": hb["batch"], "chunk_rows": hb["chunk_rows"]},
+                            args.workload)
     traffic = counters.get("bytes_per_launch") if counters else None
     log("[bench] peak-rate probes")
     peaks = {"exp_per_s": gs.peak_probe("exp", 4000, 2048),

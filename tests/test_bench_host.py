@@ -45,7 +45,7 @@ def test_stale_or_other_shape_records_are_not_reported(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "traffic_path",
-                        lambda p, s: str(prof / f"rec_{p}_b{s['batch']}_c{s['chunk_rows']}.json"))
+                        lambda p, s, w="fwd_1080p_1M": str(prof / f"rec_{p}_b{s['batch']}_c{s['chunk_rows']}.json"))
     # no record for the shape
     assert bench.read_traffic("fp16_g2l_split", shape) is None
     # a record taken on other sources
@@ -59,6 +59,11 @@ def test_stale_or_other_shape_records_are_not_reported(tmp_path, monkeypatch):
     # the matching one
     (prof / "rec_fp16_g2l_split_b128_c2.json").write_text(json.dumps(rec))
     assert bench.read_traffic("fp16_g2l_split", shape)["bytes_per_launch"] == rec["bytes_per_launch"]
+
+
+def test_other_workloads_do_not_borrow_the_1080p_records():
+    shape = {"batch": 128, "chunk_rows": 2}
+    assert bench.read_traffic("fp16_g2l_split", shape, "fwd_4k_6M") is None
 
 
 def test_more_than_one_gpu_is_refused():
