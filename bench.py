@@ -203,6 +203,21 @@ def train_step(args):
                       "opacity logits + N(0, 0.5), SH + N(0, 0.05)"}
 
 
+def frame_prefix_fn(gs, scene_dev, cam, pre, bs):
+    """A callable that runs a frame's preprocess and bin/sort (the same
+    inputs, so the same values land in the buffers `pre` and `bs` hold):
+    passed to the raster autotuner so that each launch shape is timed in the
+    state a frame leaves the GPU in."""
+    means, scales, quats, opac, sh = scene_dev
+
+    def prefix():
+        p2 = gs.preprocess(means, scales, quats, opac, sh, cam)
+        for k in ("means2d", "radii", "depths", "conics", "log_opacities", "rgb"):
+            pre[k].copy_(p2[k])
+        bs(pre["means2d"], pre["radii"], pre["depths"])
+    return prefix
+
+
 def large_scene(args, poses=range(10), steps=50, warmup=5):
     """6M Gaussians at 3840x2160, the 10 orbit poses: per pose and precision
     (FP32 path, FP16 and BF16 hi/lo split) the frame time, the raster time,
@@ -244,15 +259,7 @@ def large_scene(args, poses=range(10), steps=50, warmup=5):
             # launch shapes tuned on the first pose, kept for the others
             from paper_2505_24796_amd import autotune
             tuned = {}
-
-            def frame_prefix():
-                # the frame's preprocess and bin/sort ahead of each timed
-                # raster call (the same values into the same buffers)
-                p2 = gs.preprocess(means, scales, quats, opac, sh, cam)
-                for k in ("means2d", "radii", "depths", "conics", "log_opacities", "rgb"):
-                    pre[k].copy_(p2[k])
-                bs(pre["means2d"], pre["radii"], pre["depths"])
-
+            frame_prefix = frame_prefix_fn(gs, (means, scales, quats, opac, sh), cam, pre, bs)
             for prec in ("fp32", "fp16_g2l_split", "bf16_g2l_split"):
                 r_t = gs.Rasterizer(W, H)
                 tuned[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
@@ -620,15 +627,7 @@ def main():
         nb_, cr_ = (int(x) for x in args.raster_shape.split(","))
         tunes[args.precision] = {"best": {"batch": nb_, "chunk_rows": cr_}, "table": [],
                                  "given": True}
-    def frame_prefix():
-        # the frame's preprocess and bin/sort ahead of each timed raster call
-        # (same inputs, so the same values land in the same buffers): each
-        # shape is timed in the state a frame leaves the GPU in
-        p2 = gs.preprocess(means, scales, quats, opac, sh, cam)
-        for k in ("means2d", "radii", "depths", "conics", "log_opacities", "rgb"):
-            pre[k].copy_(p2[k])
-        bs(pre["means2d"], pre["radii"], pre["depths"])
-
+    frame_prefix = frame_prefix_fn(gs, (means, scales, quats, opac, sh), cam, pre, bs)
     for prec in ((args.precision, "fp32") if not args.raster_shape else ()):
         r_t = gs.Rasterizer(W, H)
         tunes[prec] = autotune.tune_raster(r_t, bs.ranges, bs.sorted_ids, pre["means2d"],
